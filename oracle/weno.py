@@ -12,7 +12,14 @@ Follows Section 2.2 step by step:
   (eqs. recpolydef.x, rec.x), solved with the inverse of the reference-element
   matrix, which depends only on the basis;
 * oscillation indicator sigma_s = Sigma_pm w_p w_m with
-  Sigma_pm = sum_{alpha=1..M} int_0^1 psi_p^(alpha) psi_m^(alpha) (eq. sigmas);
+  Sigma_pm = sum_{alpha=1..M} int_0^1 psi_p^(alpha) psi_m^(alpha) (eq. sigmas),
+  i.e. sigma_s = sum_alpha int_0^1 (d^alpha w^s / dxi^alpha)^2; it is evaluated
+  in that form, the squared derivative values at the Gauss nodes summed with
+  the Gauss weights (exact: the integrand has degree 2(M - alpha) <= 2M + 1).
+  The same number as the quadratic form with the assembled matrix, without
+  its cancellation: Sigma has entries up to ~1e4 at M = 3 and annihilates
+  constants, so w^T Sigma w loses digits that the weights' exponent r = 8
+  then magnifies;
 * nonlinear weights omega~_s = lambda_s / (sigma_s + eps)^r, normalised, with
   lambda = 1 for one-sided and 1e5 for central stencils, eps = 1e-14, r = 8
   (eq. omegas and the constants stated after it);
@@ -81,6 +88,23 @@ def oscillation_matrix(M: int) -> np.ndarray:
 
 
 @lru_cache(maxsize=None)
+def derivative_values(M: int) -> list:
+    """[alpha-1][k, p] = d^alpha psi_p / dxi^alpha at Gauss node k, alpha = 1..M."""
+    b = basis(M)
+    return [np.array([[p.deriv(alpha)(x) for p in b.psi] for x in b.nodes])
+            for alpha in range(1, M + 1)]
+
+
+def oscillation_indicator(ws: np.ndarray, M: int) -> np.ndarray:
+    """sigma = sum_alpha int_0^1 (d^alpha w / dxi^alpha)^2 for nodal w[..., n]."""
+    b = basis(M)
+    sigma = np.zeros(ws.shape[:-1])
+    for D in derivative_values(M):
+        sigma = sigma + ((ws @ D.T) ** 2) @ b.weights
+    return sigma
+
+
+@lru_cache(maxsize=None)
 def weno_constants(M: int):
     """Per-stencil inverse matrices, stencil windows, lambdas and Sigma."""
     sts = stencils(M)
@@ -104,7 +128,7 @@ def weno_1d(values: np.ndarray, M: int) -> np.ndarray:
     omegas = []
     for s, (a, b) in enumerate(windows):
         ws = values[..., a:b] @ inv[s].T                  # w^s_p, eq. rec.x
-        sigma = np.einsum('...p,pm,...m->...', ws, Sigma, ws)   # eq. sigmas
+        sigma = oscillation_indicator(ws, M)              # eq. sigmas
         omegas.append(lambdas[s] / (sigma + EPSILON) ** R_EXPONENT)
         polys.append(ws)
     total = sum(omegas)

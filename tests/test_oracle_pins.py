@@ -124,6 +124,19 @@ def test_oscillation_matrix_closed_forms():
 
 
 @pytest.mark.parametrize("M", range(0, 5))
+def test_oscillation_indicator_equals_quadratic_form(M):
+    """The evaluated sigma is the quadratic form of eq. sigmas."""
+    from oracle.weno import oscillation_indicator
+    rng = np.random.default_rng(90 + M)
+    w = rng.uniform(-1, 1, size=(50, M + 1))
+    S = oscillation_matrix(M)
+    quad = np.einsum('cp,pm,cm->c', w, S, w)
+    scale = max(1.0, np.abs(S).max()) * (M + 1) ** 2
+    np.testing.assert_allclose(oscillation_indicator(w, M), quad, rtol=0,
+                               atol=1e-14 * scale)
+
+
+@pytest.mark.parametrize("M", range(0, 5))
 def test_weno_constant_data_gives_linear_weights(M):
     vals = np.full((3, 2 * M + 1), 2.75)
     np.testing.assert_allclose(weno_1d(vals, M), 2.75, atol=1e-14)
