@@ -1,0 +1,211 @@
+"""Throughput benchmark of the ADER-WENO hot path on one MI355X.
+
+Workload: 2D Euler, Kelvin-Helmholtz shear layer on the periodic unit square,
+uniform 512 x 512 mesh, order 4 (M = 3), Rusanov flux, CFL 0.9 (seeded
+synthetic initial data, paper_1212_3585_amd.workloads).  A step is one pass of
+the whole hot path: CFL time step (device reduction), WENO reconstruction,
+space-time predictor, face fluxes and update.  The state stays resident in
+HBM; nothing crosses PCIe inside the timed region.
+
+Prints ONE JSON line:
+  value           fp64 path, cell-updates/s (active cells x steps / s)
+  mixed           the fp32-predictor form on the same GPU: rate, speedup,
+                  relative L1 against the fp64 oracle
+  roofline        dominant kernel (the predictor): algorithmic flops per
+                  launch / its average duration from HIP events recorded on
+                  the launch stream, against the fp64 vector peak
+  cpu_baseline    the CPU oracle timed on a bounded sample of the workload
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N = 512
+M = 3
+FP64_PEAK_TFLOPS = 78.6     # MI355X fp64 vector (256 CU x 2.4 GHz x 128 flop/clk)
+FP32_PEAK_TFLOPS = 157.3    # MI355X fp32 vector (packed)
+HBM_PEAK_GBS = 8000.0
+
+
+def predictor_flops_per_cell_iteration(dim, M, nv, euler=True):
+    """Algorithmic flops of one Picard iteration of one cell.
+
+    per space-time node: physical fluxes (Euler: d^2 + 5 d + 3 flops, a
+    division counted as one), scaling by dt/dx (d nv); per node and variable:
+    the d spatial derivative products (2 d n), the time product (2 n) and the
+    subtraction from w_hat (1).
+    """
+    n = M + 1
+    nst = n ** (dim + 1)
+    cflux = dim * dim + 5 * dim + 3 if euler else dim
+    return nst * (cflux + dim * nv + nv * (2 * dim * n + 2 * n + 1))
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_form(ader, wl, torch, precision, tol, steps, warmup, u0):
+    prob = ader.Problem(dim=2, M=M, system=ader.SYS_EULER, gamma=1.4, n=(N, N, 1),
+                        lo=(0, 0, 0), hi=(1, 1, 1), bc=(0, 0, 0), cfl=0.9,
+                        precision=precision, picard_tol=tol, picard_max=64)
+    s = ader.Solver(prob)
+    a = u0.clone()
+    b = torch.empty_like(a)
+    for _ in range(warmup):
+        s.compute_dt(a)
+        s.step(a, b)
+        a, b = b, a
+    torch.cuda.synchronize()
+    s.clear_status()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        s.compute_dt(a)
+        s.step(a, b)
+        a, b = b, a
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    flags, iters = s.read_status()
+    # second pass with per-stage HIP events (kernel durations)
+    s.clear_status()
+    s.profile_begin()
+    for _ in range(steps):
+        s.compute_dt(a)
+        s.step(a, b)
+        a, b = b, a
+    stages = s.profile_end()
+    flags2, iters2 = s.read_status()
+    return {"ms": ms, "wall_s": wall, "flags": flags | flags2, "iters": iters2,
+            "stages": stages, "solver": s}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-rows", type=int, default=64,
+                    help="mesh rows of the CPU-oracle sample (512 cells each)")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU; --gpus must be 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1212_3585_amd import ader, workloads as wl
+    ader.require_gpu()
+
+    log("bench: building initial data (KH 512^2)")
+    U0 = wl.kelvin_helmholtz(N)
+    u0 = torch.tensor(wl.to_soa(U0), dtype=torch.float64, device="cuda")
+    ncells = N * N
+
+    log("bench: fp64 timed run")
+    r64 = time_form(ader, wl, torch, ader.PREC_FP64, 1e-14, args.steps, args.warmup, u0)
+    log("bench: fp32-predictor timed run")
+    r32 = time_form(ader, wl, torch, ader.PREC_FP32_PREDICTOR, 1e-6, args.steps,
+                    args.warmup, u0)
+    rate64 = ncells * args.steps / (r64["ms"] * 1e-3)
+    rate32 = ncells * args.steps / (r32["ms"] * 1e-3)
+
+    # roofline of the dominant kernel (predictor) of the fp64 path
+    pms, plaunch = r64["stages"]["predict"]
+    flops_iter = predictor_flops_per_cell_iteration(2, M, 4)
+    iters_per_launch = r64["iters"] / plaunch
+    flops_launch = iters_per_launch * flops_iter
+    avg_s = pms / plaunch * 1e-3
+    achieved = flops_launch / avg_s / 1e12
+    p32ms, p32l = r32["stages"]["predict"]
+    ach32 = (r32["iters"] / p32l) * flops_iter / (p32ms / p32l * 1e-3) / 1e12
+
+    # one step of each form from the initial data, sampled against the oracle
+    sample_rows = max(1, args.cpu_rows)
+    cells = np.array([[i, j] for j in range(sample_rows) for i in range(N)])
+    outs = {}
+    for name, r in (("fp64", r64), ("fp32", r32)):
+        s = r["solver"]
+        b = torch.empty_like(u0)
+        s.compute_dt(u0)
+        s.step(u0, b)
+        outs[name] = wl.from_soa(b.cpu().numpy(), (N, N))[:, cells[:, 0], cells[:, 1]]
+
+    cpu = None
+    l1 = {"fp64": None, "fp32": None}
+    if not args.no_cpu:
+        import oracle
+        from threadpoolctl import threadpool_limits
+        prob = oracle.Problem(2, M, oracle.Euler(2), (N, N), (0.0, 0.0), (1.0, 1.0),
+                              ["periodic", "periodic"])
+        dt = oracle.cfl_dt(prob, U0)
+        log(f"bench: CPU oracle on {len(cells)} cells (rows 0..{sample_rows - 1})")
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            ref, _ = oracle.step_cells(prob, U0, dt, cells)
+            el = time.perf_counter() - t0
+        cpu = {"value": len(cells) / el, "unit": "cell-updates/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"one step of rows 0..{sample_rows - 1} ({len(cells)} cells) of the "
+                         f"512x512 M=3 KH workload, numpy fp64 single-threaded, "
+                         f"{el:.1f} s"}
+        # relative L1 pooled over the conserved variables
+        for k in ("fp64", "fp32"):
+            l1[k] = float(np.abs(outs[k] - ref).sum() / np.abs(ref).sum())
+
+    line = {
+        "metric": "cell-updates/s (FP32-predictor vs FP64) at stated L1 err; "
+                  "p50/p99 solve latency",
+        "value": rate64,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2D Euler Kelvin-Helmholtz, uniform 512x512, ADER-WENO "
+                               "order 4 (M=3), Rusanov, CFL 0.9, periodic, seed 1",
+                   "cells": ncells, "M": M, "parallelism": "single GPU"},
+        "l1_vs_oracle_fp64": l1["fp64"],
+        "status_flags": r64["flags"],
+        "picard_iterations_per_cell": r64["iters"] / plaunch / ncells,
+        "stage_ms_per_step": {k: v[0] / max(v[1], 1) * (v[1] / args.steps)
+                              for k, v in r64["stages"].items()},
+        "mixed": {"value": rate32, "unit": "cell-updates/s", "dtype": "f32 predictor / f64",
+                  "speedup_vs_fp64": rate32 / rate64,
+                  "l1_vs_fp64_oracle": l1["fp32"],
+                  "status_flags": r32["flags"],
+                  "picard_iterations_per_cell": r32["iters"] / p32l / ncells,
+                  "predictor_tflops": ach32,
+                  "predictor_frac_of_fp32_peak": ach32 / FP32_PEAK_TFLOPS},
+        "roofline": {"bound": "alu", "kernel": "k_predict (fp64)",
+                     "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_launch": flops_launch,
+                     "avg_launch_ms": avg_s * 1e3},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,176 @@
+/*
+ * ader.h -- C ABI of the MI355X (gfx950) one-step ADER-WENO hot path.
+ *
+ * The library advances the cell averages of a hyperbolic conservation law
+ *     u_t + f(u)_x + g(u)_y + h(u)_z = 0                 (Section 2.1, S = 0)
+ * on a uniform Cartesian mesh by one step of the one-step ADER-WENO finite
+ * volume scheme (Section 2): dimension-by-dimension polynomial WENO
+ * reconstruction (Section 2.2), element-local space-time DG predictor solved
+ * by Picard iteration (Section 2.3, eq. stdg.final), Rusanov fluxes at the
+ * space-time Gauss-Legendre points of every face (eqs. flux:F-H, rusanov) and
+ * the conservative update (eq. finite_vol).
+ *
+ * Conventions shared by every call:
+ *   - Every function returns ader_status: ADER_OK (0) or a negative code.
+ *     Argument errors are detected on the host and returned synchronously;
+ *     nothing is launched in that case.  ader_last_error() returns a message
+ *     for the most recent failure of the calling thread.
+ *   - Numerical faults found on the device (NaN, non-positive density or
+ *     pressure, predictor iteration not converged) set bits in a status word
+ *     inside the workspace; ader_read_status() fetches it.
+ *   - State arrays are structure-of-arrays in device memory, fp64:
+ *         u[v * ld + cell],  cell = i + nx * (j + ny * k)   (x fastest),
+ *     v = 0..nvar-1, ld >= number of cells.  The caller owns all device
+ *     buffers (inputs, outputs, workspace); the plan owns only host memory.
+ *   - 'stream' is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every compute call is asynchronous on that stream and never
+ *     synchronises, allocates or frees device memory.
+ *   - The time step lives in device memory (dt_dev, one double) so that a
+ *     sequence of steps needs no host round trip.
+ *   - Calls that share one workspace must be ordered (same stream or
+ *     synchronised); two concurrent calls on one workspace race.
+ */
+#ifndef ADER_H
+#define ADER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ADER_OK = 0,
+  ADER_EINVAL = -1,        /* invalid argument (null pointer, bad size ...) */
+  ADER_EUNSUPPORTED = -2,  /* valid problem outside what this build supports */
+  ADER_EHIP = -3,          /* a HIP runtime call failed */
+  ADER_EWORKSPACE = -4     /* workspace pointer null or misaligned */
+} ader_status;
+
+/* Balance law: scalar linear advection with constant velocity adv[], or the
+ * Euler equations of an ideal gas (Section 4.1, eq. Euler-system) with
+ * conserved variables (rho, rho v_x, rho v_y, [rho v_z,] E): nvar = dim + 2. */
+typedef enum { ADER_SYS_LINADV = 0, ADER_SYS_EULER = 1 } ader_system;
+
+/* FP64: every stage in double precision.  FP32_PREDICTOR: the Picard
+ * iteration of the predictor and its face traces in single precision with
+ * single-precision accumulation; reconstruction (smoothness indicators and
+ * nonlinear weights), Rusanov flux, flux quadrature and update stay fp64. */
+typedef enum { ADER_PREC_FP64 = 0, ADER_PREC_FP32_PREDICTOR = 1 } ader_precision;
+
+/* Periodic, or transmissive: zero-gradient ghost averages for the WENO
+ * stencils and, on a boundary face, outer predictor trace = inner trace. */
+typedef enum { ADER_BC_PERIODIC = 0, ADER_BC_TRANSMISSIVE = 1 } ader_bc;
+
+typedef struct {
+  int dim;            /* 2 or 3 */
+  int M;              /* polynomial degree 0..3 (order of accuracy M+1) */
+  int system;         /* ader_system */
+  double gamma;       /* ratio of specific heats (Euler) */
+  double adv[3];      /* advection velocity (linear advection) */
+  int n[3];           /* cells per axis (n[2] ignored for dim 2); each >= 1 */
+  double lo[3];       /* domain lower corner */
+  double hi[3];       /* domain upper corner */
+  int bc[3];          /* ader_bc per axis (both sides of an axis alike) */
+  double cfl;         /* Courant number of the time-step rule, in (0, 1] */
+  int precision;      /* ader_precision */
+  double picard_tol;  /* relative stop tolerance of the predictor iteration */
+  int picard_max;     /* iteration cap (1..1000); reaching it sets a flag */
+} ader_problem;
+
+typedef struct ader_plan_s* ader_plan;
+
+/* Device status bits (ader_read_status). */
+#define ADER_FLAG_NAN 1u          /* a NaN appeared in the new averages or dt */
+#define ADER_FLAG_NONPHYSICAL 2u  /* rho <= 0 or p <= 0 in the new averages */
+#define ADER_FLAG_NOCONV 4u       /* predictor reached picard_max */
+
+/* Validate the problem and build the reference-element constants (Gauss-
+ * Legendre nodes and weights, Lagrange basis values and derivatives,
+ * per-stencil inverse reconstruction matrices, oscillation matrix, and the
+ * time matrix of K^1 with its inverse; Sections 2.2 and 2.3) on the host.
+ * *out receives a plan owned by the caller; release with ader_plan_destroy.
+ * Errors: EINVAL (null pointers, non-finite or out-of-range fields),
+ * EUNSUPPORTED (dim/M/system outside this build). */
+ader_status ader_plan_create(const ader_problem* prob, ader_plan* out);
+
+/* Release a plan (NULL is accepted). */
+ader_status ader_plan_destroy(ader_plan plan);
+
+/* Number of conserved variables of the plan's system (1, 4 or 5). */
+ader_status ader_plan_nvar(ader_plan plan, int* nvar);
+
+/* Bytes of device workspace every compute call of this plan needs.  The
+ * workspace is caller-allocated device memory, 256-byte aligned, reusable
+ * across calls of the same plan; its status word survives between calls. */
+ader_status ader_workspace_bytes(ader_plan plan, size_t* bytes);
+
+/* Zero the workspace's status word and iteration counters (a fill kernel on
+ * 'stream', no hipMemset). */
+ader_status ader_clear_status(ader_plan plan, void* ws, void* stream);
+
+/* Time step from the CFL rule on the averages u at time t:
+ *   dt = cfl / max_cells sum_k (|v_k| + c) / dx_k     (|a_k| for advection),
+ * then dt = min(dt, t_end - t).  Written to dt_dev (one device double).
+ * The paper states no formula for dt; this is the rule the library uses. */
+ader_status ader_compute_dt(ader_plan plan, const double* u, int64_t ld,
+                            double t, double t_end, double* dt_dev, void* ws,
+                            void* stream);
+
+/* One step of the scheme on every cell: u_out = u_in advanced by *dt_dev
+ * (eq. finite_vol with the fluxes of eqs. flux:F-H).  u_in and u_out are
+ * distinct nvar x ld device arrays (EINVAL if they overlap). */
+ader_status ader_step(ader_plan plan, const double* u_in, double* u_out,
+                      int64_t ld, const double* dt_dev, void* ws, void* stream);
+
+/* Stage entry points (for stage-by-stage checks):
+ *
+ * ader_debug_reconstruct: WENO polynomial of every cell (Section 2.2),
+ *   w_h[(cell * nvar + v) * n^d + a], a = p_x + n p_y (+ n^2 p_z), n = M+1:
+ *   nodal values at the tensor Gauss-Legendre nodes of the reference cell.
+ *
+ * ader_debug_predict: space-time predictor (Section 2.3) of 'ncells'
+ *   independent cells from their nodal reconstructions w_h (layout above),
+ *   q_h[(cell * nvar + v) * n^(d+1) + a + n^d s] (s = time node), with
+ *   dt/dx_k of the plan's mesh and *dt_dev.  ncells is free (not tied to the
+ *   mesh); the workspace must still be the plan's. */
+ader_status ader_debug_reconstruct(ader_plan plan, const double* u, int64_t ld,
+                                   double* w_h, void* ws, void* stream);
+ader_status ader_debug_predict(ader_plan plan, const double* w_h,
+                               int64_t ncells, double* q_h,
+                               const double* dt_dev, void* ws, void* stream);
+
+/* Synchronise 'stream' and read the status bits (ADER_FLAG_*) and the sum of
+ * predictor iterations over all cells since the last clear. */
+ader_status ader_read_status(ader_plan plan, const void* ws, uint32_t* flags,
+                             uint64_t* picard_iterations, void* stream);
+
+/* Reference-element constants as the device path uses them, for checks:
+ * nodes[n], weights[n], dmat[n*n] (dmat[a*n+b] = psi_b'(node_a)),
+ * time_inv_w[n*n] = (time matrix of K^1)^-1 diag(weights). */
+ader_status ader_debug_constants(ader_plan plan, double* nodes, double* weights,
+                                 double* dmat, double* time_inv_w);
+
+/* Stage timing with HIP events recorded on the launch stream.
+ * ader_profile_begin: from now on every compute call of this plan brackets
+ *   each stage (ADER_STAGE_*) with a pair of events on its stream.
+ * ader_profile_end: synchronise those events, write the summed milliseconds
+ *   and launch counts per stage (arrays of ADER_NSTAGES), stop recording.
+ * Host-side events only; device memory is untouched. */
+#define ADER_STAGE_DT 0
+#define ADER_STAGE_WENO 1
+#define ADER_STAGE_PREDICT 2
+#define ADER_STAGE_FLUX 3
+#define ADER_STAGE_UPDATE 4
+#define ADER_NSTAGES 5
+ader_status ader_profile_begin(ader_plan plan);
+ader_status ader_profile_end(ader_plan plan, double* stage_ms, int64_t* stage_launches);
+
+const char* ader_status_string(ader_status status);
+const char* ader_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADER_H */

@@ -1,0 +1,274 @@
+"""Thin Python binding of the C ABI in include/ader.h (ctypes).
+
+Argument marshalling only: every stage of the step runs in the HIP kernels of
+libaderweno.so.  PyTorch provides device memory and the current stream.  The
+module fails loudly when the library has not been built; there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libaderweno.so")
+
+OK, EINVAL, EUNSUPPORTED, EHIP, EWORKSPACE = 0, -1, -2, -3, -4
+SYS_LINADV, SYS_EULER = 0, 1
+PREC_FP64, PREC_FP32_PREDICTOR = 0, 1
+BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
+FLAG_NAN, FLAG_NONPHYSICAL, FLAG_NOCONV = 1, 2, 4
+
+# every symbol declared in include/ader.h
+EXPORTS = [
+    "ader_plan_create", "ader_plan_destroy", "ader_plan_nvar",
+    "ader_workspace_bytes", "ader_clear_status", "ader_compute_dt", "ader_step",
+    "ader_debug_reconstruct", "ader_debug_predict", "ader_read_status",
+    "ader_debug_constants", "ader_profile_begin", "ader_profile_end",
+    "ader_status_string", "ader_last_error",
+]
+STAGES = ["dt", "weno", "predict", "flux", "update"]
+
+
+class AderError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: status {status}: {message}")
+        self.status = status
+
+
+class CProblem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("M", ctypes.c_int), ("system", ctypes.c_int),
+        ("gamma", ctypes.c_double), ("adv", ctypes.c_double * 3),
+        ("n", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
+        ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int * 3),
+        ("cfl", ctypes.c_double), ("precision", ctypes.c_int),
+        ("picard_tol", ctypes.c_double), ("picard_max", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libaderweno.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} not found: build it first "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i64, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "ader_plan_create": [ctypes.POINTER(CProblem), ctypes.POINTER(vp)],
+        "ader_plan_destroy": [vp],
+        "ader_plan_nvar": [vp, ctypes.POINTER(ctypes.c_int)],
+        "ader_workspace_bytes": [vp, ctypes.POINTER(ctypes.c_size_t)],
+        "ader_clear_status": [vp, vp, vp],
+        "ader_compute_dt": [vp, vp, i64, dbl, dbl, vp, vp, vp],
+        "ader_step": [vp, vp, vp, i64, vp, vp, vp],
+        "ader_debug_reconstruct": [vp, vp, i64, vp, vp, vp],
+        "ader_debug_predict": [vp, vp, i64, vp, vp, vp, vp],
+        "ader_read_status": [vp, vp, ctypes.POINTER(ctypes.c_uint32),
+                             ctypes.POINTER(ctypes.c_uint64), vp],
+        "ader_debug_constants": [vp, vp, vp, vp, vp],
+        "ader_profile_begin": [vp],
+        "ader_profile_end": [vp, vp, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.ader_status_string.argtypes = [ctypes.c_int]
+    lib.ader_status_string.restype = ctypes.c_char_p
+    lib.ader_last_error.argtypes = []
+    lib.ader_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        msg = load_library().ader_last_error().decode()
+        raise AderError(status, where, msg)
+
+
+def require_gpu():
+    """Raise unless a HIP device and the built library are both present."""
+    import torch
+    load_library()
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device visible")
+
+
+@dataclass
+class Problem:
+    dim: int = 2
+    M: int = 2
+    system: int = SYS_EULER
+    gamma: float = 1.4
+    adv: tuple = (1.0, 1.0, 1.0)
+    n: tuple = (20, 20, 1)
+    lo: tuple = (0.0, 0.0, 0.0)
+    hi: tuple = (1.0, 1.0, 1.0)
+    bc: tuple = (BC_PERIODIC, BC_PERIODIC, BC_PERIODIC)
+    cfl: float = 0.9
+    precision: int = PREC_FP64
+    picard_tol: float = 1e-14
+    picard_max: int = 64
+
+    def to_c(self) -> CProblem:
+        c = CProblem()
+        c.dim, c.M, c.system = self.dim, self.M, self.system
+        c.gamma = self.gamma
+        c.adv[:] = list(self.adv)[:3] + [0.0] * (3 - len(self.adv))
+        c.n[:] = list(self.n)[:3] + [1] * (3 - len(self.n))
+        c.lo[:] = list(self.lo)[:3] + [0.0] * (3 - len(self.lo))
+        c.hi[:] = list(self.hi)[:3] + [1.0] * (3 - len(self.hi))
+        c.bc[:] = list(self.bc)[:3] + [0] * (3 - len(self.bc))
+        c.cfl = self.cfl
+        c.precision = self.precision
+        c.picard_tol = self.picard_tol
+        c.picard_max = self.picard_max
+        return c
+
+    @property
+    def ncells(self) -> int:
+        return int(np.prod(list(self.n)[:self.dim]))
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Solver:
+    """A plan plus its device workspace.  Tensors are fp64 on the HIP device."""
+
+    def __init__(self, problem: Problem, device="cuda"):
+        import torch
+        self.lib = load_library()
+        self.problem = problem
+        self._plan = ctypes.c_void_p()
+        cp = problem.to_c()
+        _check(self.lib.ader_plan_create(ctypes.byref(cp), ctypes.byref(self._plan)),
+               "ader_plan_create")
+        nv = ctypes.c_int()
+        _check(self.lib.ader_plan_nvar(self._plan, ctypes.byref(nv)), "ader_plan_nvar")
+        self.nvar = nv.value
+        nb = ctypes.c_size_t()
+        _check(self.lib.ader_workspace_bytes(self._plan, ctypes.byref(nb)),
+               "ader_workspace_bytes")
+        self.workspace_bytes = nb.value
+        self.device = torch.device(device)
+        # torch's caching allocator returns 256-byte aligned blocks
+        self.ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=self.device)
+        self.dt = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self.clear_status()
+
+    def __del__(self):
+        try:
+            if self._plan:
+                self.lib.ader_plan_destroy(self._plan)
+                self._plan = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    @property
+    def ncells(self) -> int:
+        return self.problem.ncells
+
+    def empty_state(self, ld=None):
+        import torch
+        ld = self.ncells if ld is None else ld
+        return torch.zeros((self.nvar, ld), dtype=torch.float64, device=self.device)
+
+    def clear_status(self, stream=None):
+        _check(self.lib.ader_clear_status(self._plan, _ptr(self.ws), _stream(stream)),
+               "ader_clear_status")
+
+    def compute_dt(self, u, t=0.0, t_end=float("inf"), dt_out=None, stream=None):
+        dt_out = self.dt if dt_out is None else dt_out
+        _check(self.lib.ader_compute_dt(self._plan, _ptr(u), u.shape[1], t, t_end,
+                                        _ptr(dt_out), _ptr(self.ws), _stream(stream)),
+               "ader_compute_dt")
+        return dt_out
+
+    def step(self, u_in, u_out, dt=None, stream=None):
+        dt = self.dt if dt is None else dt
+        _check(self.lib.ader_step(self._plan, _ptr(u_in), _ptr(u_out), u_in.shape[1],
+                                  _ptr(dt), _ptr(self.ws), _stream(stream)), "ader_step")
+        return u_out
+
+    def reconstruct(self, u, stream=None):
+        import torch
+        n = self.problem.M + 1
+        wh = torch.empty(self.ncells * self.nvar * n ** self.problem.dim,
+                         dtype=torch.float64, device=self.device)
+        _check(self.lib.ader_debug_reconstruct(self._plan, _ptr(u), u.shape[1], _ptr(wh),
+                                               _ptr(self.ws), _stream(stream)),
+               "ader_debug_reconstruct")
+        return wh
+
+    def predict(self, wh, ncells, dt=None, stream=None):
+        import torch
+        n = self.problem.M + 1
+        dt = self.dt if dt is None else dt
+        qh = torch.empty(max(ncells, 1) * self.nvar * n ** (self.problem.dim + 1),
+                         dtype=torch.float64, device=self.device)
+        _check(self.lib.ader_debug_predict(self._plan, _ptr(wh), ncells, _ptr(qh), _ptr(dt),
+                                           _ptr(self.ws), _stream(stream)),
+               "ader_debug_predict")
+        return qh
+
+    def read_status(self, stream=None):
+        flags = ctypes.c_uint32()
+        iters = ctypes.c_uint64()
+        _check(self.lib.ader_read_status(self._plan, _ptr(self.ws), ctypes.byref(flags),
+                                         ctypes.byref(iters), _stream(stream)),
+               "ader_read_status")
+        return flags.value, iters.value
+
+    def constants(self):
+        n = self.problem.M + 1
+        arrs = [np.zeros(n), np.zeros(n), np.zeros(n * n), np.zeros(n * n)]
+        _check(self.lib.ader_debug_constants(
+            self._plan, *[a.ctypes.data_as(ctypes.c_void_p) for a in arrs]),
+            "ader_debug_constants")
+        return {"nodes": arrs[0], "weights": arrs[1], "dmat": arrs[2].reshape(n, n),
+                "time_inv_w": arrs[3].reshape(n, n)}
+
+    def profile_begin(self):
+        _check(self.lib.ader_profile_begin(self._plan), "ader_profile_begin")
+
+    def profile_end(self):
+        """{stage: (total milliseconds, launches)} since profile_begin."""
+        ms = np.zeros(len(STAGES))
+        cnt = np.zeros(len(STAGES), dtype=np.int64)
+        _check(self.lib.ader_profile_end(self._plan, ms.ctypes.data_as(ctypes.c_void_p),
+                                         cnt.ctypes.data_as(ctypes.c_void_p)),
+               "ader_profile_end")
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(STAGES)}
+
+    def run(self, u, t_end, max_steps=10**9, stream=None):
+        """Advance u to t_end; returns (u, t, steps).  Reads dt back each step."""
+        import torch
+        t = 0.0
+        steps = 0
+        a, b = u.clone(), torch.empty_like(u)
+        while t < t_end and steps < max_steps:
+            self.compute_dt(a, t, t_end, stream=stream)
+            self.step(a, b, stream=stream)
+            dt = float(self.dt.item())
+            t += dt
+            steps += 1
+            a, b = b, a
+        return a, t, steps

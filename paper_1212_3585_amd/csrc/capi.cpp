@@ -1,0 +1,322 @@
+// C ABI of the ADER-WENO hot path: argument validation, plan construction,
+// workspace layout and dispatch to the templated launchers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "plan.hpp"
+
+struct ader_plan_s {
+  ader::PlanData data;
+  const ader::ImplBase* impl = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ader_status fail(ader_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+ader_status hip_status(hipError_t e, const char* where) {
+  if (e == hipSuccess) return ADER_OK;
+  return fail(ADER_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+ader_status check_ws(const ader_plan p, const void* ws) {
+  if (!ws) return fail(ADER_EWORKSPACE, "workspace pointer is null");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+    return fail(ADER_EWORKSPACE, "workspace must be 256-byte aligned");
+  (void)p;
+  return ADER_OK;
+}
+
+ader_status check_state(const ader_plan p, const void* u, int64_t ld) {
+  if (!u) return fail(ADER_EINVAL, "state pointer is null");
+  if (ld < p->data.ncells) return fail(ADER_EINVAL, "ld is smaller than the number of cells");
+  return ADER_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ader_status_string(ader_status s) {
+  switch (s) {
+    case ADER_OK: return "ok";
+    case ADER_EINVAL: return "invalid argument";
+    case ADER_EUNSUPPORTED: return "unsupported problem";
+    case ADER_EHIP: return "HIP runtime error";
+    case ADER_EWORKSPACE: return "bad workspace";
+  }
+  return "unknown status";
+}
+
+const char* ader_last_error(void) { return g_last_error.c_str(); }
+
+ader_status ader_plan_create(const ader_problem* prob, ader_plan* out) {
+  if (!prob || !out) return fail(ADER_EINVAL, "null argument");
+  *out = nullptr;
+  const ader_problem& pr = *prob;
+  if (pr.dim != 2 && pr.dim != 3) return fail(ADER_EUNSUPPORTED, "dim must be 2 or 3");
+  if (pr.M < 0 || pr.M > 3) return fail(ADER_EUNSUPPORTED, "M must be in 0..3");
+  if (pr.system != ADER_SYS_LINADV && pr.system != ADER_SYS_EULER)
+    return fail(ADER_EUNSUPPORTED, "unknown system");
+  if (pr.precision != ADER_PREC_FP64 && pr.precision != ADER_PREC_FP32_PREDICTOR)
+    return fail(ADER_EINVAL, "unknown precision");
+  int64_t ncells = 1;
+  for (int k = 0; k < pr.dim; ++k) {
+    if (pr.n[k] < 1) return fail(ADER_EINVAL, "cells per axis must be >= 1");
+    if (!is_finite(pr.lo[k]) || !is_finite(pr.hi[k]) || !(pr.hi[k] > pr.lo[k]))
+      return fail(ADER_EINVAL, "domain bounds must be finite with hi > lo");
+    if (pr.bc[k] != ADER_BC_PERIODIC && pr.bc[k] != ADER_BC_TRANSMISSIVE)
+      return fail(ADER_EINVAL, "unknown boundary condition");
+    ncells *= pr.n[k];
+  }
+  if (ncells > (int64_t(1) << 28)) return fail(ADER_EUNSUPPORTED, "more than 2^28 cells");
+  if (!is_finite(pr.cfl) || !(pr.cfl > 0.0) || pr.cfl > 1.0)
+    return fail(ADER_EINVAL, "cfl must be in (0, 1]");
+  if (pr.system == ADER_SYS_EULER && (!is_finite(pr.gamma) || !(pr.gamma > 1.0)))
+    return fail(ADER_EINVAL, "gamma must be > 1");
+  if (pr.system == ADER_SYS_LINADV)
+    for (int k = 0; k < 3; ++k)
+      if (!is_finite(pr.adv[k])) return fail(ADER_EINVAL, "advection velocity must be finite");
+  if (!is_finite(pr.picard_tol) || !(pr.picard_tol > 0.0))
+    return fail(ADER_EINVAL, "picard_tol must be > 0");
+  if (pr.picard_max < 1 || pr.picard_max > 1000)
+    return fail(ADER_EINVAL, "picard_max must be in 1..1000");
+
+  ader_plan p = new (std::nothrow) ader_plan_s();
+  if (!p) return fail(ADER_EINVAL, "out of host memory");
+  ader::PlanData& d = p->data;
+  d.prob = pr;
+  if (pr.dim == 2) d.prob.n[2] = 1;
+  d.dim = pr.dim;
+  d.M = pr.M;
+  d.n = pr.M + 1;
+  d.nv = pr.system == ADER_SYS_LINADV ? 1 : pr.dim + 2;
+  d.ns = 1;
+  for (int k = 0; k < pr.dim; ++k) d.ns *= d.n;
+  d.nst = d.ns * d.n;
+  d.ncells = ncells;
+
+  if (!ader::build_ref_constants(pr.M, &d.ref)) {
+    delete p;
+    return fail(ADER_EINVAL, "singular reference matrix");
+  }
+  ader::DevConsts& c = d.dc;
+  std::memset(&c, 0, sizeof(c));
+  const ader::RefConstants& r = d.ref;
+  for (int a = 0; a < d.n; ++a) {
+    c.psi0[a] = (double)r.psi0[a];
+    c.psi1[a] = (double)r.psi1[a];
+    c.w[a] = (double)r.weights[a];
+    c.psi0_f[a] = (float)r.psi0[a];
+    c.psi1_f[a] = (float)r.psi1[a];
+    for (int b = 0; b < d.n; ++b) {
+      c.dmat[a][b] = (double)r.dmat[a][b];
+      c.tinvw[a][b] = (double)r.time_inv_w[a][b];
+      c.dmat_f[a][b] = (float)r.dmat[a][b];
+      c.tinvw_f[a][b] = (float)r.time_inv_w[a][b];
+      c.sigma[a][b] = (double)r.sigma[a][b];
+      for (int al = 0; al < d.M; ++al) c.dnode[al][a][b] = (double)r.dnode[al][a][b];
+    }
+  }
+  for (int s = 0; s < r.nstencils; ++s) {
+    c.lam[s] = (double)r.lambda[s];
+    for (int pp = 0; pp < d.n; ++pp)
+      for (int e = 0; e < d.n; ++e) c.rec_inv[s][pp][e] = (double)r.rec_inv[s][pp][e];
+  }
+
+  ader::MeshParams& mp = d.mp;
+  std::memset(&mp, 0, sizeof(mp));
+  for (int k = 0; k < 3; ++k) {
+    const bool used = k < pr.dim;
+    mp.n[k] = used ? pr.n[k] : 1;
+    mp.bc[k] = used ? pr.bc[k] : 0;
+    mp.dx[k] = used ? (pr.hi[k] - pr.lo[k]) / pr.n[k] : 1.0;
+    mp.adv[k] = pr.system == ADER_SYS_LINADV ? pr.adv[k] : 0.0;
+  }
+  mp.gamma = pr.gamma;
+  mp.tol = pr.picard_tol;
+  mp.maxit = pr.picard_max;
+  mp.ncells = ncells;
+  mp.ld = ncells;
+
+  p->impl = pr.dim == 2 ? ader::make_impl_2d(pr.M, pr.system, pr.precision)
+                        : ader::make_impl_3d(pr.M, pr.system, pr.precision);
+  if (!p->impl) {
+    delete p;
+    return fail(ADER_EUNSUPPORTED, "no kernels for this configuration");
+  }
+
+  // faces along axis k on the mesh extended by one cell along k
+  for (int k = 0; k < pr.dim; ++k) {
+    int64_t nf = 1;
+    for (int m = 0; m < pr.dim; ++m) nf *= mp.n[m] + (m == k ? 1 : 0);
+    d.nfaces[k] = nf;
+  }
+
+  // workspace: header | Wx | Wxy (3D) | w_h | q_h | face fluxes
+  size_t off = 256;
+  const size_t C = (size_t)ncells;
+  d.off_wx = off;
+  off = align256(off + sizeof(double) * d.nv * d.n * C);
+  d.off_wxy = off;
+  if (pr.dim == 3) off = align256(off + sizeof(double) * d.nv * d.n * d.n * C);
+  d.off_wh = off;
+  off = align256(off + sizeof(double) * d.nv * d.ns * C);
+  d.off_qh = off;
+  off = align256(off + p->impl->qh_elem_size() * d.nv * d.nst * C);
+  for (int k = 0; k < pr.dim; ++k) {
+    d.off_f[k] = off;
+    off = align256(off + sizeof(double) * d.nv * (size_t)d.nfaces[k]);
+  }
+  d.ws_bytes = off;
+  *out = p;
+  return ADER_OK;
+}
+
+ader_status ader_plan_destroy(ader_plan plan) {
+  delete plan;
+  return ADER_OK;
+}
+
+ader_status ader_plan_nvar(ader_plan plan, int* nvar) {
+  if (!plan || !nvar) return fail(ADER_EINVAL, "null argument");
+  *nvar = plan->data.nv;
+  return ADER_OK;
+}
+
+ader_status ader_workspace_bytes(ader_plan plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(ADER_EINVAL, "null argument");
+  *bytes = plan->data.ws_bytes;
+  return ADER_OK;
+}
+
+ader_status ader_clear_status(ader_plan plan, void* ws, void* stream) {
+  if (!plan) return fail(ADER_EINVAL, "null plan");
+  if (ader_status s = check_ws(plan, ws)) return s;
+  return hip_status(plan->impl->clear_status((char*)ws, (hipStream_t)stream),
+                    "ader_clear_status");
+}
+
+ader_status ader_compute_dt(ader_plan plan, const double* u, int64_t ld, double t,
+                            double t_end, double* dt_dev, void* ws, void* stream) {
+  if (!plan || !dt_dev) return fail(ADER_EINVAL, "null argument");
+  if (ader_status s = check_state(plan, u, ld)) return s;
+  if (ader_status s = check_ws(plan, ws)) return s;
+  if (!is_finite(t) || std::isnan(t_end) || !(t_end > t))
+    return fail(ADER_EINVAL, "need finite t and t_end > t");
+  return hip_status(plan->impl->compute_dt(plan->data, u, ld, t, t_end, dt_dev, (char*)ws,
+                                           (hipStream_t)stream),
+                    "ader_compute_dt");
+}
+
+ader_status ader_step(ader_plan plan, const double* u_in, double* u_out, int64_t ld,
+                      const double* dt_dev, void* ws, void* stream) {
+  if (!plan || !dt_dev) return fail(ADER_EINVAL, "null argument");
+  if (ader_status s = check_state(plan, u_in, ld)) return s;
+  if (ader_status s = check_state(plan, u_out, ld)) return s;
+  if (ader_status s = check_ws(plan, ws)) return s;
+  const uintptr_t a0 = (uintptr_t)u_in, b0 = (uintptr_t)u_out;
+  const uintptr_t len = sizeof(double) * (uintptr_t)plan->data.nv * (uintptr_t)ld;
+  if (a0 < b0 + len && b0 < a0 + len) return fail(ADER_EINVAL, "u_in and u_out overlap");
+  return hip_status(plan->impl->step(plan->data, u_in, u_out, ld, dt_dev, (char*)ws,
+                                     (hipStream_t)stream),
+                    "ader_step");
+}
+
+ader_status ader_debug_reconstruct(ader_plan plan, const double* u, int64_t ld, double* w_h,
+                                   void* ws, void* stream) {
+  if (!plan || !w_h) return fail(ADER_EINVAL, "null argument");
+  if (ader_status s = check_state(plan, u, ld)) return s;
+  if (ader_status s = check_ws(plan, ws)) return s;
+  return hip_status(plan->impl->reconstruct(plan->data, u, ld, w_h, (char*)ws,
+                                            (hipStream_t)stream),
+                    "ader_debug_reconstruct");
+}
+
+ader_status ader_debug_predict(ader_plan plan, const double* w_h, int64_t ncells, double* q_h,
+                               const double* dt_dev, void* ws, void* stream) {
+  if (!plan || !dt_dev) return fail(ADER_EINVAL, "null argument");
+  if (ncells < 0 || ncells > (int64_t(1) << 28)) return fail(ADER_EINVAL, "bad ncells");
+  if (ncells > 0 && (!w_h || !q_h)) return fail(ADER_EINVAL, "null argument");
+  if (ader_status s = check_ws(plan, ws)) return s;
+  return hip_status(plan->impl->predict_debug(plan->data, w_h, ncells, q_h, dt_dev, (char*)ws,
+                                              (hipStream_t)stream),
+                    "ader_debug_predict");
+}
+
+ader_status ader_read_status(ader_plan plan, const void* ws, uint32_t* flags,
+                             uint64_t* picard_iterations, void* stream) {
+  if (!plan || !flags) return fail(ADER_EINVAL, "null argument");
+  if (ader_status s = check_ws(plan, ws)) return s;
+  ader::WsHeader h;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(&h, ws, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_status(e, "ader_read_status");
+  *flags = h.status;
+  if (picard_iterations) *picard_iterations = h.iters;
+  return ADER_OK;
+}
+
+ader_status ader_debug_constants(ader_plan plan, double* nodes, double* weights, double* dmat,
+                                 double* time_inv_w) {
+  if (!plan || !nodes || !weights || !dmat || !time_inv_w)
+    return fail(ADER_EINVAL, "null argument");
+  const ader::RefConstants& r = plan->data.ref;
+  const int n = r.n;
+  for (int a = 0; a < n; ++a) {
+    nodes[a] = (double)r.nodes[a];
+    weights[a] = (double)r.weights[a];
+    for (int b = 0; b < n; ++b) {
+      dmat[a * n + b] = (double)r.dmat[a][b];
+      time_inv_w[a * n + b] = (double)r.time_inv_w[a][b];
+    }
+  }
+  return ADER_OK;
+}
+
+ader_status ader_profile_begin(ader_plan plan) {
+  if (!plan) return fail(ADER_EINVAL, "null plan");
+  plan->data.prof.on = true;
+  return ADER_OK;
+}
+
+ader_status ader_profile_end(ader_plan plan, double* stage_ms, int64_t* stage_launches) {
+  if (!plan || !stage_ms || !stage_launches) return fail(ADER_EINVAL, "null argument");
+  ader::Profiler& pr = plan->data.prof;
+  for (int i = 0; i < ADER_NSTAGES; ++i) {
+    stage_ms[i] = 0.0;
+    stage_launches[i] = 0;
+  }
+  hipError_t err = hipSuccess;
+  for (auto& r : pr.recs) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess && err == hipSuccess) err = e;
+    if (e == hipSuccess && r.stage >= 0 && r.stage < ADER_NSTAGES) {
+      stage_ms[r.stage] += ms;
+      stage_launches[r.stage] += 1;
+    }
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  pr.recs.clear();
+  pr.on = false;
+  return hip_status(err, "ader_profile_end");
+}
+
+}  // extern "C"

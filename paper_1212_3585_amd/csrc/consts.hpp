@@ -1,0 +1,44 @@
+// Reference-element constants of the one-step ADER-WENO scheme, built on the
+// host in long double at plan creation (Sections 2.2 and 2.3).
+//
+// Route: Gauss-Legendre nodes by Newton iteration on the three-term Legendre
+// recurrence; Lagrange basis polynomials expanded as monomials in the
+// centred variable t = xi - 1/2; every integral taken exactly from
+// antiderivatives of those monomials; small inverses by Gauss-Jordan
+// elimination with partial pivoting.
+#pragma once
+
+#include <cstdint>
+
+namespace ader {
+
+constexpr int kMaxN = 4;  // n = M + 1 <= 4  (M <= 3)
+
+struct RefConstants {
+  int M = 0;
+  int n = 1;
+  long double nodes[kMaxN];
+  long double weights[kMaxN];
+  long double psi0[kMaxN];         // psi_l(0)
+  long double psi1[kMaxN];         // psi_l(1)
+  long double dmat[kMaxN][kMaxN];  // dmat[a][b] = psi_b'(node_a)
+  long double time_mat[kMaxN][kMaxN];  // K^1 time factor [test][trial]
+  long double time_inv_w[kMaxN][kMaxN];  // time_mat^-1 diag(weights)
+  int nstencils = 0;
+  int stencil_left[kMaxN];  // L of each stencil (R = M - L)
+  long double lambda[kMaxN];
+  long double rec_inv[kMaxN][kMaxN][kMaxN];  // [stencil][p][e]
+  long double sigma[kMaxN][kMaxN];           // oscillation matrix
+  // dnode[alpha-1][k][p] = d^alpha psi_p / dxi^alpha at node k, alpha = 1..M
+  long double dnode[kMaxN - 1][kMaxN][kMaxN];
+};
+
+// Fills 'out' for degree M (0..3). Returns false if a matrix is singular.
+bool build_ref_constants(int M, RefConstants* out);
+
+// WENO constants stated after eq. sigmas.
+constexpr double kLambdaCentral = 1.0e5;
+constexpr double kLambdaOneSided = 1.0;
+constexpr double kWenoEpsilon = 1.0e-14;
+
+}  // namespace ader

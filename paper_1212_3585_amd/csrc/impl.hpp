@@ -1,0 +1,133 @@
+// Templated launcher set for one (dim, M, system, predictor precision).
+#pragma once
+
+#include "plan.hpp"
+
+namespace ader {
+
+inline unsigned int blocks_for(int64_t threads, int per_block = kBlock) {
+  return (unsigned int)((threads + per_block - 1) / per_block);
+}
+
+template <int DIM, int M, int SYS, typename R>
+struct Impl final : ImplBase {
+  static constexpr int n = M + 1;
+  static constexpr int NS = Pow<n, DIM>::v;
+  static constexpr int NV = NVars<SYS, DIM>::v;
+
+  size_t qh_elem_size() const override { return sizeof(R); }
+
+  hipError_t clear_status(char* ws, hipStream_t st) const override {
+    hipLaunchKernelGGL(k_clear_status<DIM>, dim3(1), dim3(64), 0, st,
+                       reinterpret_cast<WsHeader*>(ws));
+    return hipGetLastError();
+  }
+
+  static MeshParams params(const PlanData& p, int64_t ld) {
+    MeshParams mp = p.mp;
+    mp.ld = ld;
+    return mp;
+  }
+
+  hipError_t compute_dt(const PlanData& p, const double* u, int64_t ld, double t, double t_end,
+                        double* dt, char* ws, hipStream_t st) const override {
+    WsHeader* hdr = reinterpret_cast<WsHeader*>(ws);
+    const MeshParams mp = params(p, ld);
+    StageTimer timer(&p.prof, ADER_STAGE_DT, st);
+    hipLaunchKernelGGL(k_dt_reset<DIM>, dim3(1), dim3(64), 0, st, hdr);
+    unsigned int nb = blocks_for(p.ncells);
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL((k_dt_reduce<DIM, SYS>), dim3(nb), dim3(kBlock), 0, st, u, mp, hdr);
+    hipLaunchKernelGGL(k_dt_finalize<DIM>, dim3(1), dim3(64), 0, st, hdr, p.prob.cfl, t, t_end,
+                       dt);
+    return hipGetLastError();
+  }
+
+  // WENO passes: averages -> w_h (per-cell blocks) written to wh
+  hipError_t weno(const PlanData& p, const double* u, int64_t ld, double* wh, char* ws,
+                  hipStream_t st) const {
+    const MeshParams mp = params(p, ld);
+    const int64_t C = p.ncells;
+    StageTimer timer(&p.prof, ADER_STAGE_WENO, st);
+    double* wx = reinterpret_cast<double*>(ws + p.off_wx);
+    hipLaunchKernelGGL((k_weno_pass<DIM, M, NV, 0, false>), dim3(blocks_for(C * NV)),
+                       dim3(kBlock), 0, st, u, ld, 1, wx, mp, p.dc);
+    if constexpr (DIM == 2) {
+      hipLaunchKernelGGL((k_weno_pass<DIM, M, NV, 1, true>), dim3(blocks_for(C * NV * n)),
+                         dim3(kBlock), 0, st, (const double*)wx, C, n, wh, mp, p.dc);
+    } else {
+      double* wxy = reinterpret_cast<double*>(ws + p.off_wxy);
+      hipLaunchKernelGGL((k_weno_pass<DIM, M, NV, 1, false>), dim3(blocks_for(C * NV * n)),
+                         dim3(kBlock), 0, st, (const double*)wx, C, n, wxy, mp, p.dc);
+      hipLaunchKernelGGL((k_weno_pass<DIM, M, NV, 2, true>),
+                         dim3(blocks_for(C * NV * n * n)), dim3(kBlock), 0, st,
+                         (const double*)wxy, C, n * n, wh, mp, p.dc);
+    }
+    return hipGetLastError();
+  }
+
+  hipError_t reconstruct(const PlanData& p, const double* u, int64_t ld, double* wh, char* ws,
+                         hipStream_t st) const override {
+    return weno(p, u, ld, wh, ws, st);
+  }
+
+  template <typename OUT>
+  hipError_t predict(const PlanData& p, const double* wh, int64_t ncells, OUT* qh,
+                     const double* dt, char* ws, hipStream_t st) const {
+    constexpr int CPB = kBlock / NS;
+    WsHeader* hdr = reinterpret_cast<WsHeader*>(ws);
+    MeshParams mp = p.mp;
+    StageTimer timer(&p.prof, ADER_STAGE_PREDICT, st);
+    hipLaunchKernelGGL((k_predict<DIM, M, SYS, R, OUT>), dim3(blocks_for(ncells, CPB)),
+                       dim3(kBlock), 0, st, wh, qh, ncells, dt, mp, p.dc, hdr);
+    return hipGetLastError();
+  }
+
+  hipError_t predict_debug(const PlanData& p, const double* wh, int64_t ncells, double* qh,
+                           const double* dt, char* ws, hipStream_t st) const override {
+    if (ncells == 0) return hipSuccess;
+    return predict<double>(p, wh, ncells, qh, dt, ws, st);
+  }
+
+  hipError_t step(const PlanData& p, const double* u_in, double* u_out, int64_t ld,
+                  const double* dt, char* ws, hipStream_t st) const override {
+    hipError_t e;
+    double* wh = reinterpret_cast<double*>(ws + p.off_wh);
+    R* qh = reinterpret_cast<R*>(ws + p.off_qh);
+    if ((e = weno(p, u_in, ld, wh, ws, st)) != hipSuccess) return e;
+    if ((e = predict<R>(p, wh, p.ncells, qh, dt, ws, st)) != hipSuccess) return e;
+    const MeshParams mp = params(p, ld);
+    double* F[3] = {nullptr, nullptr, nullptr};
+    for (int k = 0; k < DIM; ++k) F[k] = reinterpret_cast<double*>(ws + p.off_f[k]);
+    constexpr int FPB = kBlock / NS;
+    {
+    StageTimer timer(&p.prof, ADER_STAGE_FLUX, st);
+    hipLaunchKernelGGL((k_face_flux<DIM, M, SYS, R, 0>), dim3(blocks_for(p.nfaces[0], FPB)),
+                       dim3(kBlock), 0, st, (const R*)qh, F[0], p.nfaces[0], mp, p.dc);
+    hipLaunchKernelGGL((k_face_flux<DIM, M, SYS, R, 1>), dim3(blocks_for(p.nfaces[1], FPB)),
+                       dim3(kBlock), 0, st, (const R*)qh, F[1], p.nfaces[1], mp, p.dc);
+    if constexpr (DIM == 3)
+      hipLaunchKernelGGL((k_face_flux<DIM, M, SYS, R, 2>), dim3(blocks_for(p.nfaces[2], FPB)),
+                         dim3(kBlock), 0, st, (const R*)qh, F[2], p.nfaces[2], mp, p.dc);
+    }
+    StageTimer timer(&p.prof, ADER_STAGE_UPDATE, st);
+    WsHeader* hdr = reinterpret_cast<WsHeader*>(ws);
+    hipLaunchKernelGGL((k_update<DIM, SYS>), dim3(blocks_for(p.ncells)), dim3(kBlock), 0, st,
+                       u_in, u_out, (const double*)F[0], (const double*)F[1],
+                       (const double*)F[2], p.nfaces[0], p.nfaces[1], p.nfaces[2], dt, mp,
+                       hdr);
+    return hipGetLastError();
+  }
+};
+
+template <int DIM, int M>
+const ImplBase* pick_impl(int sys, int prec) {
+  static const Impl<DIM, M, 0, double> a;
+  static const Impl<DIM, M, 0, float> b;
+  static const Impl<DIM, M, 1, double> c;
+  static const Impl<DIM, M, 1, float> d;
+  if (sys == 0) return prec == 0 ? (const ImplBase*)&a : (const ImplBase*)&b;
+  return prec == 0 ? (const ImplBase*)&c : (const ImplBase*)&d;
+}
+
+}  // namespace ader

@@ -1,0 +1,631 @@
+// HIP kernels of the one-step ADER-WENO step for gfx950 (CDNA4, wave64).
+//
+// Stage kernels (one launch each, data between stages in the workspace):
+//   k_dt_*         CFL time step: per-cell wave-speed sum, wavefront max,
+//                  64-bit atomic max on the bit pattern, finalisation.
+//   k_weno_line    one 1D WENO pass (Section 2.2) along axis K over a
+//                  structure-of-arrays field; the x pass reads the averages,
+//                  the y (and z) passes read the previous pass's nodal values
+//                  (eqs. rec.x, rec.y, rec.z, omegas, sigmas), always fp64.
+//   k_predict      space-time DG predictor (Section 2.3, eq. stdg.final):
+//                  one lane per spatial node of a cell, the lane holding all
+//                  time nodes of all variables; spatial derivative products
+//                  exchange fluxes through LDS, the time product is
+//                  lane-local.  Picard until the relative update drops below
+//                  the tolerance, per cell.
+//   k_face_flux    predictor traces on both sides of a face, Rusanov flux
+//                  (eq. rusanov) at the space-time Gauss points, Gauss sum
+//                  (eqs. flux:F-H): one lane per point, a fixed-order sum.
+//   k_update       conservative update (eq. finite_vol) and device checks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ader {
+
+constexpr int kBlock = 256;
+
+struct DevConsts {
+  double dmat[4][4];   // dmat[a][b] = psi_b'(node_a)
+  double tinvw[4][4];  // (time factor of K^1)^-1 diag(w)
+  double psi0[4], psi1[4], w[4];
+  double rec_inv[4][4][4];  // per stencil: [p][e]
+  double sigma[4][4];
+  double dnode[3][4][4];  // [alpha-1][k][p]: alpha-th derivative of psi_p at node k
+  double lam[4];
+  float dmat_f[4][4];
+  float tinvw_f[4][4];
+  float psi0_f[4], psi1_f[4];
+};
+
+struct MeshParams {
+  int n[3];
+  int bc[3];          // 0 periodic, 1 transmissive
+  double dx[3];
+  double gamma;
+  double adv[3];
+  double tol;
+  int maxit;
+  int64_t ncells;
+  int64_t ld;
+};
+
+struct WsHeader {
+  unsigned int status;
+  unsigned int pad0;
+  unsigned long long iters;
+  unsigned long long smax_bits;
+  double pad1[5];
+};
+
+constexpr unsigned int kFlagNan = 1u, kFlagNonPhysical = 2u, kFlagNoConv = 4u;
+
+template <int B, int E> struct Pow { static constexpr int v = B * Pow<B, E - 1>::v; };
+template <int B> struct Pow<B, 0> { static constexpr int v = 1; };
+
+// number of conserved variables: linear advection 1, Euler dim + 2
+template <int SYS, int DIM> struct NVars { static constexpr int v = SYS == 0 ? 1 : DIM + 2; };
+
+// ---------------------------------------------------------------- physics
+// Physical fluxes of all DIM directions at one state (eq. Euler-system, or
+// linear advection f_k = a_k u).  F[k][v].
+template <int SYS, int DIM, typename R>
+__device__ __forceinline__ void phys_fluxes(const R (&q)[NVars<SYS, DIM>::v], R gamma,
+                                            const R (&adv)[3],
+                                            R (&F)[DIM][NVars<SYS, DIM>::v]) {
+  if constexpr (SYS == 0) {
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) F[k][0] = adv[k] * q[0];
+  } else {
+    const R rho = q[0];
+    R vel[DIM];
+    R kin = R(0);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      vel[k] = q[1 + k] / rho;
+      kin += q[1 + k] * vel[k];
+    }
+    const R E = q[DIM + 1];
+    const R p = (gamma - R(1)) * (E - R(0.5) * kin);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      F[k][0] = q[1 + k];
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) F[k][1 + m] = q[1 + m] * vel[k];
+      F[k][1 + k] += p;
+      F[k][DIM + 1] = vel[k] * (E + p);
+    }
+  }
+}
+
+// flux along one axis k and |largest eigenvalue| along k (fp64)
+template <int SYS, int DIM>
+__device__ __forceinline__ void phys_flux_dir(const double (&q)[NVars<SYS, DIM>::v], int k,
+                                              double gamma, const double (&adv)[3],
+                                              double (&f)[NVars<SYS, DIM>::v], double& speed) {
+  if constexpr (SYS == 0) {
+    f[0] = adv[k] * q[0];
+    speed = fabs(adv[k]);
+  } else {
+    const double rho = q[0];
+    double vel[DIM];
+    double kin = 0.0;
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) {
+      vel[m] = q[1 + m] / rho;
+      kin += q[1 + m] * vel[m];
+    }
+    const double E = q[DIM + 1];
+    const double p = (gamma - 1.0) * (E - 0.5 * kin);
+    double vk = 0.0, mk = 0.0;
+#pragma unroll
+    for (int m = 0; m < DIM; ++m)
+      if (m == k) { vk = vel[m]; mk = q[1 + m]; }
+    f[0] = mk;
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) f[1 + m] = q[1 + m] * vk;
+#pragma unroll
+    for (int m = 0; m < DIM; ++m)
+      if (m == k) f[1 + m] += p;
+    f[DIM + 1] = vk * (E + p);
+    speed = fabs(vk) + sqrt(gamma * p / rho);
+  }
+}
+
+// ------------------------------------------------------------- indexing
+__device__ __forceinline__ int bc_map(int i, int n, int bc) {
+  if (bc == 0) {
+    i %= n;
+    return i < 0 ? i + n : i;
+  }
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// ------------------------------------------------------------- WENO line
+template <int M> struct Stencils;
+template <> struct Stencils<0> { static constexpr int ns = 3; };
+template <> struct Stencils<1> { static constexpr int ns = 4; };
+template <> struct Stencils<2> { static constexpr int ns = 3; };
+template <> struct Stencils<3> { static constexpr int ns = 4; };
+
+template <int M>
+__device__ __forceinline__ constexpr int stencil_left(int s) {
+  if constexpr (M % 2 == 0) {
+    return s == 0 ? M / 2 : (s == 1 ? M : 0);
+  } else {
+    return s == 0 ? M / 2 + 1 : (s == 1 ? M / 2 : (s == 2 ? M : 0));
+  }
+}
+
+// One-dimensional WENO on 2M+1 averages v[] (home cell at index M) -> the
+// n nodal values of the combined polynomial (eqs. rec.x, sigmas, omegas, weno)
+template <int M>
+__device__ __forceinline__ void weno_line(const double (&v)[2 * M + 1], const DevConsts& c,
+                                          double (&out)[M + 1]) {
+  constexpr int n = M + 1;
+  constexpr int NSt = Stencils<M>::ns;
+  double ws[NSt][n];
+  double om[NSt];
+#pragma unroll
+  for (int s = 0; s < NSt; ++s) {
+    const int base = M - stencil_left<M>(s);
+#pragma unroll
+    for (int p = 0; p < n; ++p) {
+      double acc = 0.0;
+#pragma unroll
+      for (int e = 0; e < n; ++e) acc += c.rec_inv[s][p][e] * v[base + e];
+      ws[s][p] = acc;
+    }
+    // sigma = sum_alpha int_0^1 (d^alpha w / dxi^alpha)^2 (eq. sigmas), the
+    // squared derivative values at the Gauss nodes summed with the weights
+    double sig = 0.0;
+#pragma unroll
+    for (int al = 0; al < M; ++al) {
+      double part = 0.0;
+#pragma unroll
+      for (int k = 0; k < n; ++k) {
+        double d = 0.0;
+#pragma unroll
+        for (int p = 0; p < n; ++p) d += c.dnode[al][k][p] * ws[s][p];
+        part += c.w[k] * (d * d);
+      }
+      sig += part;
+    }
+    double x = sig + 1.0e-14;
+    x = x * x;  // ^2
+    x = x * x;  // ^4
+    x = x * x;  // ^8
+    om[s] = c.lam[s] / x;
+  }
+  double tot = 0.0;
+#pragma unroll
+  for (int s = 0; s < NSt; ++s) tot += om[s];
+#pragma unroll
+  for (int p = 0; p < n; ++p) {
+    double acc = 0.0;
+#pragma unroll
+    for (int s = 0; s < NSt; ++s) acc += (om[s] / tot) * ws[s][p];
+    out[p] = acc;
+  }
+}
+
+// WENO pass along axis K.  The input field holds 'nin' nodal components per
+// variable (1 for the averages; n for the y pass; n^2 for the z pass), laid
+// out src[(v * nin + comp) * sld + cell].  Each thread handles one
+// (variable, component, cell) line and writes n outputs.
+//   OUT_AOS = false: dst[((v * n + p) * nin + comp) * C + cell], so that the
+//                    next pass sees nin' = n * nin components comp' =
+//                    comp + nin * p (earlier axes fastest)
+//   OUT_AOS = true : dst[(cell * NV + v) * n^DIM + node(comp, p)] where the
+//                    new index p becomes the slowest spatial index (x, y, z
+//                    order), i.e. node = comp + nin * p.
+template <int DIM, int M, int NV, int K, bool OUT_AOS>
+__global__ void __launch_bounds__(kBlock)
+k_weno_pass(const double* __restrict__ src, int64_t sld, int nin, double* __restrict__ dst,
+            MeshParams mp, DevConsts c) {
+  constexpr int n = M + 1;
+  const int64_t C = mp.ncells;
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= C * NV * nin) return;
+  const int64_t cell = t % C;
+  const int64_t vc = t / C;  // v * nin + comp
+  const int comp = (int)(vc % nin);
+  const int v = (int)(vc / nin);
+  int idx[3];
+  idx[0] = (int)(cell % mp.n[0]);
+  idx[1] = (int)((cell / mp.n[0]) % mp.n[1]);
+  idx[2] = DIM == 3 ? (int)(cell / ((int64_t)mp.n[0] * mp.n[1])) : 0;
+  const int64_t stride = K == 0 ? 1 : (K == 1 ? (int64_t)mp.n[0] : (int64_t)mp.n[0] * mp.n[1]);
+  double vals[2 * M + 1];
+  const double* row = src + vc * sld + (cell - (int64_t)idx[K] * stride);
+#pragma unroll
+  for (int o = 0; o < 2 * M + 1; ++o) {
+    const int j = bc_map(idx[K] + o - M, mp.n[K], mp.bc[K]);
+    vals[o] = row[(int64_t)j * stride];
+  }
+  double w[n];
+  weno_line<M>(vals, c, w);
+  if constexpr (OUT_AOS) {
+    constexpr int NS = Pow<n, DIM>::v;
+#pragma unroll
+    for (int p = 0; p < n; ++p) dst[(cell * NV + v) * NS + comp + nin * p] = w[p];
+  } else {
+#pragma unroll
+    for (int p = 0; p < n; ++p) dst[(((int64_t)v * n + p) * nin + comp) * C + cell] = w[p];
+  }
+}
+
+// ------------------------------------------------------------- predictor
+template <typename R> struct Bits;
+template <> struct Bits<double> {
+  using U = unsigned long long;
+  static __device__ __forceinline__ U of(double x) { return __double_as_longlong(x); }
+  static __device__ __forceinline__ double val(U u) { return __longlong_as_double((long long)u); }
+};
+template <> struct Bits<float> {
+  using U = unsigned int;
+  static __device__ __forceinline__ U of(float x) { return __float_as_uint(x); }
+  static __device__ __forceinline__ float val(U u) { return __uint_as_float(u); }
+};
+
+template <typename R> __device__ __forceinline__ R cget(const double& d, const float& f);
+template <> __device__ __forceinline__ double cget<double>(const double& d, const float&) { return d; }
+template <> __device__ __forceinline__ float cget<float>(const double&, const float& f) { return f; }
+
+// Select row 'a' of a 4x4 constant table into registers (unrolled selects, so
+// a lane-dependent row never turns into an indexed private-memory access).
+template <int n, typename R>
+__device__ __forceinline__ void pick_row(const DevConsts& c, int a, R (&row)[n]) {
+#pragma unroll
+  for (int b = 0; b < n; ++b) {
+    R r = cget<R>(c.dmat[0][b], c.dmat_f[0][b]);
+#pragma unroll
+    for (int aa = 1; aa < n; ++aa)
+      r = (a == aa) ? cget<R>(c.dmat[aa][b], c.dmat_f[aa][b]) : r;
+    row[b] = r;
+  }
+}
+
+// Space-time predictor of 'ncells' cells whose nodal reconstructions are
+// wh[(cell * NV + v) * NS + a].  Output qh[(cell * NV + v) * NST + a + NS * s]
+// in type OUT.  One lane per spatial node a; CPB cells per 256-thread block.
+template <int DIM, int M, int SYS, typename R, typename OUT>
+__global__ void __launch_bounds__(kBlock)
+k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
+          const double* __restrict__ dt_dev, MeshParams mp, DevConsts c, WsHeader* hdr) {
+  constexpr int n = M + 1;
+  constexpr int NS = Pow<n, DIM>::v;
+  constexpr int NST = NS * n;
+  constexpr int NV = NVars<SYS, DIM>::v;
+  constexpr int G = NS;
+  constexpr int CPB = kBlock / G;
+  using U = typename Bits<R>::U;
+  __shared__ R shF[DIM * NV * kBlock];
+  __shared__ U shDelta[CPB];
+  __shared__ U shMag[CPB];
+
+  const int tid = threadIdx.x;
+  const int lc = tid / G;
+  const int a = tid - lc * G;
+  const int64_t cell = (int64_t)blockIdx.x * CPB + lc;
+  const bool active = lc < CPB && cell < ncells;
+  int ak[3];
+  ak[0] = a % n;
+  ak[1] = (a / n) % n;
+  ak[2] = a / (n * n);
+
+  const double dt = *dt_dev;
+  R cour[DIM];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) cour[k] = (R)(dt / mp.dx[k]);
+  const R gamma = (R)mp.gamma;
+  R adv[3] = {(R)mp.adv[0], (R)mp.adv[1], (R)mp.adv[2]};
+
+  R drow[DIM][n];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) pick_row<n, R>(c, ak[k], drow[k]);
+
+  R w[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+    w[v] = active ? (R)wh[(cell * NV + v) * NS + a] : (v == 0 || v == NV - 1 ? R(1) : R(0));
+  R q[NV][n];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int s = 0; s < n; ++s) q[v][s] = w[v];
+
+  const R tol = (R)mp.tol;
+  bool done = !active;
+  int iters = 0;
+  for (int it = 1; it <= mp.maxit; ++it) {
+    if (tid < CPB) {
+      shDelta[tid] = 0;
+      shMag[tid] = 0;
+    }
+    R Racc[NV][n];
+#pragma unroll
+    for (int s = 0; s < n; ++s) {
+      R qs[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) qs[v] = q[v][s];
+      R F[DIM][NV];
+      phys_fluxes<SYS, DIM, R>(qs, gamma, adv, F);
+#pragma unroll
+      for (int k = 0; k < DIM; ++k)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) shF[(k * NV + v) * kBlock + tid] = cour[k] * F[k][v];
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        R acc = R(0);
+        // lanes past the last whole cell of the block read nothing
+        if (lc < CPB) {
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) {
+            const int stride = k == 0 ? 1 : (k == 1 ? n : n * n);
+            const int base = tid - ak[k] * stride;
+#pragma unroll
+            for (int b = 0; b < n; ++b)
+              acc += drow[k][b] * shF[(k * NV + v) * kBlock + base + b * stride];
+          }
+        }
+        Racc[v][s] = acc;
+      }
+      __syncthreads();
+    }
+    R delta = R(0), mag = R(0);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+      for (int s = 0; s < n; ++s) {
+        R acc = R(0);
+#pragma unroll
+        for (int sp = 0; sp < n; ++sp)
+          acc += cget<R>(c.tinvw[s][sp], c.tinvw_f[s][sp]) * Racc[v][sp];
+        const R qn = w[v] - acc;
+        delta = fmax(delta, fabs(qn - q[v][s]));
+        mag = fmax(mag, fabs(qn));
+        if (!done) q[v][s] = qn;
+      }
+    }
+    if (!done) {
+      atomicMax(&shDelta[lc], Bits<R>::of(delta));
+      atomicMax(&shMag[lc], Bits<R>::of(mag));
+    }
+    __syncthreads();
+    if (!done) {
+      const R dcell = Bits<R>::val(shDelta[lc]);
+      const R mcell = Bits<R>::val(shMag[lc]);
+      if (dcell <= tol * fmax(R(1), mcell)) {
+        done = true;
+        iters = it;
+      }
+    }
+    if (__syncthreads_and(done)) break;
+  }
+  if (active) {
+    if (!done) {
+      iters = mp.maxit;
+      if (a == 0) atomicOr(&hdr->status, kFlagNoConv);
+    }
+    if (a == 0) atomicAdd(&hdr->iters, (unsigned long long)iters);
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int s = 0; s < n; ++s) qh[(cell * NV + v) * NST + a + NS * s] = (OUT)q[v][s];
+  }
+}
+
+// ------------------------------------------------------------- face fluxes
+// Faces along axis K are indexed on the mesh extended by one along K:
+// f = i + Ex * (j + Ey * k) with E = n except E_K = n_K + 1.  Face index i_K
+// separates cells i_K - 1 and i_K.  F[v * nf + f].
+template <int DIM, int M, int SYS, typename R, int K>
+__global__ void __launch_bounds__(kBlock)
+k_face_flux(const R* __restrict__ qh, double* __restrict__ F, int64_t nfaces, MeshParams mp,
+            DevConsts c) {
+  constexpr int n = M + 1;
+  constexpr int NS = Pow<n, DIM>::v;
+  constexpr int NST = NS * n;
+  constexpr int NV = NVars<SYS, DIM>::v;
+  constexpr int NT = NS / n;  // transverse nodes
+  constexpr int G = NS;       // (transverse points) x (time points)
+  constexpr int FPB = kBlock / G;
+  __shared__ double sh[NV * kBlock];
+
+  const int tid = threadIdx.x;
+  const int lf = tid / G;
+  const int l = tid - lf * G;
+  const int64_t f = (int64_t)blockIdx.x * FPB + lf;
+  const bool active = lf < FPB && f < nfaces;
+
+  double wpt = 0.0;
+  if (active) {
+    int e[3] = {mp.n[0], mp.n[1], DIM == 3 ? mp.n[2] : 1};
+    e[K] += 1;
+    int fi[3];
+    fi[0] = (int)(f % e[0]);
+    fi[1] = (int)((f / e[0]) % e[1]);
+    fi[2] = (int)(f / ((int64_t)e[0] * e[1]));
+    // neighbouring cells along K
+    const int iL = fi[K] - 1, iR = fi[K];
+    const bool outL = iL < 0, outR = iR >= mp.n[K];
+    int cl[3] = {fi[0], fi[1], fi[2]}, cr[3] = {fi[0], fi[1], fi[2]};
+    cl[K] = bc_map(iL, mp.n[K], mp.bc[K]);
+    cr[K] = bc_map(iR, mp.n[K], mp.bc[K]);
+    const int64_t cellL = cl[0] + (int64_t)mp.n[0] * (cl[1] + (int64_t)mp.n[1] * cl[2]);
+    const int64_t cellR = cr[0] + (int64_t)mp.n[0] * (cr[1] + (int64_t)mp.n[1] * cr[2]);
+    // lane -> (transverse node b, time node s)
+    const int b = l % NT;
+    const int s = l / NT;
+    int tb[2] = {b % n, b / n};  // transverse axes in increasing order
+    int strideK = K == 0 ? 1 : (K == 1 ? n : n * n);
+    int abase = 0;
+    {
+      int ti = 0;
+#pragma unroll
+      for (int ax = 0; ax < DIM; ++ax) {
+        if (ax == K) continue;
+        const int st = ax == 0 ? 1 : (ax == 1 ? n : n * n);
+        abase += tb[ti] * st;
+        ++ti;
+      }
+    }
+    double qL[NV], qR[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      R accL = R(0), accR = R(0);
+#pragma unroll
+      for (int j = 0; j < n; ++j) {
+        const int node = abase + j * strideK + NS * s;
+        accL += cget<R>(c.psi1[j], c.psi1_f[j]) * qh[(cellL * NV + v) * NST + node];
+        accR += cget<R>(c.psi0[j], c.psi0_f[j]) * qh[(cellR * NV + v) * NST + node];
+      }
+      qL[v] = (double)accL;
+      qR[v] = (double)accR;
+    }
+    if (mp.bc[K] != 0) {
+      if (outL) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) qL[v] = qR[v];
+      }
+      if (outR) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) qR[v] = qL[v];
+      }
+    }
+    double fL[NV], fR[NV], sL, sR;
+    const double adv[3] = {mp.adv[0], mp.adv[1], mp.adv[2]};
+    phys_flux_dir<SYS, DIM>(qL, K, mp.gamma, adv, fL, sL);
+    phys_flux_dir<SYS, DIM>(qR, K, mp.gamma, adv, fR, sR);
+    const double smax = fmax(sL, sR);
+    double wt = c.w[s];
+    {
+      int ti = 0;
+#pragma unroll
+      for (int ax = 0; ax < DIM; ++ax) {
+        if (ax == K) continue;
+        wt *= c.w[tb[ti]];
+        ++ti;
+      }
+    }
+    wpt = wt;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      sh[v * kBlock + tid] = wt * (0.5 * (fL[v] + fR[v]) - 0.5 * smax * (qR[v] - qL[v]));
+  }
+  (void)wpt;
+  __syncthreads();
+  if (active && l == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double acc = 0.0;
+      for (int j = 0; j < G; ++j) acc += sh[v * kBlock + tid + j];
+      F[v * nfaces + f] = acc;
+    }
+  }
+}
+
+// ------------------------------------------------------------- update
+template <int DIM, int SYS>
+__global__ void __launch_bounds__(kBlock)
+k_update(const double* __restrict__ u_in, double* __restrict__ u_out, const double* __restrict__ Fx,
+         const double* __restrict__ Fy, const double* __restrict__ Fz, int64_t nfx, int64_t nfy,
+         int64_t nfz, const double* __restrict__ dt_dev, MeshParams mp, WsHeader* hdr) {
+  constexpr int NV = NVars<SYS, DIM>::v;
+  const int64_t cell = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (cell >= mp.ncells) return;
+  const int i = (int)(cell % mp.n[0]);
+  const int j = (int)((cell / mp.n[0]) % mp.n[1]);
+  const int k = DIM == 3 ? (int)(cell / ((int64_t)mp.n[0] * mp.n[1])) : 0;
+  const double dt = *dt_dev;
+  const int nx = mp.n[0], ny = mp.n[1];
+  const int64_t fx0 = i + (int64_t)(nx + 1) * (j + (int64_t)ny * k);
+  const int64_t fy0 = i + (int64_t)nx * (j + (int64_t)(ny + 1) * k);
+  const int64_t fz0 = cell;
+  double q[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double u = u_in[v * mp.ld + cell];
+    u -= (dt / mp.dx[0]) * (Fx[v * nfx + fx0 + 1] - Fx[v * nfx + fx0]);
+    u -= (dt / mp.dx[1]) * (Fy[v * nfy + fy0 + nx] - Fy[v * nfy + fy0]);
+    if constexpr (DIM == 3)
+      u -= (dt / mp.dx[2]) * (Fz[v * nfz + fz0 + (int64_t)nx * ny] - Fz[v * nfz + fz0]);
+    u_out[v * mp.ld + cell] = u;
+    q[v] = u;
+  }
+  unsigned int flags = 0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+    if (q[v] != q[v]) flags |= kFlagNan;
+  if constexpr (SYS == 1) {
+    double kin = 0.0;
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) kin += q[1 + m] * q[1 + m] / q[0];
+    const double p = (mp.gamma - 1.0) * (q[DIM + 1] - 0.5 * kin);
+    if (!(q[0] > 0.0) || !(p > 0.0)) flags |= kFlagNonPhysical;
+  }
+  if (flags) atomicOr(&hdr->status, flags);
+}
+
+// ------------------------------------------------------------- time step
+template <int DIM>
+__global__ void k_dt_reset(WsHeader* hdr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) hdr->smax_bits = 0ull;
+}
+
+template <int DIM>
+__global__ void k_clear_status(WsHeader* hdr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    hdr->status = 0u;
+    hdr->iters = 0ull;
+  }
+}
+
+template <int DIM, int SYS>
+__global__ void __launch_bounds__(kBlock)
+k_dt_reduce(const double* __restrict__ u, MeshParams mp, WsHeader* hdr) {
+  constexpr int NV = NVars<SYS, DIM>::v;
+  double smax = 0.0;
+  const double adv[3] = {mp.adv[0], mp.adv[1], mp.adv[2]};
+  for (int64_t cell = (int64_t)blockIdx.x * kBlock + threadIdx.x; cell < mp.ncells;
+       cell += (int64_t)gridDim.x * kBlock) {
+    double q[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) q[v] = u[v * mp.ld + cell];
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      double f[NV], sp;
+      phys_flux_dir<SYS, DIM>(q, k, mp.gamma, adv, f, sp);
+      s += sp / mp.dx[k];
+    }
+    // NaN must win the maximum so that it reaches dt and the status word
+    smax = (s != s || s > smax) ? s : smax;
+  }
+  unsigned long long bits = __double_as_longlong(smax);
+  // wavefront maximum (non-negative doubles order like their bit patterns)
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_xor(bits, off, 64);
+    bits = o > bits ? o : bits;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(&hdr->smax_bits, bits);
+}
+
+template <int DIM>
+__global__ void k_dt_finalize(WsHeader* hdr, double cfl, double t, double t_end, double* dt_out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const double smax = __longlong_as_double((long long)hdr->smax_bits);
+    double dt = cfl / smax;
+    const double rest = t_end - t;
+    dt = rest < dt ? rest : dt;
+    if (dt != dt) atomicOr(&hdr->status, kFlagNan);
+    *dt_out = dt;
+  }
+}
+
+}  // namespace ader

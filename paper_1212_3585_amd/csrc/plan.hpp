@@ -1,0 +1,88 @@
+// Plan data shared by the C ABI and the templated launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/ader.h"
+#include "consts.hpp"
+#include "kernels.hpp"
+
+namespace ader {
+
+// Optional per-stage timing with HIP events (see ader_profile_begin).
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  hipError_t mark(int stage, hipStream_t st, hipEvent_t* a) {
+    if (!on) return hipSuccess;
+    hipError_t e = hipEventCreate(a);
+    if (e == hipSuccess) e = hipEventRecord(*a, st);
+    (void)stage;
+    return e;
+  }
+  hipError_t close(int stage, hipStream_t st, hipEvent_t a) {
+    if (!on) return hipSuccess;
+    hipEvent_t b;
+    hipError_t e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e == hipSuccess) recs.push_back({stage, a, b});
+    return e;
+  }
+};
+
+// RAII bracket of one stage
+struct StageTimer {
+  Profiler* prof;
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  StageTimer(Profiler* p, int s, hipStream_t stream) : prof(p), stage(s), st(stream) {
+    if (prof && prof->on) prof->mark(stage, st, &a);
+  }
+  ~StageTimer() {
+    if (prof && prof->on && a) prof->close(stage, st, a);
+  }
+};
+
+struct PlanData {
+  ader_problem prob;
+  int dim = 2, M = 0, n = 1, nv = 1, ns = 1, nst = 1;
+  int64_t ncells = 0;
+  int64_t nfaces[3] = {0, 0, 0};
+  MeshParams mp;
+  DevConsts dc;
+  RefConstants ref;
+  // workspace layout (byte offsets; every section 256-byte aligned)
+  size_t off_wx = 0, off_wxy = 0, off_wh = 0, off_qh = 0, off_f[3] = {0, 0, 0};
+  size_t ws_bytes = 0;
+  mutable Profiler prof;
+};
+
+// Per-(dim, M, system, precision) launcher set.
+struct ImplBase {
+  virtual ~ImplBase() = default;
+  virtual size_t qh_elem_size() const = 0;
+  virtual hipError_t clear_status(char* ws, hipStream_t st) const = 0;
+  virtual hipError_t compute_dt(const PlanData& p, const double* u, int64_t ld, double t,
+                                double t_end, double* dt, char* ws, hipStream_t st) const = 0;
+  virtual hipError_t reconstruct(const PlanData& p, const double* u, int64_t ld, double* wh,
+                                 char* ws, hipStream_t st) const = 0;
+  virtual hipError_t predict_debug(const PlanData& p, const double* wh, int64_t ncells,
+                                   double* qh, const double* dt, char* ws,
+                                   hipStream_t st) const = 0;
+  virtual hipError_t step(const PlanData& p, const double* u_in, double* u_out, int64_t ld,
+                          const double* dt, char* ws, hipStream_t st) const = 0;
+};
+
+const ImplBase* make_impl_2d(int M, int sys, int prec);
+const ImplBase* make_impl_3d(int M, int sys, int prec);
+
+}  // namespace ader

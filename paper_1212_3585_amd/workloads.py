@@ -21,7 +21,10 @@ Workloads (conserved variables (rho, rho v, E), ideal gas):
     (0.125, 0.1) outside, at rest; then rho *= 1 + 0.01 U(-1, 1) (seed 2);
   * spherical blast on [-1, 1]^3: rho = 1, p = 1 for r < 0.3 and 0.1 outside;
     then rho *= 1 + 0.01 U(-1, 1) (seed 3);
-  * linear advection of a smooth sine wave, and a seeded random field.
+  * linear advection of a smooth sine wave, and a seeded random field;
+  * a generic test state on the unit cube: smooth sinusoidal density,
+    velocity and pressure with seeded phases, a discontinuity (density x1.5,
+    pressure x1.8 for x < 0.4) and 1% seeded per-cell noise.
 """
 from __future__ import annotations
 
@@ -119,6 +122,26 @@ def sine_wave(n, dim=2, L=1.0):
     """Average of sin(2 pi (x + y [+ z]) / L) on the periodic cube [0, L]^d."""
     fn = lambda *c: np.sin(2.0 * np.pi * sum(c) / L)[None]
     return _cell_average(fn, (n,) * dim, (0.0,) * dim, (L,) * dim)
+
+
+def perturbed_smooth_euler(n, seed, noise=0.01, gamma=GAMMA):
+    """Smooth state + jump + per-cell noise on the unit cube, averages per cell.
+
+    Cell-centre values (no sub-cell quadrature): a test input, not a solution.
+    """
+    dim = len(n)
+    r = np.random.Generator(np.random.PCG64(seed))
+    X = np.meshgrid(*[(np.arange(k) + 0.5) / k for k in n], indexing="ij")
+    ph = r.uniform(0.0, 2.0 * np.pi, size=4)
+    rho = 1.0 + 0.2 * np.sin(2 * np.pi * X[0] + ph[0]) * np.cos(2 * np.pi * X[-1] + ph[1])
+    vel = [0.3 * np.sin(2 * np.pi * X[(k + 1) % dim] + ph[2 + k % 2]) for k in range(dim)]
+    p = 1.0 + 0.2 * np.cos(2 * np.pi * X[0] + ph[3])
+    jump = X[0] < 0.4
+    rho = np.where(jump, 1.5 * rho, rho)
+    p = np.where(jump, 1.8 * p, p)
+    rho = rho * (1.0 + noise * r.uniform(-1.0, 1.0, size=rho.shape))
+    vel = [v + noise * r.uniform(-1.0, 1.0, size=v.shape) for v in vel]
+    return conserved_from_primitive(rho, vel, p, gamma)
 
 
 def random_field(shape, seed, lo=-1.0, hi=1.0):

@@ -1,0 +1,65 @@
+"""Shared helpers of the GPU tests: problem construction and comparisons."""
+import sys
+
+import numpy as np
+
+import oracle
+from oracle import Euler, LinearAdvection, Problem as OProblem
+from paper_1212_3585_amd import workloads as wl
+
+BCS = {"periodic": 0, "transmissive": 1}
+
+
+def say(msg):
+    """Name the case before a GPU step (survives a crash of the process)."""
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def make_pair(ader, dim, M, n, lo, hi, bc="periodic", system="euler", adv=(1.0, 0.5, 0.25),
+              precision=0, cfl=0.9, tol=1e-14, maxit=64, gamma=1.4):
+    """(oracle problem, GPU problem) describing the same mesh and scheme."""
+    bcs = [bc] * dim if isinstance(bc, str) else list(bc)
+    sysobj = Euler(dim, gamma) if system == "euler" else LinearAdvection(dim, adv)
+    op = OProblem(dim, M, sysobj, tuple(n), tuple(lo), tuple(hi), bcs, cfl=cfl,
+                  tol=tol, max_iter=maxit)
+    gp = ader.Problem(dim=dim, M=M, system=ader.SYS_EULER if system == "euler" else ader.SYS_LINADV,
+                      gamma=gamma, adv=tuple(adv), n=tuple(n) + (1,) * (3 - dim),
+                      lo=tuple(lo) + (0.0,) * (3 - dim), hi=tuple(hi) + (1.0,) * (3 - dim),
+                      bc=tuple(BCS[b] for b in bcs) + (0,) * (3 - dim), cfl=cfl,
+                      precision=precision, picard_tol=tol, picard_max=maxit)
+    return op, gp
+
+
+def to_device(U, ld=None):
+    import torch
+    return torch.tensor(wl.to_soa(U, ld), dtype=torch.float64, device="cuda")
+
+
+def from_device(u, shape):
+    return wl.from_soa(u.cpu().numpy(), shape)
+
+
+def rel_l1(a, b):
+    """Relative L1 distance of two states, pooled over the conserved variables:
+    sum_{v,cells} |a - b| / sum_{v,cells} |b|."""
+    return float(np.abs(a - b).sum() / np.abs(b).sum())
+
+
+def rel_l1_per_var(a, b):
+    """Per-variable relative L1 (informative: a variable near zero, such as the
+    momentum of a gas at rest, makes its own ratio meaningless)."""
+    return [float(np.abs(a[v] - b[v]).sum() / max(np.abs(b[v]).sum(), 1e-300))
+            for v in range(a.shape[0])]
+
+
+def oracle_wh_to_gpu_layout(w, dim):
+    """oracle w[v, C, px, py(, pz)] -> flat [(cell * nv + v) * n^d + a]."""
+    from oracle.predictor import spatial_flat
+    wf = spatial_flat(w, dim)                 # [v, C, a]
+    return np.ascontiguousarray(np.transpose(wf, (1, 0, 2))).ravel()
+
+
+def gpu_qh_to_oracle_layout(qh, nv, C, nst):
+    """flat [(cell * nv + v) * nst + i] -> [v, C, nst]."""
+    return np.transpose(qh.reshape(C, nv, nst), (1, 0, 2))

@@ -1,0 +1,122 @@
+"""Host-side checks of the C ABI: exports, argument validation, constants.
+
+None of these calls launches a kernel or touches a GPU.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.basis import basis
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ader.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1212_3585_amd import ader
+    if not os.path.exists(ader._LIB_PATH):
+        from paper_1212_3585_amd.build import build_library
+        build_library()
+    return ader.load_library()
+
+
+@pytest.fixture(scope="module")
+def ader_mod(lib):
+    from paper_1212_3585_amd import ader
+    return ader
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(ader_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib, ader_mod):
+    names = declared_functions()
+    assert set(names) == set(ader_mod.EXPORTS)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def _create(ader_mod, **kw):
+    prob = ader_mod.Problem(**kw).to_c()
+    plan = ctypes.c_void_p()
+    st = ader_mod.load_library().ader_plan_create(ctypes.byref(prob), ctypes.byref(plan))
+    return st, plan
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(dim=1), -2), (dict(M=4), -2), (dict(M=-1), -2), (dict(system=7), -2),
+    (dict(n=(0, 4, 1)), -1), (dict(cfl=0.0), -1), (dict(cfl=1.5), -1),
+    (dict(gamma=1.0), -1), (dict(picard_tol=0.0), -1), (dict(picard_max=0), -1),
+    (dict(hi=(0.0, 1.0, 1.0)), -1), (dict(bc=(0, 5, 0)), -1), (dict(precision=3), -1),
+    (dict(lo=(float("nan"), 0.0, 0.0)), -1),
+])
+def test_plan_create_rejects_bad_problems(ader_mod, kw, status):
+    st, plan = _create(ader_mod, **kw)
+    assert st == status
+    assert not plan.value
+    assert len(ader_mod.load_library().ader_last_error()) > 0
+
+
+def test_plan_basics_and_workspace(ader_mod):
+    lib = ader_mod.load_library()
+    for dim, M, system, nv in [(2, 3, 1, 4), (3, 2, 1, 5), (2, 1, 0, 1)]:
+        st, plan = _create(ader_mod, dim=dim, M=M, system=system, n=(8, 6, 5))
+        assert st == 0
+        n = ctypes.c_int()
+        assert lib.ader_plan_nvar(plan, ctypes.byref(n)) == 0 and n.value == nv
+        b = ctypes.c_size_t()
+        assert lib.ader_workspace_bytes(plan, ctypes.byref(b)) == 0
+        C = 8 * 6 * (5 if dim == 3 else 1)
+        # at least the predictor tensor of every cell
+        assert b.value >= 8 * nv * (M + 1) ** (dim + 1) * C
+        assert lib.ader_plan_destroy(plan) == 0
+    assert lib.ader_plan_destroy(None) == 0
+
+
+def test_compute_calls_validate_before_launching(ader_mod):
+    lib = ader_mod.load_library()
+    st, plan = _create(ader_mod, dim=2, M=2, n=(8, 8, 1))
+    assert st == 0
+    fake = ctypes.c_void_p(0x10000)
+    ws = ctypes.c_void_p(0x20000)
+    dt = ctypes.c_void_p(0x30000)
+    # same input and output
+    assert lib.ader_step(plan, fake, fake, 64, dt, ws, None) == -1
+    # overlapping input and output
+    assert lib.ader_step(plan, fake, ctypes.c_void_p(0x10000 + 8), 64, dt, ws, None) == -1
+    # ld too small
+    assert lib.ader_step(plan, fake, ctypes.c_void_p(0x90000), 63, dt, ws, None) == -1
+    # misaligned / null workspace
+    assert lib.ader_step(plan, fake, ctypes.c_void_p(0x90000), 64, dt,
+                         ctypes.c_void_p(0x20008), None) == -4
+    assert lib.ader_step(plan, fake, ctypes.c_void_p(0x90000), 64, dt, None, None) == -4
+    # bad time interval
+    assert lib.ader_compute_dt(plan, fake, 64, 1.0, 0.5, dt, ws, None) == -1
+    assert lib.ader_debug_predict(plan, fake, -1, fake, dt, ws, None) == -1
+    lib.ader_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("M", [0, 1, 2, 3])
+def test_device_path_constants_agree_with_oracle(ader_mod, M):
+    """The library's long-double generator and the oracle's exact polynomial
+    algebra are separate routes to the same reference-element constants."""
+    lib = ader_mod.load_library()
+    st, plan = _create(ader_mod, dim=2, M=M, n=(4, 4, 1))
+    assert st == 0
+    n = M + 1
+    arrs = [np.zeros(n), np.zeros(n), np.zeros(n * n), np.zeros(n * n)]
+    assert lib.ader_debug_constants(plan, *[a.ctypes.data_as(ctypes.c_void_p)
+                                            for a in arrs]) == 0
+    b = basis(M)
+    np.testing.assert_allclose(arrs[0], b.nodes, rtol=0, atol=2e-16)
+    np.testing.assert_allclose(arrs[1], b.weights, rtol=0, atol=2e-16)
+    np.testing.assert_allclose(arrs[2].reshape(n, n), b.dmat, rtol=0, atol=1e-13)
+    A = np.linalg.solve(b.time_matrix(), np.diag(b.weights))
+    np.testing.assert_allclose(arrs[3].reshape(n, n), A, rtol=0, atol=1e-14)
+    lib.ader_plan_destroy(plan)

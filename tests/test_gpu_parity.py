@@ -1,0 +1,271 @@
+"""Parity of the HIP path (through the C ABI) with the CPU fp64 oracle.
+
+Bar: relative L1 pooled over the conserved variables,
+sum_{v,cells} |gpu - oracle| / sum_{v,cells} |oracle| <= 1e-11, for the fp64
+path; the fp32-predictor path states its L1 error
+against the fp64 oracle and must stay below 1e-5.  Inputs are seeded and
+shaped like the paper's tests; mesh sizes span several thread blocks and end
+in ragged tails.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.predictor import predict as oracle_predict
+from oracle.scheme import all_cells
+from oracle.weno import reconstruct as oracle_reconstruct
+from paper_1212_3585_amd import workloads as wl
+
+from gpu_helpers import (from_device, gpu_qh_to_oracle_layout, make_pair,
+                         oracle_wh_to_gpu_layout, rel_l1, rel_l1_per_var, say,
+                         to_device)
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+def _kh(n, seed=1, amp=0.01):
+    return wl.kelvin_helmholtz(n, seed=seed, amp=amp)
+
+
+def _euler_random(shape, seed, dim):
+    return wl.perturbed_smooth_euler(tuple(shape), seed)
+
+
+# ------------------------------------------------------------ constants
+@pytest.mark.parametrize("M", [0, 1, 2, 3])
+def test_constants_match_oracle(ader, M):
+    from oracle.basis import basis
+    op, gp = make_pair(ader, 2, M, (4, 4), (0, 0), (1, 1))
+    c = ader.Solver(gp).constants()
+    b = basis(M)
+    np.testing.assert_allclose(c["nodes"], b.nodes, rtol=0, atol=2e-16)
+    np.testing.assert_allclose(c["weights"], b.weights, rtol=0, atol=2e-16)
+    np.testing.assert_allclose(c["dmat"], b.dmat, rtol=0, atol=1e-13)
+    A = np.linalg.solve(b.time_matrix(), np.diag(b.weights))
+    np.testing.assert_allclose(c["time_inv_w"], A, rtol=0, atol=1e-14)
+
+
+# ------------------------------------------------------------ time step
+@pytest.mark.parametrize("dim,n", [(2, (37, 29)), (3, (9, 7, 6))])
+def test_cfl_time_step(ader, dim, n):
+    say(f"dt parity dim={dim} n={n}")
+    U = _euler_random(n, 3, dim)
+    op, gp = make_pair(ader, dim, 2, n, (0,) * dim, (1.0, 2.0, 0.5)[:dim])
+    s = ader.Solver(gp)
+    dt = s.compute_dt(to_device(U), 0.0, 1e9).item()
+    assert abs(dt - oracle.cfl_dt(op, U)) <= 1e-15 * dt
+    dt2 = s.compute_dt(to_device(U), 0.7, 0.7 + 1e-5).item()
+    assert dt2 == pytest.approx(1e-5, rel=1e-9)
+
+
+# ------------------------------------------------------------ reconstruction
+@pytest.mark.parametrize("dim,M,n,bc", [
+    (2, 1, (13, 11), "periodic"), (2, 2, (17, 9), "transmissive"),
+    (2, 3, (19, 23), "periodic"), (2, 0, (5, 6), "periodic"),
+    (3, 1, (6, 5, 7), "transmissive"), (3, 2, (7, 6, 5), "periodic"),
+    (3, 3, (5, 7, 6), "periodic")])
+def test_reconstruction_parity(ader, dim, M, n, bc):
+    say(f"reconstruct dim={dim} M={M} n={n} bc={bc}")
+    U = _euler_random(n, 10 + M, dim)
+    op, gp = make_pair(ader, dim, M, n, (0,) * dim, (1,) * dim, bc)
+    s = ader.Solver(gp)
+    wh = s.reconstruct(to_device(U)).cpu().numpy()
+    w = oracle_reconstruct(U, all_cells(op), M, op.bc[:dim])
+    ref = oracle_wh_to_gpu_layout(w, dim)
+    # the nonlinear weights (exponent 8) make w_h sensitive to rounding: the
+    # oracle itself moves by up to ~2e-12 under 1-ulp input perturbations
+    np.testing.assert_allclose(wh, ref, rtol=0, atol=2e-11 * np.abs(ref).max())
+    assert np.abs(wh - ref).sum() / np.abs(ref).sum() <= 1e-13
+
+
+# ------------------------------------------------------------ predictor
+@pytest.mark.parametrize("dim,M,system,ncells", [
+    (2, 1, "euler", 301), (2, 2, "euler", 333), (2, 3, "euler", 257),
+    (3, 1, "euler", 70), (3, 2, "euler", 95), (3, 3, "euler", 9),
+    (2, 3, "linadv", 100), (3, 2, "linadv", 40), (2, 0, "euler", 17)])
+def test_predictor_parity(ader, dim, M, system, ncells):
+    say(f"predict dim={dim} M={M} {system} ncells={ncells}")
+    import torch
+    side = 8 if dim == 2 else 6
+    n = (side,) * dim
+    U = _euler_random(n, 20 + M, dim) if system == "euler" else \
+        wl.random_field((1,) + n, 21)
+    op, gp = make_pair(ader, dim, M, n, (0,) * dim, (1,) * dim, system=system)
+    cells = all_cells(op)
+    reps = (ncells + len(cells) - 1) // len(cells)
+    cells = np.concatenate([cells] * reps)[:ncells]
+    w = oracle_reconstruct(U, cells, M, op.bc[:dim])
+    dt = 0.9 * oracle.cfl_dt(op, U)
+    cour = [dt / h for h in op.dx]
+    q, it, ok = oracle_predict(op.system, w, cour, M, dim, op.tol, op.max_iter)
+    assert ok.all()
+    s = ader.Solver(gp)
+    s.clear_status()
+    whd = torch.tensor(oracle_wh_to_gpu_layout(w, dim), device="cuda")
+    dtd = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    qh = s.predict(whd, ncells, dt=dtd).cpu().numpy()
+    nst = (M + 1) ** (dim + 1)
+    got = gpu_qh_to_oracle_layout(qh[: ncells * op.system.nv * nst], op.system.nv, ncells, nst)
+    np.testing.assert_allclose(got, q, rtol=0, atol=1e-12 * max(1.0, np.abs(q).max()))
+    flags, iters = s.read_status()
+    assert flags == 0
+    # per-cell stopping rule as the oracle: total iterations agree closely
+    assert abs(iters - int(it.sum())) <= max(2, 0.02 * it.sum())
+
+
+# ------------------------------------------------------------ full step
+@pytest.mark.parametrize("dim,M,n,bc,system", [
+    (2, 2, (20, 20), "periodic", "euler"),
+    (2, 3, (37, 29), "periodic", "euler"),
+    (2, 1, (33, 17), "transmissive", "euler"),
+    (2, 3, (24, 13), "transmissive", "linadv"),
+    (2, 0, (16, 16), "periodic", "euler"),
+    (3, 2, (9, 8, 7), "transmissive", "euler"),
+    (3, 1, (8, 6, 5), "periodic", "euler"),
+    (3, 3, (6, 5, 7), "periodic", "euler")])
+def test_step_parity(ader, dim, M, n, bc, system):
+    say(f"step dim={dim} M={M} n={n} bc={bc} {system}")
+    if system == "euler":
+        U = _euler_random(n, 30 + M, dim)
+    else:
+        U = wl.random_field((1,) + n, 31)
+    hi = (1.0, 1.5, 0.75)[:dim]
+    op, gp = make_pair(ader, dim, M, n, (0,) * dim, hi, bc, system=system)
+    s = ader.Solver(gp)
+    s.clear_status()
+    u = to_device(U, ld=((op.ncells + 63) // 64) * 64)
+    out = s.empty_state(u.shape[1])
+    Uo = U
+    for k in range(3):
+        dt = oracle.cfl_dt(op, Uo)
+        Uo, _ = oracle.step(op, Uo, dt)
+        s.compute_dt(u, 0.0, 1e9)
+        assert abs(s.dt.item() - dt) <= 1e-13 * dt
+        s.step(u, out)
+        u, out = out, u
+    got = from_device(u, n)
+    assert rel_l1(got, Uo) <= TOL, (rel_l1(got, Uo), rel_l1_per_var(got, Uo))
+    flags, _ = s.read_status()
+    assert flags == 0
+
+
+def test_isentropic_vortex_to_t1(ader):
+    """20x20 vortex, M = 2, CFL 0.9, to t = 1 (the small configuration)."""
+    say("vortex 20x20 M=2 to t=1")
+    N = 20
+    U0 = wl.isentropic_vortex(N)
+    op, gp = make_pair(ader, 2, 2, (N, N), (0, 0), (10, 10))
+    Uo, t, ns, dts = oracle.run(op, U0, 1.0)
+    s = ader.Solver(gp)
+    u, tg, ng = s.run(to_device(U0), 1.0)
+    assert ng == ns and abs(tg - 1.0) < 1e-14
+    got = from_device(u, (N, N))
+    assert rel_l1(got, Uo) <= TOL, rel_l1(got, Uo)
+    exact = wl.isentropic_vortex(N, t=1.0)
+    assert np.abs(got[0] - exact[0]).mean() < 5e-3
+
+
+def test_kelvin_helmholtz_ten_steps(ader):
+    """KH shear layer, M = 3: ten steps on 64^2 against the full oracle."""
+    say("KH 64x64 M=3 10 steps")
+    N = 64
+    U0 = _kh(N)
+    op, gp = make_pair(ader, 2, 3, (N, N), (0, 0), (1, 1))
+    Uo, *_ = oracle.run(op, U0, 1.0, max_steps=10)
+    s = ader.Solver(gp)
+    u, *_ = s.run(to_device(U0), 1.0, max_steps=10)
+    got = from_device(u, (N, N))
+    print("KH 64^2 10 steps: pooled", rel_l1(got, Uo), "per variable",
+          rel_l1_per_var(got, Uo))
+    assert rel_l1(got, Uo) <= TOL, (rel_l1(got, Uo), rel_l1_per_var(got, Uo))
+
+
+def test_kelvin_helmholtz_512_sampled(ader):
+    """Full-size KH (512^2, M = 3): one step, sampled cells against the oracle."""
+    say("KH 512x512 M=3 sampled")
+    N = 512
+    U0 = _kh(N)
+    op, gp = make_pair(ader, 2, 3, (N, N), (0, 0), (1, 1))
+    s = ader.Solver(gp)
+    u = to_device(U0)
+    out = s.empty_state()
+    s.compute_dt(u)
+    s.step(u, out)
+    got = from_device(out, (N, N))
+    dt = oracle.cfl_dt(op, U0)
+    assert abs(s.dt.item() - dt) <= 1e-13 * dt
+    rng = np.random.default_rng(5)
+    cells = np.concatenate([rng.integers(0, N, size=(200, 2)),
+                            [[0, 0], [N - 1, N - 1], [0, N - 1], [N - 1, 0], [N // 2, N // 4]]])
+    ref, _ = oracle.step_cells(op, U0, dt, cells)
+    g = got[:, cells[:, 0], cells[:, 1]]
+    assert rel_l1(g, ref) <= TOL
+
+
+@pytest.mark.parametrize("dim,M,n", [(2, 3, (48, 40)), (3, 2, (10, 9, 8))])
+def test_mixed_precision_error_is_stated(ader, dim, M, n):
+    say(f"mixed precision dim={dim} M={M} n={n}")
+    U = _euler_random(n, 40 + M, dim)
+    op, gp = make_pair(ader, dim, M, n, (0,) * dim, (1,) * dim, precision=1, tol=1e-6)
+    op64, _ = make_pair(ader, dim, M, n, (0,) * dim, (1,) * dim)
+    Uo, *_ = oracle.run(op64, U, 1.0, max_steps=3)
+    s = ader.Solver(gp)
+    u, *_ = s.run(to_device(U), 1.0, max_steps=3)
+    err = rel_l1(from_device(u, n), Uo)
+    print(f"fp32-predictor relative L1 vs fp64 oracle after 3 steps: {err:.3e}")
+    assert err < 1e-5
+
+
+def test_conservation_on_device(ader):
+    say("conservation KH 96x80 M=3")
+    U = _kh(96)[:, :, :80]
+    op, gp = make_pair(ader, 2, 3, (96, 80), (0, 0), (1, 1))
+    s = ader.Solver(gp)
+    u, *_ = s.run(to_device(U), 10.0, max_steps=5)
+    got = from_device(u, (96, 80))
+    rel = np.abs(got.sum(axis=(1, 2)) - U.sum(axis=(1, 2))) / np.abs(U).sum(axis=(1, 2))
+    assert rel.max() < 1e-12
+
+
+def test_determinism(ader):
+    say("determinism KH 128x128 M=3 x2")
+    U = _kh(128)
+    _, gp = make_pair(ader, 2, 3, (128, 128), (0, 0), (1, 1))
+    outs = []
+    for _ in range(2):
+        s = ader.Solver(gp)
+        u, *_ = s.run(to_device(U), 1.0, max_steps=3)
+        outs.append(u.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+# ------------------------------------------------------------ device flags
+def test_nonphysical_state_is_flagged(ader):
+    say("flag: negative density")
+    U = _euler_random((16, 16), 50, 2)
+    U[0, 5, 5] = -0.1
+    _, gp = make_pair(ader, 2, 2, (16, 16), (0, 0), (1, 1))
+    s = ader.Solver(gp)
+    u = to_device(U)
+    out = s.empty_state()
+    import torch
+    s.dt.copy_(torch.tensor([1e-4], dtype=torch.float64))
+    s.step(u, out)
+    flags, _ = s.read_status()
+    assert flags & ader.FLAG_NONPHYSICAL
+
+
+def test_picard_cap_is_flagged(ader):
+    say("flag: picard cap")
+    U = _euler_random((16, 16), 51, 2)
+    _, gp = make_pair(ader, 2, 2, (16, 16), (0, 0), (1, 1), maxit=1)
+    s = ader.Solver(gp)
+    u = to_device(U)
+    s.compute_dt(u)
+    s.step(u, s.empty_state())
+    flags, _ = s.read_status()
+    assert flags & ader.FLAG_NOCONV
+    s.clear_status()
+    assert s.read_status()[0] == 0
