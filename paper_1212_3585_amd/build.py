@@ -30,6 +30,8 @@ def hipcc() -> str:
 def compile_flags() -> list[str]:
     return [f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # keep matrix-core results in ordinary VGPRs (no AGPR copies)
+            "-mllvm", "-amdgpu-mfma-vgpr-form",
             "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 
 

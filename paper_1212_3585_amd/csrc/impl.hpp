@@ -1,7 +1,10 @@
 // Templated launcher set for one (dim, M, system, predictor precision).
 #pragma once
 
+#include <type_traits>
+
 #include "plan.hpp"
+#include "predict_mfma.hpp"
 
 namespace ader {
 
@@ -78,8 +81,15 @@ struct Impl final : ImplBase {
     WsHeader* hdr = reinterpret_cast<WsHeader*>(ws);
     MeshParams mp = p.mp;
     StageTimer timer(&p.prof, ADER_STAGE_PREDICT, st);
-    hipLaunchKernelGGL((k_predict<DIM, M, SYS, R, OUT>), dim3(blocks_for(ncells, CPB)),
-                       dim3(kBlock), 0, st, wh, qh, ncells, dt, mp, p.dc, hdr);
+    if constexpr (DIM == 2 && std::is_same<R, double>::value) {
+      // fp64 matrix cores: 4 cells per wavefront, 16 per block
+      hipLaunchKernelGGL((k_predict_mfma2d<M, SYS, OUT>),
+                         dim3(blocks_for(ncells, 4 * (kBlock / 64))), dim3(kBlock), 0, st, wh,
+                         qh, ncells, dt, mp, p.dc, hdr);
+    } else {
+      hipLaunchKernelGGL((k_predict<DIM, M, SYS, R, OUT>), dim3(blocks_for(ncells, CPB)),
+                         dim3(kBlock), 0, st, wh, qh, ncells, dt, mp, p.dc, hdr);
+    }
     return hipGetLastError();
   }
 

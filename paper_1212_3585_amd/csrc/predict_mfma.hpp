@@ -1,0 +1,148 @@
+// Space-time predictor for 2D problems on the fp64 matrix cores (gfx950).
+//
+// v_mfma_f64_4x4x4f64 multiplies four independent 4x4 blocks.  Writing a
+// lane as (b0, b1, b2) = (lane & 3, (lane >> 2) & 3, lane >> 4), it reads
+// A[b1][i = b0][k = b2] and B[b1][k = b2][j = b0] and returns
+// D[b1][i = b2][j = b0]: the contraction always runs over b2.
+//
+// Layout: a wavefront holds four cells (b1).  Lane (b0, b1, b2) owns the
+// spatial node p_x = b2, p_y = b0 of cell b1 and keeps, in registers, all
+// conserved variables at all n time nodes of that node.  One Picard sweep of
+// eq. stdg.final, with the tensor structure used dimension by dimension:
+//   * nodal fluxes f*, g* at the lane's n space-time nodes (lane-local);
+//   * x derivative: data as operand B against (dt/dx) D in operand A
+//     (contracts p_x on b2, result stays in the home layout);
+//   * y derivative: a transpose (data as operand A against the identity)
+//     moves p_y to b2, then data as operand A against (dt/dy) D^T contracts
+//     p_y and returns the home layout, accumulated onto the x part;
+//   * time product with (time factor of K^1)^-1 diag(w) and the update
+//     q = w_hat - ... are lane-local.
+// A cell stops counting iterations when its relative update falls below the
+// tolerance; the wavefront sweeps until its last cell has converged.
+// Degrees M < 3 pad the node axes to four with zero matrix entries and a
+// benign state in the padding lanes.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace ader {
+
+template <int n>
+__device__ __forceinline__ double pick_entry(const double (&m)[4][4], int i, int k) {
+  double r = 0.0;
+#pragma unroll
+  for (int a = 0; a < n; ++a)
+#pragma unroll
+    for (int b = 0; b < n; ++b) r = (i == a && k == b) ? m[a][b] : r;
+  return r;
+}
+
+__device__ __forceinline__ double cell_max(double x) {
+  // maximum over the 16 lanes of one cell: b0 (xor 1, 2) and b2 (xor 16, 32)
+  x = fmax(x, __shfl_xor(x, 1, 64));
+  x = fmax(x, __shfl_xor(x, 2, 64));
+  x = fmax(x, __shfl_xor(x, 16, 64));
+  x = fmax(x, __shfl_xor(x, 32, 64));
+  return x;
+}
+
+template <int M, int SYS, typename OUT>
+__global__ void __launch_bounds__(kBlock)
+k_predict_mfma2d(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
+                 const double* __restrict__ dt_dev, MeshParams mp, DevConsts c,
+                 WsHeader* hdr) {
+  constexpr int DIM = 2;
+  constexpr int n = M + 1;
+  constexpr int NS = n * n;
+  constexpr int NST = NS * n;
+  constexpr int NV = NVars<SYS, DIM>::v;
+  static_assert(n <= 4, "four-point blocks");
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int b0 = lane & 3, b1 = (lane >> 2) & 3, b2 = lane >> 4;
+  const int64_t cell = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * 4 + b1;
+  const bool cell_ok = cell < ncells;
+  const bool node_ok = b0 < n && b2 < n;
+  const bool active = cell_ok && node_ok;
+  const int a = b2 + n * b0;  // spatial node index p_x + n p_y
+
+  const double dt = *dt_dev;
+  const double dval = pick_entry<n>(c.dmat, b0, b2);
+  const double mx = (dt / mp.dx[0]) * dval;   // operand A: D[i=b0][k=b2]
+  const double my = (dt / mp.dx[1]) * dval;   // operand B: D^T[k=b2][j=b0]
+  const double idv = (b0 == b2) ? 1.0 : 0.0;  // operand B: identity
+  const double gamma = mp.gamma;
+  const double adv[3] = {mp.adv[0], mp.adv[1], mp.adv[2]};
+
+  double w[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+    w[v] = active ? wh[(cell * NV + v) * NS + a] : (v == 0 || v == NV - 1 ? 1.0 : 0.0);
+  double q[NV][n];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int s = 0; s < n; ++s) q[v][s] = w[v];
+
+  const double tol = mp.tol;
+  bool done = !cell_ok;
+  int iters = 0;
+  for (int it = 1; it <= mp.maxit; ++it) {
+    double R[NV][n];
+#pragma unroll
+    for (int s = 0; s < n; ++s) {
+      double qs[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) qs[v] = q[v][s];
+      double F[DIM][NV];
+      phys_fluxes<SYS, DIM, double>(qs, gamma, adv, F);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double rx = __builtin_amdgcn_mfma_f64_4x4x4f64(mx, F[0][v], 0.0, 0, 0, 0);
+        const double gt = __builtin_amdgcn_mfma_f64_4x4x4f64(F[1][v], idv, 0.0, 0, 0, 0);
+        R[v][s] = __builtin_amdgcn_mfma_f64_4x4x4f64(gt, my, rx, 0, 0, 0);
+      }
+    }
+    double delta = 0.0, mag = 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+      for (int s = 0; s < n; ++s) {
+        double acc = 0.0;
+#pragma unroll
+        for (int sp = 0; sp < n; ++sp) acc += c.tinvw[s][sp] * R[v][sp];
+        const double qn = w[v] - acc;
+        delta = fmax(delta, fabs(qn - q[v][s]));
+        mag = fmax(mag, fabs(qn));
+        // a cell that has converged keeps sweeping with its wavefront: each
+        // further sweep moves q by less than the tolerance towards the fixed
+        // point (its iteration count is the one at first convergence)
+        q[v][s] = qn;
+      }
+    }
+    // padding lanes hold a constant state: their delta is zero
+    delta = cell_max(node_ok ? delta : 0.0);
+    mag = cell_max(node_ok ? mag : 0.0);
+    if (!done && delta <= tol * fmax(1.0, mag)) {
+      done = true;
+      iters = it;
+    }
+    if (!__any(!done)) break;
+  }
+  if (cell_ok) {
+    if (!done) {
+      iters = mp.maxit;
+      if (lane == 4 * b1) atomicOr(&hdr->status, kFlagNoConv);
+    }
+    if (lane == 4 * b1) atomicAdd(&hdr->iters, (unsigned long long)iters);
+  }
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int s = 0; s < n; ++s) qh[(cell * NV + v) * NST + a + NS * s] = (OUT)q[v][s];
+  }
+}
+
+}  // namespace ader
