@@ -1,0 +1,429 @@
+// Fused 2D step: a cell kernel (WENO + predictor + face traces) and a face
+// kernel (Rusanov fluxes + Gauss sums + update).  R is the predictor
+// precision: double (derivative products on the fp64 matrix cores) or float
+// (fp32 FMAs on shuffled values, fp32 accumulation).
+//
+// k_cell2d   one block = a 4 x TY tile of cells, TY wavefronts; wavefront w
+//            holds the tile's row w, one cell per matrix block b1.
+//   1. the averages of the tile plus M ghost layers are staged in LDS
+//      (periodic or zero-gradient ghosts);
+//   2. WENO x pass (Section 2.2, eqs. rec.x, sigmas, omegas, weno) on every
+//      row of the tile and M rows above and below, into LDS;
+//   3. WENO y pass per x degree of freedom (eqs. rec.y, weno.y) -> w_h in LDS;
+//   4. Picard iteration of the space-time predictor on the matrix cores, as
+//      in predict_mfma.hpp (Section 2.3, eq. stdg.final);
+//   5. predictor traces on the four faces at the face Gauss points in space
+//      and time (used by eqs. flux:F, flux:G): contraction with psi(0) and
+//      psi(1) along x by one MFMA, along y by a transpose and one MFMA.
+//   Traces go to HBM as trace[face][cell][v][s][b] (b: transverse node,
+//   s: time node), face = x-low, x-high, y-low, y-high.
+//
+// k_face2d   one block = a 16 x 4 tile of cells; one 16-lane group per face,
+//            one lane per space-time Gauss point of the face: Rusanov flux
+//            (eq. rusanov) between the two traces, weighted by the Gauss
+//            weights and summed over the group (eqs. flux:F, flux:G); then the
+//            conservative update of the tile's cells (eq. finite_vol).  A face
+//            on a tile edge is computed by both tiles with the same code and
+//            the same operands, hence bitwise the same flux: the update stays
+//            exactly conservative.
+#pragma once
+
+#include <type_traits>
+
+#include "predict_mfma.hpp"
+
+namespace ader {
+
+constexpr int kCellTX = 4;  // tile width of the cell kernel = cells per wavefront
+
+template <typename R>
+__device__ __forceinline__ R cell_max_r(R x) {
+  x = fmax(x, __shfl_xor(x, 1, 64));
+  x = fmax(x, __shfl_xor(x, 2, 64));
+  x = fmax(x, __shfl_xor(x, 16, 64));
+  x = fmax(x, __shfl_xor(x, 32, 64));
+  return x;
+}
+
+// Lane-local coefficients of the shuffle form (fp32 predictor): the node
+// p ^ m of the same line is fetched with a xor shuffle; coef[m] = D[p][p ^ m]
+// (zero where p ^ m is a padding node).
+template <int n>
+__device__ __forceinline__ void xor_row(const DevConsts& c, int p, double scale, float (&coef)[4]) {
+#pragma unroll
+  for (int m = 0; m < 4; ++m) coef[m] = (float)(scale * pick_entry<n>(c.dmat, p, p ^ m));
+}
+
+template <typename R>
+__device__ __forceinline__ R xor_line(R x, const R (&coef)[4], int stride) {
+  // sum_m coef[m] * x(lane ^ (m * stride)) in the order m = 0, 1, 2, 3
+  R acc = coef[0] * x;
+  acc = fma(coef[1], __shfl_xor(x, stride, 64), acc);
+  acc = fma(coef[2], __shfl_xor(x, 2 * stride, 64), acc);
+  acc = fma(coef[3], __shfl_xor(x, 3 * stride, 64), acc);
+  return acc;
+}
+
+template <int M, int SYS, int TY, typename R>
+__global__ void __launch_bounds__(64 * TY)
+k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
+         const double* __restrict__ dt_dev, MeshParams mp, DevConsts c, WsHeader* hdr) {
+  constexpr int DIM = 2;
+  constexpr int n = M + 1;
+  constexpr int NS = n * n;
+  constexpr int NV = NVars<SYS, DIM>::v;
+  constexpr int TX = kCellTX;
+  constexpr int RX = TX + 2 * M;   // staged columns
+  constexpr int RY = TY + 2 * M;   // staged rows
+  constexpr int NT = 64 * TY;      // threads
+  __shared__ double sU[NV * RY * RX];
+  __shared__ double sWx[NV * RY * TX * n];
+  __shared__ double sWh[TX * TY * NV * NS];
+
+  const int tid = threadIdx.x;
+  const int x0 = blockIdx.x * TX;
+  const int y0 = blockIdx.y * TY;
+  const int nx = mp.n[0], ny = mp.n[1];
+
+  // 1. stage the averages (tile + M ghost layers)
+  for (int e = tid; e < NV * RY * RX; e += NT) {
+    const int rx = e % RX;
+    const int ry = (e / RX) % RY;
+    const int v = e / (RX * RY);
+    const int gi = bc_map(x0 + rx - M, nx, mp.bc[0]);
+    const int gj = bc_map(y0 + ry - M, ny, mp.bc[1]);
+    sU[e] = u[(int64_t)v * ld + gi + (int64_t)nx * gj];
+  }
+  __syncthreads();
+  // 2. x pass: one thread per (variable, staged row, tile column)
+  for (int e = tid; e < NV * RY * TX; e += NT) {
+    const int cx = e % TX;
+    const int ry = (e / TX) % RY;
+    const int v = e / (TX * RY);
+    double vals[2 * M + 1];
+#pragma unroll
+    for (int o = 0; o < 2 * M + 1; ++o) vals[o] = sU[(v * RY + ry) * RX + cx + o];
+    double w[n];
+    weno_line<M>(vals, c, w);
+#pragma unroll
+    for (int p = 0; p < n; ++p) sWx[((v * RY + ry) * TX + cx) * n + p] = w[p];
+  }
+  __syncthreads();
+  // 3. y pass: one thread per (tile cell, variable, x node)
+  for (int e = tid; e < TX * TY * NV * n; e += NT) {
+    const int px = e % n;
+    const int v = (e / n) % NV;
+    const int cl = e / (n * NV);  // tile cell: cx + TX cy
+    const int cx = cl % TX, cy = cl / TX;
+    double vals[2 * M + 1];
+#pragma unroll
+    for (int o = 0; o < 2 * M + 1; ++o) vals[o] = sWx[((v * RY + cy + o) * TX + cx) * n + px];
+    double w[n];
+    weno_line<M>(vals, c, w);
+#pragma unroll
+    for (int p = 0; p < n; ++p) sWh[(cl * NV + v) * NS + px + n * p] = w[p];
+  }
+  __syncthreads();
+
+  // 4. predictor: wavefront = tile row, b1 = tile column.  fp64: the
+  //    derivative products on the matrix cores; fp32: fp32 FMAs on values
+  //    fetched by xor shuffles (p_x across b2, p_y across b0)
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int b0 = lane & 3, b1 = (lane >> 2) & 3, b2 = lane >> 4;
+  const int gi = x0 + b1, gj = y0 + wave;
+  const bool cell_ok = gi < nx && gj < ny;
+  const bool node_ok = b0 < n && b2 < n;
+  const int64_t cell = gi + (int64_t)nx * gj;
+  const int cl = b1 + TX * wave;
+
+  constexpr bool kMatrix = std::is_same<R, double>::value;
+  const double dt = *dt_dev;
+  const double dval = pick_entry<n>(c.dmat, b0, b2);
+  const double mx = (dt / mp.dx[0]) * dval;
+  const double my = (dt / mp.dx[1]) * dval;
+  const double idv = (b0 == b2) ? 1.0 : 0.0;
+  float cxm[4], cym[4];
+  xor_row<n>(c, b2, dt / mp.dx[0], cxm);
+  xor_row<n>(c, b0, dt / mp.dx[1], cym);
+  const R gamma = (R)mp.gamma;
+  const R adv[3] = {(R)mp.adv[0], (R)mp.adv[1], (R)mp.adv[2]};
+
+  R w[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+    w[v] = node_ok ? (R)sWh[(cl * NV + v) * NS + b2 + n * b0] : (v == 0 || v == NV - 1 ? R(1) : R(0));
+  R q[NV][n];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int s = 0; s < n; ++s) q[v][s] = w[v];
+
+  const R tol = (R)mp.tol;
+  bool done = !cell_ok;
+  int iters = 0;
+  for (int it = 1; it <= mp.maxit; ++it) {
+    R Rs[NV][n];
+#pragma unroll
+    for (int s = 0; s < n; ++s) {
+      R qs[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) qs[v] = q[v][s];
+      R F[DIM][NV];
+      phys_fluxes<SYS, DIM, R>(qs, gamma, adv, F);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        if constexpr (kMatrix) {
+          const double rx = __builtin_amdgcn_mfma_f64_4x4x4f64(mx, F[0][v], 0.0, 0, 0, 0);
+          const double gt = __builtin_amdgcn_mfma_f64_4x4x4f64(F[1][v], idv, 0.0, 0, 0, 0);
+          Rs[v][s] = __builtin_amdgcn_mfma_f64_4x4x4f64(gt, my, rx, 0, 0, 0);
+        } else {
+          Rs[v][s] = xor_line<R>(F[0][v], cxm, 16) + xor_line<R>(F[1][v], cym, 1);
+        }
+      }
+    }
+    R delta = R(0), mag = R(0);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+      for (int s = 0; s < n; ++s) {
+        R acc = R(0);
+#pragma unroll
+        for (int sp = 0; sp < n; ++sp)
+          acc += cget<R>(c.tinvw[s][sp], c.tinvw_f[s][sp]) * Rs[v][sp];
+        const R qn = w[v] - acc;
+        delta = fmax(delta, fabs(qn - q[v][s]));
+        mag = fmax(mag, fabs(qn));
+        q[v][s] = qn;
+      }
+    }
+    delta = cell_max_r<R>(node_ok ? delta : R(0));
+    mag = cell_max_r<R>(node_ok ? mag : R(0));
+    if (!done && delta <= tol * fmax(R(1), mag)) {
+      done = true;
+      iters = it;
+    }
+    if (!__any(!done)) break;
+  }
+  if (cell_ok) {
+    if (!done) {
+      iters = mp.maxit;
+      if (lane == 4 * b1) atomicOr(&hdr->status, kFlagNoConv);
+    }
+    if (lane == 4 * b1) atomicAdd(&hdr->iters, (unsigned long long)iters);
+  }
+
+  // 5. face traces.  x faces: operand A row 0 = psi(0), row 1 = psi(1)
+  //    (A[i=b0][k=b2]); result lane (b0 = y node, b2 = 0 / 1 = low / high).
+  //    y faces: transpose, then operand B column 0 = psi(0), column 1 = psi(1)
+  //    (B[k=b2][j=b0]); result lane (b0 = 0 / 1 = low / high, b2 = x node).
+  //    fp32: each lane forms, by shuffles, the four traces at its own
+  //    transverse node; lanes b2 = 0 write the x faces, lanes b0 = 0 the y
+  //    faces.
+  const int64_t C = mp.ncells;
+  constexpr int TRC = NV * n * n;  // values per trace
+  if constexpr (kMatrix) {
+    double ex = 0.0;
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+      const double p0 = c.psi0[k], p1 = c.psi1[k];
+      ex = (b2 == k) ? (b0 == 0 ? p0 : (b0 == 1 ? p1 : 0.0)) : ex;
+    }
+    const double ey = ex;  // same lane pattern: B[k=b2][j=b0] = psi_k(j)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+      for (int s = 0; s < n; ++s) {
+        const double tx = __builtin_amdgcn_mfma_f64_4x4x4f64(ex, q[v][s], 0.0, 0, 0, 0);
+        const double qt = __builtin_amdgcn_mfma_f64_4x4x4f64(q[v][s], idv, 0.0, 0, 0, 0);
+        const double ty = __builtin_amdgcn_mfma_f64_4x4x4f64(qt, ey, 0.0, 0, 0, 0);
+        if (cell_ok) {
+          if (b2 < 2 && b0 < n)  // x face b2 (0 low, 1 high), transverse node b0
+            traces[((int64_t)b2 * C + cell) * TRC + (v * n + s) * n + b0] = tx;
+          if (b0 < 2 && b2 < n)  // y face b0, transverse node b2
+            traces[((int64_t)(2 + b0) * C + cell) * TRC + (v * n + s) * n + b2] = ty;
+        }
+      }
+    }
+  } else {
+    float e0x[4], e1x[4], e0y[4], e1y[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      float a0 = 0.f, a1 = 0.f, c0 = 0.f, c1 = 0.f;
+#pragma unroll
+      for (int k = 0; k < n; ++k) {
+        a0 = ((b2 ^ m) == k) ? c.psi0_f[k] : a0;
+        a1 = ((b2 ^ m) == k) ? c.psi1_f[k] : a1;
+        c0 = ((b0 ^ m) == k) ? c.psi0_f[k] : c0;
+        c1 = ((b0 ^ m) == k) ? c.psi1_f[k] : c1;
+      }
+      e0x[m] = a0;
+      e1x[m] = a1;
+      e0y[m] = c0;
+      e1y[m] = c1;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+      for (int s = 0; s < n; ++s) {
+        const R x = q[v][s];
+        const R tx0 = xor_line<R>(x, e0x, 16), tx1 = xor_line<R>(x, e1x, 16);
+        const R ty0 = xor_line<R>(x, e0y, 1), ty1 = xor_line<R>(x, e1y, 1);
+        if (cell_ok) {
+          if (b2 == 0 && b0 < n) {
+            traces[((int64_t)0 * C + cell) * TRC + (v * n + s) * n + b0] = tx0;
+            traces[((int64_t)1 * C + cell) * TRC + (v * n + s) * n + b0] = tx1;
+          }
+          if (b0 == 0 && b2 < n) {
+            traces[((int64_t)2 * C + cell) * TRC + (v * n + s) * n + b2] = ty0;
+            traces[((int64_t)3 * C + cell) * TRC + (v * n + s) * n + b2] = ty1;
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int M, int SYS>
+__device__ __forceinline__ void rusanov_point(const double (&qL)[NVars<SYS, 2>::v],
+                                              const double (&qR)[NVars<SYS, 2>::v], int k,
+                                              const MeshParams& mp,
+                                              double (&F)[NVars<SYS, 2>::v]) {
+  constexpr int NV = NVars<SYS, 2>::v;
+  const double adv[3] = {mp.adv[0], mp.adv[1], mp.adv[2]};
+  double fL[NV], fR[NV], sL, sR;
+  phys_flux_dir<SYS, 2>(qL, k, mp.gamma, adv, fL, sL);
+  phys_flux_dir<SYS, 2>(qR, k, mp.gamma, adv, fR, sR);
+  const double smax = fmax(sL, sR);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) F[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * smax * (qR[v] - qL[v]);
+}
+
+constexpr int kFaceTX = 16, kFaceTY = 4;
+
+template <int M, int SYS, typename TR>
+__global__ void __launch_bounds__(kBlock)
+k_face2d(const TR* __restrict__ traces, const double* __restrict__ u_in,
+         double* __restrict__ u_out, int64_t ld, const double* __restrict__ dt_dev,
+         MeshParams mp, DevConsts c, WsHeader* hdr) {
+  constexpr int DIM = 2;
+  constexpr int n = M + 1;
+  constexpr int NV = NVars<SYS, DIM>::v;
+  constexpr int TRC = NV * n * n;
+  constexpr int TX = kFaceTX, TY = kFaceTY;
+  constexpr int NFX = (TX + 1) * TY;  // x faces of the tile
+  constexpr int NFY = TX * (TY + 1);  // y faces of the tile
+  constexpr int NF = NFX + NFY;
+  constexpr int GROUPS = kBlock / 16;
+  __shared__ double sF[NF * NV];
+
+  const int tid = threadIdx.x;
+  const int grp = tid >> 4;
+  const int l = tid & 15;  // Gauss point l = b + n s of the face
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  const int nx = mp.n[0], ny = mp.n[1];
+  const int64_t C = mp.ncells;
+  const bool point_ok = l < n * n;
+  const int b = point_ok ? l % n : 0;
+  const int s = point_ok ? l / n : 0;
+  const double wts = point_ok ? c.w[b] * c.w[s] : 0.0;
+
+  // the same trip count for every group keeps the shuffles below uniform
+  for (int base = 0; base < NF; base += GROUPS) {
+    const int f = base + grp;
+    const bool f_in = f < NF;
+    int k, fi, fj;  // axis, face index (i along x, j along y)
+    if (f < NFX) {
+      k = 0;
+      fi = x0 + f % (TX + 1);
+      fj = y0 + f / (TX + 1);
+    } else {
+      k = 1;
+      fi = x0 + (f - NFX) % TX;
+      fj = y0 + (f - NFX) / TX;
+    }
+    const int nk = k == 0 ? nx : ny;
+    const int ik = k == 0 ? fi : fj;       // index along the axis: separates ik-1 | ik
+    const bool face_ok = f_in && fi <= nx && fj <= ny && (k == 0 ? fj < ny : fi < nx);
+    double Fp[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fp[v] = 0.0;
+    if (face_ok && point_ok) {
+      const bool outL = ik - 1 < 0, outR = ik >= nk;
+      const int iL = bc_map(ik - 1, nk, mp.bc[k]), iR = bc_map(ik, nk, mp.bc[k]);
+      const int64_t cL = k == 0 ? iL + (int64_t)nx * fj : fi + (int64_t)nx * iL;
+      const int64_t cR = k == 0 ? iR + (int64_t)nx * fj : fi + (int64_t)nx * iR;
+      // high-side trace of the left cell, low-side trace of the right cell
+      const TR* tL = traces + ((int64_t)(2 * k + 1) * C + cL) * TRC;
+      const TR* tR = traces + ((int64_t)(2 * k) * C + cR) * TRC;
+      double qL[NV], qR[NV];  // traces in the predictor precision, flux in fp64
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        qL[v] = (double)tL[(v * n + s) * n + b];
+        qR[v] = (double)tR[(v * n + s) * n + b];
+      }
+      if (mp.bc[k] != 0) {
+        if (outL) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) qL[v] = qR[v];
+        }
+        if (outR) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) qR[v] = qL[v];
+        }
+      }
+      double Fpt[NV];
+      rusanov_point<M, SYS>(qL, qR, k, mp, Fpt);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Fp[v] = wts * Fpt[v];
+    }
+    // Gauss sum over the 16 lanes of the group (fixed butterfly order)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double x = Fp[v];
+      x += __shfl_xor(x, 8, 16);
+      x += __shfl_xor(x, 4, 16);
+      x += __shfl_xor(x, 2, 16);
+      x += __shfl_xor(x, 1, 16);
+      if (l == 0 && f_in) sF[f * NV + v] = x;
+    }
+  }
+  __syncthreads();
+
+  // update: one thread per tile cell
+  const int cx = tid % TX, cy = tid / TX;
+  if (tid < TX * TY) {
+    const int gi = x0 + cx, gj = y0 + cy;
+    if (gi < nx && gj < ny) {
+      const int64_t cell = gi + (int64_t)nx * gj;
+      const double dt = *dt_dev;
+      const double cxf = dt / mp.dx[0], cyf = dt / mp.dx[1];
+      const int fxl = cx + (TX + 1) * cy, fxh = fxl + 1;
+      const int fyl = NFX + cx + TX * cy, fyh = fyl + TX;
+      double q[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double uu = u_in[(int64_t)v * ld + cell];
+        uu -= cxf * (sF[fxh * NV + v] - sF[fxl * NV + v]);
+        uu -= cyf * (sF[fyh * NV + v] - sF[fyl * NV + v]);
+        u_out[(int64_t)v * ld + cell] = uu;
+        q[v] = uu;
+      }
+      unsigned int flags = 0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        if (q[v] != q[v]) flags |= kFlagNan;
+      if constexpr (SYS == 1) {
+        double kin = 0.0;
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) kin += q[1 + m] * q[1 + m] / q[0];
+        const double p = (mp.gamma - 1.0) * (q[DIM + 1] - 0.5 * kin);
+        if (!(q[0] > 0.0) || !(p > 0.0)) flags |= kFlagNonPhysical;
+      }
+      if (flags) atomicOr(&hdr->status, flags);
+    }
+  }
+  (void)C;
+}
+
+}  // namespace ader

@@ -4,6 +4,7 @@
 #include <type_traits>
 
 #include "plan.hpp"
+#include "fused2d.hpp"
 #include "predict_mfma.hpp"
 
 namespace ader {
@@ -37,12 +38,11 @@ struct Impl final : ImplBase {
     WsHeader* hdr = reinterpret_cast<WsHeader*>(ws);
     const MeshParams mp = params(p, ld);
     StageTimer timer(&p.prof, ADER_STAGE_DT, st);
-    hipLaunchKernelGGL(k_dt_reset<DIM>, dim3(1), dim3(64), 0, st, hdr);
     unsigned int nb = blocks_for(p.ncells);
-    if (nb > 4096) nb = 4096;
-    hipLaunchKernelGGL((k_dt_reduce<DIM, SYS>), dim3(nb), dim3(kBlock), 0, st, u, mp, hdr);
-    hipLaunchKernelGGL(k_dt_finalize<DIM>, dim3(1), dim3(64), 0, st, hdr, p.prob.cfl, t, t_end,
-                       dt);
+    if (nb > (unsigned)kDtMaxBlocks) nb = kDtMaxBlocks;
+    double* partial = reinterpret_cast<double*>(ws + p.off_dtp);
+    hipLaunchKernelGGL((k_dt<DIM, SYS>), dim3(nb), dim3(kBlock), 0, st, u, mp, hdr, partial,
+                       p.prob.cfl, t, t_end, dt);
     return hipGetLastError();
   }
 
@@ -101,6 +101,34 @@ struct Impl final : ImplBase {
 
   hipError_t step(const PlanData& p, const double* u_in, double* u_out, int64_t ld,
                   const double* dt, char* ws, hipStream_t st) const override {
+    if constexpr (DIM == 2) return step_fused2d(p, u_in, u_out, ld, dt, ws, st);
+    return step_stages(p, u_in, u_out, ld, dt, ws, st);
+  }
+
+  // 2D: cell kernel (WENO + predictor + traces) and face kernel
+  hipError_t step_fused2d(const PlanData& p, const double* u_in, double* u_out, int64_t ld,
+                          const double* dt, char* ws, hipStream_t st) const {
+    constexpr int TY = 4;
+    const MeshParams mp = params(p, ld);
+    WsHeader* hdr = reinterpret_cast<WsHeader*>(ws);
+    R* tr = reinterpret_cast<R*>(ws + p.off_tr);
+    {
+      StageTimer timer(&p.prof, ADER_STAGE_PREDICT, st);
+      dim3 grid((p.mp.n[0] + kCellTX - 1) / kCellTX, (p.mp.n[1] + TY - 1) / TY);
+      hipLaunchKernelGGL((k_cell2d<M, SYS, TY, R>), grid, dim3(64 * TY), 0, st, u_in, ld, tr,
+                         dt, mp, p.dc, hdr);
+    }
+    {
+      StageTimer timer(&p.prof, ADER_STAGE_FLUX, st);
+      dim3 grid((p.mp.n[0] + kFaceTX - 1) / kFaceTX, (p.mp.n[1] + kFaceTY - 1) / kFaceTY);
+      hipLaunchKernelGGL((k_face2d<M, SYS, R>), grid, dim3(kBlock), 0, st, (const R*)tr, u_in,
+                         u_out, ld, dt, mp, p.dc, hdr);
+    }
+    return hipGetLastError();
+  }
+
+  hipError_t step_stages(const PlanData& p, const double* u_in, double* u_out, int64_t ld,
+                         const double* dt, char* ws, hipStream_t st) const {
     hipError_t e;
     double* wh = reinterpret_cast<double*>(ws + p.off_wh);
     R* qh = reinterpret_cast<R*>(ws + p.off_qh);

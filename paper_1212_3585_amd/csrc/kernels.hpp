@@ -1,8 +1,8 @@
 // HIP kernels of the one-step ADER-WENO step for gfx950 (CDNA4, wave64).
 //
 // Stage kernels (one launch each, data between stages in the workspace):
-//   k_dt_*         CFL time step: per-cell wave-speed sum, wavefront max,
-//                  64-bit atomic max on the bit pattern, finalisation.
+//   k_dt           CFL time step: per-cell wave-speed sum, block maxima,
+//                  last-arriving block reduces them (one launch).
 //   k_weno_line    one 1D WENO pass (Section 2.2) along axis K over a
 //                  structure-of-arrays field; the x pass reads the averages,
 //                  the y (and z) passes read the previous pass's nodal values
@@ -54,7 +54,7 @@ struct MeshParams {
 
 struct WsHeader {
   unsigned int status;
-  unsigned int pad0;
+  unsigned int dt_blocks_done;  // arrival counter of k_dt (zero between calls)
   unsigned long long iters;
   unsigned long long smax_bits;
   double pad1[5];
@@ -588,22 +588,28 @@ k_update(const double* __restrict__ u_in, double* __restrict__ u_out, const doub
 
 // ------------------------------------------------------------- time step
 template <int DIM>
-__global__ void k_dt_reset(WsHeader* hdr) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) hdr->smax_bits = 0ull;
-}
-
-template <int DIM>
 __global__ void k_clear_status(WsHeader* hdr) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     hdr->status = 0u;
     hdr->iters = 0ull;
+    hdr->dt_blocks_done = 0u;
   }
 }
 
+// few blocks: every block adds one arrival to a single counter
+constexpr int kDtMaxBlocks = 128;
+
+// Time step in one launch: per-block maximum of sum_k (|v_k| + c)/dx_k over
+// a grid-stride range of cells, written to partial[block]; the last block to
+// arrive (arrival counter in the header) reduces the partials, clips to the
+// end time, writes dt and re-arms the counter.
 template <int DIM, int SYS>
 __global__ void __launch_bounds__(kBlock)
-k_dt_reduce(const double* __restrict__ u, MeshParams mp, WsHeader* hdr) {
+k_dt(const double* __restrict__ u, MeshParams mp, WsHeader* hdr, double* partial, double cfl,
+     double t, double t_end, double* dt_out) {
   constexpr int NV = NVars<SYS, DIM>::v;
+  __shared__ double sw[kBlock / 64];
+  __shared__ bool last;
   double smax = 0.0;
   const double adv[3] = {mp.adv[0], mp.adv[1], mp.adv[2]};
   for (int64_t cell = (int64_t)blockIdx.x * kBlock + threadIdx.x; cell < mp.ncells;
@@ -618,28 +624,49 @@ k_dt_reduce(const double* __restrict__ u, MeshParams mp, WsHeader* hdr) {
       phys_flux_dir<SYS, DIM>(q, k, mp.gamma, adv, f, sp);
       s += sp / mp.dx[k];
     }
-    // NaN must win the maximum so that it reaches dt and the status word
+    // a NaN must win the maximum so that it reaches dt and the status word
     smax = (s != s || s > smax) ? s : smax;
   }
-  unsigned long long bits = __double_as_longlong(smax);
-  // wavefront maximum (non-negative doubles order like their bit patterns)
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
-    unsigned long long o = __shfl_xor(bits, off, 64);
-    bits = o > bits ? o : bits;
+    const double o = __shfl_xor(smax, off, 64);
+    smax = (o != o || o > smax) ? o : smax;
   }
-  if ((threadIdx.x & 63) == 0) atomicMax(&hdr->smax_bits, bits);
-}
-
-template <int DIM>
-__global__ void k_dt_finalize(WsHeader* hdr, double cfl, double t, double t_end, double* dt_out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const double smax = __longlong_as_double((long long)hdr->smax_bits);
-    double dt = cfl / smax;
+  if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = smax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = sw[0];
+#pragma unroll
+    for (int i = 1; i < kBlock / 64; ++i) b = (sw[i] != sw[i] || sw[i] > b) ? sw[i] : b;
+    partial[blockIdx.x] = b;
+    __threadfence();
+    last = atomicAdd(&hdr->dt_blocks_done, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double m = 0.0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += kBlock) {
+    const double o = __hip_atomic_load(&partial[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    m = (o != o || o > m) ? o : m;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(m, off, 64);
+    m = (o != o || o > m) ? o : m;
+  }
+  if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = sw[0];
+#pragma unroll
+    for (int i = 1; i < kBlock / 64; ++i) b = (sw[i] != sw[i] || sw[i] > b) ? sw[i] : b;
+    double dt = cfl / b;
     const double rest = t_end - t;
     dt = rest < dt ? rest : dt;
     if (dt != dt) atomicOr(&hdr->status, kFlagNan);
     *dt_out = dt;
+    hdr->dt_blocks_done = 0u;
   }
 }
 

@@ -62,6 +62,8 @@ struct PlanData {
   RefConstants ref;
   // workspace layout (byte offsets; every section 256-byte aligned)
   size_t off_wx = 0, off_wxy = 0, off_wh = 0, off_qh = 0, off_f[3] = {0, 0, 0};
+  size_t off_dtp = 0;  // per-block partial maxima of the time-step reduction
+  size_t off_tr = 0;   // face traces of the fused 2D path
   size_t ws_bytes = 0;
   mutable Profiler prof;
 };
