@@ -167,7 +167,7 @@ ader_status ader_plan_create(const ader_problem* prob, ader_plan* out) {
   }
 
   // workspace: header | Wx | Wxy (3D) | w_h | q_h | face fluxes
-  size_t off = 256;
+  size_t off = ader::kHeaderBytes;
   const size_t C = (size_t)ncells;
   d.off_wx = off;
   off = align256(off + sizeof(double) * d.nv * d.n * C);
@@ -272,7 +272,11 @@ ader_status ader_read_status(ader_plan plan, const void* ws, uint32_t* flags,
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_status(e, "ader_read_status");
   *flags = h.status;
-  if (picard_iterations) *picard_iterations = h.iters;
+  if (picard_iterations) {
+    uint64_t total = 0;
+    for (int i = 0; i < ader::kCounterSlots; ++i) total += h.iters[i];
+    *picard_iterations = total;
+  }
   return ADER_OK;
 }
 

@@ -1,7 +1,7 @@
 // Fused 2D step: a cell kernel (WENO + predictor + face traces) and a face
 // kernel (Rusanov fluxes + Gauss sums + update).  R is the predictor
 // precision: double (derivative products on the fp64 matrix cores) or float
-// (fp32 FMAs on shuffled values, fp32 accumulation).
+// (fp32 FMAs on exchanged lane values, fp32 accumulation).
 //
 // k_cell2d   one block = a 4 x TY tile of cells, TY wavefronts; wavefront w
 //            holds the tile's row w, one cell per matrix block b1.
@@ -36,31 +36,68 @@ namespace ader {
 
 constexpr int kCellTX = 4;  // tile width of the cell kernel = cells per wavefront
 
+// fp32 lane exchanges without the LDS crossbar (gfx950):
+//   lane ^ 1, ^ 2, ^ 3 : DPP quad permutations;
+//   lane ^ 16          : v_permlane16_swap with both operands x -- the partner
+//                        value is returned in slot 1 on even rows of 16 lanes
+//                        and in slot 0 on odd rows;
+//   lane ^ 32          : v_permlane32_swap likewise (slot 1 for lanes < 32).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kQuadXor3 = 0x1B;  // [1032] [2301] [3210]
+
+__device__ __forceinline__ float xor16_f(float x) {
+  const unsigned u = __float_as_uint(x);
+  const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+  return __uint_as_float(((threadIdx.x >> 4) & 1) ? r[0] : r[1]);
+}
+__device__ __forceinline__ float xor32_f(float x) {
+  const unsigned u = __float_as_uint(x);
+  const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+  return __uint_as_float(((threadIdx.x >> 5) & 1) ? r[0] : r[1]);
+}
+
 template <typename R>
-__device__ __forceinline__ R cell_max_r(R x) {
-  x = fmax(x, __shfl_xor(x, 1, 64));
-  x = fmax(x, __shfl_xor(x, 2, 64));
-  x = fmax(x, __shfl_xor(x, 16, 64));
-  x = fmax(x, __shfl_xor(x, 32, 64));
+__device__ __forceinline__ R cell_max_r(R x);
+template <>
+__device__ __forceinline__ double cell_max_r<double>(double x) {
+  return cell_max(x);
+}
+template <>
+__device__ __forceinline__ float cell_max_r<float>(float x) {
+  x = fmaxf(x, dpp_f<kQuadXor1>(x));
+  x = fmaxf(x, dpp_f<kQuadXor2>(x));
+  x = fmaxf(x, xor16_f(x));
+  x = fmaxf(x, xor32_f(x));
   return x;
 }
 
-// Lane-local coefficients of the shuffle form (fp32 predictor): the node
-// p ^ m of the same line is fetched with a xor shuffle; coef[m] = D[p][p ^ m]
-// (zero where p ^ m is a padding node).
+// Lane-local coefficients of the exchange form (fp32 predictor): the node
+// p ^ m of the same line is fetched from lane ^ m (b0) or lane ^ 16 m (b2);
+// coef[m] = D[p][p ^ m] (zero where p ^ m is a padding node).
 template <int n>
 __device__ __forceinline__ void xor_row(const DevConsts& c, int p, double scale, float (&coef)[4]) {
 #pragma unroll
   for (int m = 0; m < 4; ++m) coef[m] = (float)(scale * pick_entry<n>(c.dmat, p, p ^ m));
 }
 
-template <typename R>
-__device__ __forceinline__ R xor_line(R x, const R (&coef)[4], int stride) {
-  // sum_m coef[m] * x(lane ^ (m * stride)) in the order m = 0, 1, 2, 3
-  R acc = coef[0] * x;
-  acc = fma(coef[1], __shfl_xor(x, stride, 64), acc);
-  acc = fma(coef[2], __shfl_xor(x, 2 * stride, 64), acc);
-  acc = fma(coef[3], __shfl_xor(x, 3 * stride, 64), acc);
+// sum_m coef[m] * x(lane ^ m) over the quad (the b0 axis), m = 0..3 in order
+__device__ __forceinline__ float xor_line_b0(float x, const float (&coef)[4]) {
+  float acc = coef[0] * x;
+  acc = fmaf(coef[1], dpp_f<kQuadXor1>(x), acc);
+  acc = fmaf(coef[2], dpp_f<kQuadXor2>(x), acc);
+  acc = fmaf(coef[3], dpp_f<kQuadXor3>(x), acc);
+  return acc;
+}
+// sum_m coef[m] * x(lane ^ 16 m) across rows (the b2 axis), m = 0..3 in order
+__device__ __forceinline__ float xor_line_b2(float x, const float (&coef)[4]) {
+  const float x32 = xor32_f(x);
+  float acc = coef[0] * x;
+  acc = fmaf(coef[1], xor16_f(x), acc);
+  acc = fmaf(coef[2], x32, acc);
+  acc = fmaf(coef[3], xor16_f(x32), acc);
   return acc;
 }
 
@@ -178,7 +215,7 @@ k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
           const double gt = __builtin_amdgcn_mfma_f64_4x4x4f64(F[1][v], idv, 0.0, 0, 0, 0);
           Rs[v][s] = __builtin_amdgcn_mfma_f64_4x4x4f64(gt, my, rx, 0, 0, 0);
         } else {
-          Rs[v][s] = xor_line<R>(F[0][v], cxm, 16) + xor_line<R>(F[1][v], cym, 1);
+          Rs[v][s] = xor_line_b2(F[0][v], cxm) + xor_line_b0(F[1][v], cym);
         }
       }
     }
@@ -205,19 +242,15 @@ k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
     }
     if (!__any(!done)) break;
   }
-  if (cell_ok) {
-    if (!done) {
-      iters = mp.maxit;
-      if (lane == 4 * b1) atomicOr(&hdr->status, kFlagNoConv);
-    }
-    if (lane == 4 * b1) atomicAdd(&hdr->iters, (unsigned long long)iters);
-  }
+  if (cell_ok && !done) iters = mp.maxit;
+  block_report(cell_ok && lane == 4 * b1 ? (unsigned)iters : 0u,
+               cell_ok && lane == 4 * b1 && !done ? kFlagNoConv : 0u, hdr);
 
   // 5. face traces.  x faces: operand A row 0 = psi(0), row 1 = psi(1)
   //    (A[i=b0][k=b2]); result lane (b0 = y node, b2 = 0 / 1 = low / high).
   //    y faces: transpose, then operand B column 0 = psi(0), column 1 = psi(1)
   //    (B[k=b2][j=b0]); result lane (b0 = 0 / 1 = low / high, b2 = x node).
-  //    fp32: each lane forms, by shuffles, the four traces at its own
+  //    fp32: each lane forms, by lane exchanges, the four traces at its own
   //    transverse node; lanes b2 = 0 write the x faces, lanes b0 = 0 the y
   //    faces.
   const int64_t C = mp.ncells;
@@ -267,8 +300,8 @@ k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
 #pragma unroll
       for (int s = 0; s < n; ++s) {
         const R x = q[v][s];
-        const R tx0 = xor_line<R>(x, e0x, 16), tx1 = xor_line<R>(x, e1x, 16);
-        const R ty0 = xor_line<R>(x, e0y, 1), ty1 = xor_line<R>(x, e1y, 1);
+        const R tx0 = xor_line_b2(x, e0x), tx1 = xor_line_b2(x, e1x);
+        const R ty0 = xor_line_b0(x, e0y), ty1 = xor_line_b0(x, e1y);
         if (cell_ok) {
           if (b2 == 0 && b0 < n) {
             traces[((int64_t)0 * C + cell) * TRC + (v * n + s) * n + b0] = tx0;
@@ -392,6 +425,7 @@ k_face2d(const TR* __restrict__ traces, const double* __restrict__ u_in,
 
   // update: one thread per tile cell
   const int cx = tid % TX, cy = tid / TX;
+  unsigned int flags = 0;
   if (tid < TX * TY) {
     const int gi = x0 + cx, gj = y0 + cy;
     if (gi < nx && gj < ny) {
@@ -409,7 +443,6 @@ k_face2d(const TR* __restrict__ traces, const double* __restrict__ u_in,
         u_out[(int64_t)v * ld + cell] = uu;
         q[v] = uu;
       }
-      unsigned int flags = 0;
 #pragma unroll
       for (int v = 0; v < NV; ++v)
         if (q[v] != q[v]) flags |= kFlagNan;
@@ -420,9 +453,9 @@ k_face2d(const TR* __restrict__ traces, const double* __restrict__ u_in,
         const double p = (mp.gamma - 1.0) * (q[DIM + 1] - 0.5 * kin);
         if (!(q[0] > 0.0) || !(p > 0.0)) flags |= kFlagNonPhysical;
       }
-      if (flags) atomicOr(&hdr->status, flags);
     }
   }
+  block_report(0u, flags, hdr);
   (void)C;
 }
 

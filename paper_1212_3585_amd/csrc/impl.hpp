@@ -22,7 +22,7 @@ struct Impl final : ImplBase {
   size_t qh_elem_size() const override { return sizeof(R); }
 
   hipError_t clear_status(char* ws, hipStream_t st) const override {
-    hipLaunchKernelGGL(k_clear_status<DIM>, dim3(1), dim3(64), 0, st,
+    hipLaunchKernelGGL(k_clear_status<DIM>, dim3(1), dim3(kCounterSlots), 0, st,
                        reinterpret_cast<WsHeader*>(ws));
     return hipGetLastError();
   }
@@ -108,7 +108,7 @@ struct Impl final : ImplBase {
   // 2D: cell kernel (WENO + predictor + traces) and face kernel
   hipError_t step_fused2d(const PlanData& p, const double* u_in, double* u_out, int64_t ld,
                           const double* dt, char* ws, hipStream_t st) const {
-    constexpr int TY = 4;
+    constexpr int TY = 8;  // tile rows = wavefronts per block
     const MeshParams mp = params(p, ld);
     WsHeader* hdr = reinterpret_cast<WsHeader*>(ws);
     R* tr = reinterpret_cast<R*>(ws + p.off_tr);

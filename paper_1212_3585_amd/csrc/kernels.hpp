@@ -52,15 +52,42 @@ struct MeshParams {
   int64_t ld;
 };
 
+// Picard sweeps are counted in kCounterSlots slots (block b adds to slot
+// b mod kCounterSlots) so that no single address takes an atomic from every
+// block; the host sums the slots.
+constexpr int kCounterSlots = 64;
+
 struct WsHeader {
   unsigned int status;
   unsigned int dt_blocks_done;  // arrival counter of k_dt (zero between calls)
-  unsigned long long iters;
-  unsigned long long smax_bits;
-  double pad1[5];
+  unsigned long long iters[kCounterSlots];
 };
+constexpr size_t kHeaderBytes = 1024;
+static_assert(sizeof(WsHeader) <= kHeaderBytes, "workspace header");
 
 constexpr unsigned int kFlagNan = 1u, kFlagNonPhysical = 2u, kFlagNoConv = 4u;
+
+// Adds each thread's (Picard sweeps, status bits) to the workspace header
+// with one global atomic of each kind per block (block-level reduction in
+// LDS first).  Every thread of the block must call it.
+__device__ __forceinline__ void block_report(unsigned int sweeps, unsigned int flags,
+                                             WsHeader* hdr) {
+  __shared__ unsigned long long s_sweeps;
+  __shared__ unsigned int s_flags;
+  if (threadIdx.x == 0) {
+    s_sweeps = 0ull;
+    s_flags = 0u;
+  }
+  __syncthreads();
+  if (sweeps) atomicAdd(&s_sweeps, (unsigned long long)sweeps);
+  if (flags) atomicOr(&s_flags, flags);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned slot = (blockIdx.x + 17u * blockIdx.y) % kCounterSlots;
+    if (s_sweeps) atomicAdd(&hdr->iters[slot], s_sweeps);
+    if (s_flags) atomicOr(&hdr->status, s_flags);
+  }
+}
 
 template <int B, int E> struct Pow { static constexpr int v = B * Pow<B, E - 1>::v; };
 template <int B> struct Pow<B, 0> { static constexpr int v = 1; };
@@ -212,16 +239,19 @@ __device__ __forceinline__ void weno_line(const double (&v)[2 * M + 1], const De
     x = x * x;  // ^2
     x = x * x;  // ^4
     x = x * x;  // ^8
-    om[s] = c.lam[s] / x;
+    om[s] = c.lam[s] * recip(x);
   }
   double tot = 0.0;
 #pragma unroll
   for (int s = 0; s < NSt; ++s) tot += om[s];
+  const double inv_tot = recip(tot);
+#pragma unroll
+  for (int s = 0; s < NSt; ++s) om[s] *= inv_tot;
 #pragma unroll
   for (int p = 0; p < n; ++p) {
     double acc = 0.0;
 #pragma unroll
-    for (int s = 0; s < NSt; ++s) acc += (om[s] / tot) * ws[s][p];
+    for (int s = 0; s < NSt; ++s) acc += om[s] * ws[s][p];
     out[p] = acc;
   }
 }
@@ -421,12 +451,10 @@ k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
     }
     if (__syncthreads_and(done)) break;
   }
+  if (active && !done) iters = mp.maxit;
+  block_report(active && a == 0 ? (unsigned)iters : 0u,
+               active && a == 0 && !done ? kFlagNoConv : 0u, hdr);
   if (active) {
-    if (!done) {
-      iters = mp.maxit;
-      if (a == 0) atomicOr(&hdr->status, kFlagNoConv);
-    }
-    if (a == 0) atomicAdd(&hdr->iters, (unsigned long long)iters);
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -551,8 +579,9 @@ k_update(const double* __restrict__ u_in, double* __restrict__ u_out, const doub
          const double* __restrict__ Fy, const double* __restrict__ Fz, int64_t nfx, int64_t nfy,
          int64_t nfz, const double* __restrict__ dt_dev, MeshParams mp, WsHeader* hdr) {
   constexpr int NV = NVars<SYS, DIM>::v;
-  const int64_t cell = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (cell >= mp.ncells) return;
+  const int64_t cell_raw = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool in = cell_raw < mp.ncells;
+  const int64_t cell = in ? cell_raw : 0;
   const int i = (int)(cell % mp.n[0]);
   const int j = (int)((cell / mp.n[0]) % mp.n[1]);
   const int k = DIM == 3 ? (int)(cell / ((int64_t)mp.n[0] * mp.n[1])) : 0;
@@ -569,7 +598,7 @@ k_update(const double* __restrict__ u_in, double* __restrict__ u_out, const doub
     u -= (dt / mp.dx[1]) * (Fy[v * nfy + fy0 + nx] - Fy[v * nfy + fy0]);
     if constexpr (DIM == 3)
       u -= (dt / mp.dx[2]) * (Fz[v * nfz + fz0 + (int64_t)nx * ny] - Fz[v * nfz + fz0]);
-    u_out[v * mp.ld + cell] = u;
+    if (in) u_out[v * mp.ld + cell] = u;
     q[v] = u;
   }
   unsigned int flags = 0;
@@ -583,15 +612,15 @@ k_update(const double* __restrict__ u_in, double* __restrict__ u_out, const doub
     const double p = (mp.gamma - 1.0) * (q[DIM + 1] - 0.5 * kin);
     if (!(q[0] > 0.0) || !(p > 0.0)) flags |= kFlagNonPhysical;
   }
-  if (flags) atomicOr(&hdr->status, flags);
+  block_report(0u, in ? flags : 0u, hdr);
 }
 
 // ------------------------------------------------------------- time step
 template <int DIM>
 __global__ void k_clear_status(WsHeader* hdr) {
+  if (blockIdx.x == 0 && threadIdx.x < kCounterSlots) hdr->iters[threadIdx.x] = 0ull;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     hdr->status = 0u;
-    hdr->iters = 0ull;
     hdr->dt_blocks_done = 0u;
   }
 }

@@ -130,13 +130,9 @@ k_predict_mfma2d(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t nc
     }
     if (!__any(!done)) break;
   }
-  if (cell_ok) {
-    if (!done) {
-      iters = mp.maxit;
-      if (lane == 4 * b1) atomicOr(&hdr->status, kFlagNoConv);
-    }
-    if (lane == 4 * b1) atomicAdd(&hdr->iters, (unsigned long long)iters);
-  }
+  if (cell_ok && !done) iters = mp.maxit;
+  block_report(cell_ok && lane == 4 * b1 ? (unsigned)iters : 0u,
+               cell_ok && lane == 4 * b1 && !done ? kFlagNoConv : 0u, hdr);
   if (active) {
 #pragma unroll
     for (int v = 0; v < NV; ++v)
