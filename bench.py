@@ -71,6 +71,57 @@ def cell_kernel_flops(dim, M, nv, picard_sweeps_total, ncells):
     return weno + picard + traces
 
 
+def device_source_hash():
+    """sha256 of the HIP sources: a traffic figure measured on other kernels
+    than the ones built now is not reported."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1212_3585_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hpp", ".hip", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_cell2d_kh512_m3.json")
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the fp64 cell kernel from the committed
+    counter measurement, or None when the kernels have changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("device_source_sha256") != device_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def traffic_probe():
+    """Run under rocprofv3 --pmc: one step of each precision on the bench
+    workload, then a 256 MiB device-to-device copy whose FETCH_SIZE and
+    WRITE_SIZE calibrate the counters (known 256 MiB read + 256 MiB write)."""
+    import torch
+    from paper_1212_3585_amd import ader, workloads as wl
+    ader.require_gpu()
+    U0 = wl.kelvin_helmholtz(N)
+    u0 = torch.tensor(wl.to_soa(U0), dtype=torch.float64, device="cuda")
+    for precision, tol in ((ader.PREC_FP64, 1e-14), (ader.PREC_FP32_PREDICTOR, 1e-6)):
+        s = ader.Solver(ader.Problem(dim=2, M=M, n=(N, N, 1), precision=precision,
+                                     picard_tol=tol))
+        b = torch.empty_like(u0)
+        s.compute_dt(u0)
+        s.step(u0, b)
+    src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print("traffic probe done: copy of", src.numel() * 8, "bytes", flush=True)
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -122,7 +173,12 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=64,
                     help="mesh rows of the CPU-oracle sample (512 cells each)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only run the launches that the HBM counters calibrate")
     args = ap.parse_args()
+    if args.traffic_probe:
+        traffic_probe()
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus must be 1",
               file=sys.stderr)
@@ -221,7 +277,7 @@ def main():
         "roofline": {"bound": "alu",
                      "kernel": "k_cell2d<3,1,4,double> (WENO + Picard predictor + traces)",
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": recorded_traffic(),
                      "flops_per_launch": flops_launch,
                      "avg_launch_ms": avg_s * 1e3},
         "cpu_baseline": cpu,

@@ -55,6 +55,7 @@ def _create(ader_mod, **kw):
     (dict(gamma=1.0), -1), (dict(picard_tol=0.0), -1), (dict(picard_max=0), -1),
     (dict(hi=(0.0, 1.0, 1.0)), -1), (dict(bc=(0, 5, 0)), -1), (dict(precision=3), -1),
     (dict(lo=(float("nan"), 0.0, 0.0)), -1),
+    (dict(dim=3, n=(1024, 1024, 257)), -2),      # beyond 2^28 cells
 ])
 def test_plan_create_rejects_bad_problems(ader_mod, kw, status):
     st, plan = _create(ader_mod, **kw)

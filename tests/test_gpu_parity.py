@@ -269,3 +269,82 @@ def test_picard_cap_is_flagged(ader):
     assert flags & ader.FLAG_NOCONV
     s.clear_status()
     assert s.read_status()[0] == 0
+
+
+# ------------------------------------------------ the other full-size configs
+def test_explosion_100_full_oracle(ader):
+    """Circular explosion on [-1,1]^2, 100^2 level-0 mesh, M = 2, transmissive:
+    three steps against the full-mesh oracle (uniform proxy of the AMR run)."""
+    say("explosion 100x100 M=2 3 steps")
+    N = 100
+    U0 = wl.explosion_2d(N)
+    op, gp = make_pair(ader, 2, 2, (N, N), (-1, -1), (1, 1), "transmissive")
+    Uo, *_ = oracle.run(op, U0, 1.0, max_steps=3)
+    s = ader.Solver(gp)
+    u, *_ = s.run(to_device(U0), 1.0, max_steps=3)
+    got = from_device(u, (N, N))
+    assert rel_l1(got, Uo) <= TOL, (rel_l1(got, Uo), rel_l1_per_var(got, Uo))
+    assert s.read_status()[0] == 0
+
+
+def test_explosion_900_sampled(ader):
+    """Fine-equivalent 900^2 mesh of the explosion (100 x 3^2): one step,
+    sampled cells (boundaries, corners, the discontinuity) against the oracle."""
+    say("explosion 900x900 M=2 sampled")
+    N = 900
+    U0 = wl.explosion_2d(N)
+    op, gp = make_pair(ader, 2, 2, (N, N), (-1, -1), (1, 1), "transmissive")
+    s = ader.Solver(gp)
+    u = to_device(U0)
+    out = s.empty_state()
+    s.compute_dt(u)
+    s.step(u, out)
+    got = from_device(out, (N, N))
+    dt = oracle.cfl_dt(op, U0)
+    rng = np.random.default_rng(11)
+    ring = [[int(N / 2 + 225 * np.cos(a)), int(N / 2 + 225 * np.sin(a))]
+            for a in np.linspace(0, 2 * np.pi, 40, endpoint=False)]
+    cells = np.concatenate([rng.integers(0, N, size=(120, 2)), ring,
+                            [[0, 0], [N - 1, N - 1], [0, N - 1], [N - 1, 0], [0, 450]]])
+    ref, _ = oracle.step_cells(op, U0, dt, cells)
+    g = got[:, cells[:, 0], cells[:, 1]]
+    assert rel_l1(g, ref) <= TOL, rel_l1(g, ref)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_blast_3d_64_sampled(ader, precision):
+    """Spherical blast on [-1,1]^3, 64^3, M = 2, transmissive: one step,
+    sampled cells against the fp64 oracle (fp64: 1e-11; fp32 predictor:
+    stated, < 1e-5)."""
+    say(f"3D blast 64^3 M=2 sampled precision={precision}")
+    N = 64
+    U0 = wl.blast_3d(N)
+    op, gp = make_pair(ader, 3, 2, (N, N, N), (-1,) * 3, (1,) * 3, "transmissive",
+                       precision=precision, tol=1e-14 if precision == 0 else 1e-6)
+    s = ader.Solver(gp)
+    u = to_device(U0)
+    out = s.empty_state()
+    s.compute_dt(u)
+    s.step(u, out)
+    got = from_device(out, (N, N, N))
+    dt = oracle.cfl_dt(op, U0)
+    rng = np.random.default_rng(12)
+    cells = np.concatenate([rng.integers(0, N, size=(60, 3)),
+                            [[0, 0, 0], [N - 1, N - 1, N - 1], [32, 32, 41], [32, 42, 32],
+                             [22, 32, 32], [0, 32, N - 1]]])
+    ref, _ = oracle.step_cells(op, U0, dt, cells)
+    g = got[:, cells[:, 0], cells[:, 1], cells[:, 2]]
+    err = rel_l1(g, ref)
+    print(f"3D blast 64^3 precision {precision}: relative L1 {err:.3e}")
+    assert err <= (TOL if precision == 0 else 1e-5)
+    assert s.read_status()[0] == 0
+
+
+def test_empty_predictor_call_is_a_no_op(ader):
+    import torch
+    _, gp = make_pair(ader, 2, 3, (8, 8), (0, 0), (1, 1))
+    s = ader.Solver(gp)
+    s.clear_status()
+    dummy = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s.predict(dummy, 0)
+    assert s.read_status() == (0, 0)
