@@ -85,6 +85,7 @@ typedef struct ader_plan_s* ader_plan;
 #define ADER_FLAG_NAN 1u          /* a NaN appeared in the new averages or dt */
 #define ADER_FLAG_NONPHYSICAL 2u  /* rho <= 0 or p <= 0 in the new averages */
 #define ADER_FLAG_NOCONV 4u       /* predictor reached picard_max */
+#define ADER_FLAG_BADINDEX 8u     /* a level view held an index out of range */
 
 /* Validate the problem and build the reference-element constants (Gauss-
  * Legendre nodes and weights, Lagrange basis values and derivatives,
@@ -140,6 +141,46 @@ ader_status ader_debug_reconstruct(ader_plan plan, const double* u, int64_t ld,
 ader_status ader_debug_predict(ader_plan plan, const double* w_h,
                                int64_t ncells, double* q_h,
                                const double* dt_dev, void* ws, void* stream);
+
+/* One step over the cell lists of one refinement level (or any subset of a
+ * uniform mesh).  On a cell-by-cell AMR mesh the predictor is element-local
+ * and identical to the uniform one; the reconstruction of every cell reads a
+ * layer of at least M same-level cells, real or virtual (Section 3), which
+ * the caller names explicitly:
+ *   level       refinement level (informational)
+ *   dx          mesh widths of the level
+ *   npred       cells whose predictor is computed: the cells updated and the
+ *               face neighbours their fluxes need
+ *   pred_cells  [npred] state index of each of them
+ *   pred_patch  [npred * (2M+1)^d] state indices of the (2M+1)^d cells around
+ *               each (offsets -M..M per axis, x fastest); virtual and ghost
+ *               cells are ordinary entries of the state arrays
+ *   nupd        cells updated
+ *   upd         [nupd] positions (0..npred-1) in pred_cells of those cells
+ *   upd_nbr     [nupd * 2d] positions in pred_cells of their face neighbours,
+ *               order x-low, x-high, y-low, y-high[, z-low, z-high]; -1 marks
+ *               an outflow face (outer trace = inner trace)
+ * u_out receives the new averages of the updated cells only; u_in and u_out
+ * must not overlap.  All arrays are device memory.  The plan's M, dim,
+ * system, precision and Picard settings apply; its mesh sizes do not.  The
+ * workspace is ader_level_workspace_bytes(plan, npred) bytes.  Indices out
+ * of range are not dereferenced: they set ADER_FLAG_BADINDEX (an outflow
+ * face for a bad neighbour, no update for a bad cell). */
+typedef struct {
+  int level;
+  double dx[3];
+  int64_t npred;
+  const int32_t* pred_cells;
+  const int32_t* pred_patch;
+  int64_t nupd;
+  const int32_t* upd;
+  const int32_t* upd_nbr;
+} ader_level_view;
+
+ader_status ader_level_workspace_bytes(ader_plan plan, int64_t npred, size_t* bytes);
+ader_status ader_step_level(ader_plan plan, const ader_level_view* view,
+                            const double* u_in, double* u_out, int64_t ld,
+                            const double* dt_dev, void* ws, void* stream);
 
 /* Synchronise 'stream' and read the status bits (ADER_FLAG_*) and the sum of
  * predictor iterations over all cells since the last clear. */

@@ -19,7 +19,7 @@ OK, EINVAL, EUNSUPPORTED, EHIP, EWORKSPACE = 0, -1, -2, -3, -4
 SYS_LINADV, SYS_EULER = 0, 1
 PREC_FP64, PREC_FP32_PREDICTOR = 0, 1
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
-FLAG_NAN, FLAG_NONPHYSICAL, FLAG_NOCONV = 1, 2, 4
+FLAG_NAN, FLAG_NONPHYSICAL, FLAG_NOCONV, FLAG_BADINDEX = 1, 2, 4, 8
 
 # every symbol declared in include/ader.h
 EXPORTS = [
@@ -27,6 +27,7 @@ EXPORTS = [
     "ader_workspace_bytes", "ader_clear_status", "ader_compute_dt", "ader_step",
     "ader_debug_reconstruct", "ader_debug_predict", "ader_read_status",
     "ader_debug_constants", "ader_profile_begin", "ader_profile_end",
+    "ader_level_workspace_bytes", "ader_step_level",
     "ader_status_string", "ader_last_error",
 ]
 STAGES = ["dt", "weno", "predict", "flux", "update"]
@@ -46,6 +47,15 @@ class CProblem(ctypes.Structure):
         ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int * 3),
         ("cfl", ctypes.c_double), ("precision", ctypes.c_int),
         ("picard_tol", ctypes.c_double), ("picard_max", ctypes.c_int),
+    ]
+
+
+class CLevelView(ctypes.Structure):
+    _fields_ = [
+        ("level", ctypes.c_int), ("dx", ctypes.c_double * 3),
+        ("npred", ctypes.c_int64), ("pred_cells", ctypes.c_void_p),
+        ("pred_patch", ctypes.c_void_p), ("nupd", ctypes.c_int64),
+        ("upd", ctypes.c_void_p), ("upd_nbr", ctypes.c_void_p),
     ]
 
 
@@ -77,6 +87,8 @@ def load_library():
         "ader_debug_constants": [vp, vp, vp, vp, vp],
         "ader_profile_begin": [vp],
         "ader_profile_end": [vp, vp, vp],
+        "ader_level_workspace_bytes": [vp, i64, ctypes.POINTER(ctypes.c_size_t)],
+        "ader_step_level": [vp, ctypes.POINTER(CLevelView), vp, vp, i64, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -257,6 +269,41 @@ class Solver:
                                          cnt.ctypes.data_as(ctypes.c_void_p)),
                "ader_profile_end")
         return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(STAGES)}
+
+    def step_level(self, pred_cells, pred_patch, upd, upd_nbr, dx, u_in, u_out, dt=None,
+                   level=0, stream=None):
+        """One step over a level's cell lists (int32 device tensors; see
+        ader_step_level).  Allocates the level workspace on first use."""
+        import torch
+        npred = int(pred_cells.numel())
+        nb = ctypes.c_size_t()
+        _check(self.lib.ader_level_workspace_bytes(self._plan, npred, ctypes.byref(nb)),
+               "ader_level_workspace_bytes")
+        if getattr(self, "_lws", None) is None or self._lws.numel() < nb.value:
+            self._lws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+            self._lws[:1024].zero_()
+        view = CLevelView()
+        view.level = level
+        view.dx[:] = list(dx)[:3] + [1.0] * (3 - len(dx))
+        view.npred = npred
+        view.pred_cells = _ptr(pred_cells) if npred else None
+        view.pred_patch = _ptr(pred_patch) if npred else None
+        view.nupd = int(upd.numel())
+        view.upd = _ptr(upd) if view.nupd else None
+        view.upd_nbr = _ptr(upd_nbr) if view.nupd else None
+        dt = self.dt if dt is None else dt
+        _check(self.lib.ader_step_level(self._plan, ctypes.byref(view), _ptr(u_in), _ptr(u_out),
+                                        u_in.shape[1], _ptr(dt), _ptr(self._lws),
+                                        _stream(stream)), "ader_step_level")
+        return u_out
+
+    def read_level_status(self, stream=None):
+        flags = ctypes.c_uint32()
+        iters = ctypes.c_uint64()
+        _check(self.lib.ader_read_status(self._plan, _ptr(self._lws), ctypes.byref(flags),
+                                         ctypes.byref(iters), _stream(stream)),
+               "ader_read_status")
+        return flags.value, iters.value
 
     def run(self, u, t_end, max_steps=10**9, stream=None):
         """Advance u to t_end; returns (u, t, steps).  Reads dt back each step."""

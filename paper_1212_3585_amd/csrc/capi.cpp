@@ -262,6 +262,44 @@ ader_status ader_debug_predict(ader_plan plan, const double* w_h, int64_t ncells
                     "ader_debug_predict");
 }
 
+ader_status ader_level_workspace_bytes(ader_plan plan, int64_t npred, size_t* bytes) {
+  if (!plan || !bytes) return fail(ADER_EINVAL, "null argument");
+  if (npred < 0 || npred > (int64_t(1) << 28)) return fail(ADER_EINVAL, "bad npred");
+  *bytes = plan->impl->level_layout(plan->data, npred).bytes;
+  return ADER_OK;
+}
+
+ader_status ader_step_level(ader_plan plan, const ader_level_view* view, const double* u_in,
+                            double* u_out, int64_t ld, const double* dt_dev, void* ws,
+                            void* stream) {
+  if (!plan || !view || !dt_dev) return fail(ADER_EINVAL, "null argument");
+  if (!u_in || !u_out) return fail(ADER_EINVAL, "state pointer is null");
+  if (ld < 1 || ld > (int64_t(1) << 31) - 1) return fail(ADER_EINVAL, "bad ld");
+  if (ader_status s = check_ws(plan, ws)) return s;
+  const ader_level_view& v = *view;
+  if (v.npred < 0 || v.npred > (int64_t(1) << 28) || v.nupd < 0 || v.nupd > v.npred)
+    return fail(ADER_EINVAL, "need 0 <= nupd <= npred <= 2^28");
+  if (v.npred > 0 && (!v.pred_cells || !v.pred_patch))
+    return fail(ADER_EINVAL, "null predicted-cell arrays");
+  if (v.nupd > 0 && (!v.upd || !v.upd_nbr)) return fail(ADER_EINVAL, "null update arrays");
+  for (int k = 0; k < plan->data.dim; ++k)
+    if (!is_finite(v.dx[k]) || !(v.dx[k] > 0.0)) return fail(ADER_EINVAL, "dx must be > 0");
+  const uintptr_t a0 = (uintptr_t)u_in, b0 = (uintptr_t)u_out;
+  const uintptr_t len = sizeof(double) * (uintptr_t)plan->data.nv * (uintptr_t)ld;
+  if (a0 < b0 + len && b0 < a0 + len) return fail(ADER_EINVAL, "u_in and u_out overlap");
+  ader::LevelArgs L;
+  for (int k = 0; k < 3; ++k) L.dx[k] = k < plan->data.dim ? v.dx[k] : 1.0;
+  L.npred = v.npred;
+  L.nupd = v.nupd;
+  L.pred_cells = v.pred_cells;
+  L.pred_patch = v.pred_patch;
+  L.upd = v.upd;
+  L.upd_nbr = v.upd_nbr;
+  return hip_status(plan->impl->step_level(plan->data, L, u_in, u_out, ld, dt_dev, (char*)ws,
+                                           (hipStream_t)stream),
+                    "ader_step_level");
+}
+
 ader_status ader_read_status(ader_plan plan, const void* ws, uint32_t* flags,
                              uint64_t* picard_iterations, void* stream) {
   if (!plan || !flags) return fail(ADER_EINVAL, "null argument");

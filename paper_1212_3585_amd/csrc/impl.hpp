@@ -5,6 +5,7 @@
 
 #include "plan.hpp"
 #include "fused2d.hpp"
+#include "level.hpp"
 #include "predict_mfma.hpp"
 
 namespace ader {
@@ -105,6 +106,68 @@ struct Impl final : ImplBase {
     return step_stages(p, u_in, u_out, ld, dt, ws, st);
   }
 
+  LevelLayout level_layout(const PlanData& p, int64_t npred) const override {
+    return level_layout_for<DIM, M, SYS, R>(p, npred);
+  }
+
+  // one step over a level's cell lists (patch WENO, predictor, update)
+  hipError_t step_level(const PlanData& p, const LevelArgs& L, const double* u_in,
+                        double* u_out, int64_t ld, const double* dt, char* ws,
+                        hipStream_t st) const override {
+    constexpr int S = 2 * M + 1;
+    constexpr int NS = Pow<n, DIM>::v;
+    const LevelLayout lay = level_layout(p, L.npred);
+    WsHeader* hdr = reinterpret_cast<WsHeader*>(ws);
+    double* A = reinterpret_cast<double*>(ws + lay.off_a);
+    double* B = reinterpret_cast<double*>(ws + lay.off_b);
+    double* wh = reinterpret_cast<double*>(ws + lay.off_wh);
+    R* qh = reinterpret_cast<R*>(ws + lay.off_qh);
+    MeshParams mp = p.mp;
+    for (int k = 0; k < 3; ++k) mp.dx[k] = L.dx[k];
+    mp.ld = ld;
+    unsigned int* flags = &hdr->status;
+    if (L.npred > 0) {
+      StageTimer timer(&p.prof, ADER_STAGE_WENO, st);
+      const int64_t l0 = L.npred * NV * Pow<S, DIM - 1>::v;
+      // pass 0 -> A; pass 1 -> w_h (2D) or B (3D); pass 2 (3D) -> w_h
+      hipLaunchKernelGGL((k_level_weno_pass<DIM, M, NV, 0>), dim3(blocks_for(l0)), dim3(kBlock),
+                         0, st, u_in, ld, L.pred_patch, (const double*)nullptr, A, L.npred,
+                         p.dc, flags);
+      const int64_t l1 = L.npred * NV * n * Pow<S, DIM - 2>::v;
+      hipLaunchKernelGGL((k_level_weno_pass<DIM, M, NV, 1>), dim3(blocks_for(l1)), dim3(kBlock),
+                         0, st, u_in, ld, L.pred_patch, (const double*)A, DIM == 2 ? wh : B,
+                         L.npred, p.dc, flags);
+      if constexpr (DIM == 3) {
+        const int64_t l2 = L.npred * NV * n * n;
+        hipLaunchKernelGGL((k_level_weno_pass<DIM, M, NV, 2>), dim3(blocks_for(l2)),
+                           dim3(kBlock), 0, st, u_in, ld, L.pred_patch, (const double*)B, wh,
+                           L.npred, p.dc, flags);
+      }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (L.npred > 0) {
+      StageTimer timer(&p.prof, ADER_STAGE_PREDICT, st);
+      if constexpr (DIM == 2 && std::is_same<R, double>::value) {
+        hipLaunchKernelGGL((k_predict_mfma2d<M, SYS, R>),
+                           dim3(blocks_for(L.npred, 4 * (kBlock / 64))), dim3(kBlock), 0, st,
+                           (const double*)wh, qh, L.npred, dt, mp, p.dc, hdr);
+      } else {
+        hipLaunchKernelGGL((k_predict<DIM, M, SYS, R, R>),
+                           dim3(blocks_for(L.npred, kBlock / NS)), dim3(kBlock), 0, st,
+                           (const double*)wh, qh, L.npred, dt, mp, p.dc, hdr);
+      }
+    }
+    if (L.nupd > 0) {
+      StageTimer timer(&p.prof, ADER_STAGE_UPDATE, st);
+      hipLaunchKernelGGL((k_level_update<DIM, M, SYS, R>), dim3(blocks_for(L.nupd)),
+                         dim3(kBlock), 0, st, (const R*)qh, L.pred_cells, L.upd, L.upd_nbr,
+                         L.nupd, L.npred, u_in, u_out, ld, dt, L.dx[0], L.dx[1], L.dx[2], mp,
+                         p.dc, hdr);
+    }
+    return hipGetLastError();
+  }
+
   // 2D: cell kernel (WENO + predictor + traces) and face kernel
   hipError_t step_fused2d(const PlanData& p, const double* u_in, double* u_out, int64_t ld,
                           const double* dt, char* ws, hipStream_t st) const {
@@ -157,6 +220,26 @@ struct Impl final : ImplBase {
     return hipGetLastError();
   }
 };
+
+template <int DIM, int M, int SYS, typename R>
+LevelLayout level_layout_for(const PlanData& p, int64_t npred) {
+  constexpr int n = M + 1, S = 2 * M + 1, NV = NVars<SYS, DIM>::v;
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t np = (size_t)(npred > 0 ? npred : 1);
+  LevelLayout L;
+  size_t off = kHeaderBytes;
+  L.off_a = off;
+  off = al(off + sizeof(double) * np * NV * n * Pow<S, DIM - 1>::v);
+  L.off_b = off;
+  off = al(off + (DIM == 3 ? sizeof(double) * np * NV * n * n * S : 0));
+  L.off_wh = off;
+  off = al(off + sizeof(double) * np * NV * Pow<n, DIM>::v);
+  L.off_qh = off;
+  off = al(off + sizeof(R) * np * NV * Pow<n, DIM + 1>::v);
+  L.bytes = off;
+  (void)p;
+  return L;
+}
 
 template <int DIM, int M>
 const ImplBase* pick_impl(int sys, int prec) {

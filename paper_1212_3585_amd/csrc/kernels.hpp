@@ -65,7 +65,8 @@ struct WsHeader {
 constexpr size_t kHeaderBytes = 1024;
 static_assert(sizeof(WsHeader) <= kHeaderBytes, "workspace header");
 
-constexpr unsigned int kFlagNan = 1u, kFlagNonPhysical = 2u, kFlagNoConv = 4u;
+constexpr unsigned int kFlagNan = 1u, kFlagNonPhysical = 2u, kFlagNoConv = 4u,
+                       kFlagBadIndex = 8u;
 
 // Adds each thread's (Picard sweeps, status bits) to the workspace header
 // with one global atomic of each kind per block (block-level reduction in

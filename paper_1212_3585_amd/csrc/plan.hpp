@@ -68,6 +68,21 @@ struct PlanData {
   mutable Profiler prof;
 };
 
+// A level view after validation (device pointers).
+struct LevelArgs {
+  double dx[3];
+  int64_t npred, nupd;
+  const int32_t* pred_cells;
+  const int32_t* pred_patch;
+  const int32_t* upd;
+  const int32_t* upd_nbr;
+};
+
+// Level workspace: header | pass scratch A | pass scratch B | w_h | q_h
+struct LevelLayout {
+  size_t off_a, off_b, off_wh, off_qh, bytes;
+};
+
 // Per-(dim, M, system, precision) launcher set.
 struct ImplBase {
   virtual ~ImplBase() = default;
@@ -82,6 +97,10 @@ struct ImplBase {
                                    hipStream_t st) const = 0;
   virtual hipError_t step(const PlanData& p, const double* u_in, double* u_out, int64_t ld,
                           const double* dt, char* ws, hipStream_t st) const = 0;
+  virtual LevelLayout level_layout(const PlanData& p, int64_t npred) const = 0;
+  virtual hipError_t step_level(const PlanData& p, const LevelArgs& L, const double* u_in,
+                                double* u_out, int64_t ld, const double* dt, char* ws,
+                                hipStream_t st) const = 0;
 };
 
 const ImplBase* make_impl_2d(int M, int sys, int prec);

@@ -121,3 +121,37 @@ def test_device_path_constants_agree_with_oracle(ader_mod, M):
     A = np.linalg.solve(b.time_matrix(), np.diag(b.weights))
     np.testing.assert_allclose(arrs[3].reshape(n, n), A, rtol=0, atol=1e-14)
     lib.ader_plan_destroy(plan)
+
+
+def test_step_level_validates_before_launching(ader_mod):
+    lib = ader_mod.load_library()
+    st, plan = _create(ader_mod, dim=2, M=2, n=(8, 8, 1))
+    assert st == 0
+    fake = ctypes.c_void_p(0x10000)
+    out = ctypes.c_void_p(0x90000)
+    ws = ctypes.c_void_p(0x20000)
+    dt = ctypes.c_void_p(0x30000)
+    V = ader_mod.CLevelView
+    ok = dict(npred=4, pred_cells=0x40000, pred_patch=0x50000, nupd=2, upd=0x60000,
+              upd_nbr=0x70000)
+
+    def call(**over):
+        kw = dict(ok, **over)
+        v = V()
+        v.dx[:] = kw.pop("dx", [0.1, 0.1, 1.0])
+        for k, val in kw.items():
+            setattr(v, k, val)
+        return lib.ader_step_level(plan, ctypes.byref(v), fake, out, 64, dt, ws, None)
+    assert call(nupd=5) == -1                 # more updated than predicted
+    assert call(npred=-1) == -1
+    assert call(pred_patch=None) == -1
+    assert call(upd_nbr=None) == -1
+    assert call(dx=[0.0, 0.1, 1.0]) == -1
+    v = V()
+    v.dx[:] = [0.1, 0.1, 1.0]
+    assert lib.ader_step_level(plan, ctypes.byref(v), fake, fake, 64, dt, ws, None) == -1
+    assert lib.ader_step_level(plan, None, fake, out, 64, dt, ws, None) == -1
+    b = ctypes.c_size_t()
+    assert lib.ader_level_workspace_bytes(plan, 1000, ctypes.byref(b)) == 0 and b.value > 0
+    assert lib.ader_level_workspace_bytes(plan, -1, ctypes.byref(b)) == -1
+    lib.ader_plan_destroy(plan)

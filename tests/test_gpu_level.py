@@ -1,0 +1,93 @@
+"""ader_step_level: one step over explicit cell lists, against ader_step and
+the oracle (pooled relative L1 <= 1e-11)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1212_3585_amd import workloads as wl
+
+from gpu_helpers import from_device, make_pair, rel_l1, say, to_device
+from level_views import mesh_level_view
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.tensor(a, dtype=torch.int32, device="cuda")
+
+
+def _step_level(ader, s, U, shape, M, bcs, dx, cells=None, dt=None):
+    import torch
+    pc, pp, up, nb = mesh_level_view(shape, M, bcs, cells)
+    u = to_device(U)
+    out = u.clone()
+    if dt is None:
+        s.compute_dt(u)
+    else:
+        s.dt.copy_(torch.tensor([dt], dtype=torch.float64))
+    s.step_level(_dev(pc), _dev(pp), _dev(up), _dev(nb), dx, u, out)
+    return u, out
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_level_covering_the_mesh_equals_step(ader, precision):
+    say(f"level = whole periodic mesh, 24x20 M=3, precision {precision}")
+    shape = (24, 20)
+    U = wl.perturbed_smooth_euler(shape, 60)
+    op, gp = make_pair(ader, 2, 3, shape, (0, 0), (1, 1), precision=precision,
+                       tol=1e-14 if precision == 0 else 1e-6)
+    s = ader.Solver(gp)
+    u, out = _step_level(ader, s, U, shape, 3, ["periodic"] * 2, op.dx)
+    ref = s.empty_state()
+    s.step(u, ref)
+    a, b = from_device(out, shape), from_device(ref, shape)
+    assert rel_l1(a, b) <= (1e-13 if precision == 0 else 1e-6)
+    if precision == 0:
+        Uo, _ = oracle.step(op, U, oracle.cfl_dt(op, U))
+        assert rel_l1(a, Uo) <= 1e-11
+    assert s.read_level_status()[0] == 0
+
+
+def test_level_3d_transmissive_against_oracle(ader):
+    say("level = whole 3D mesh, 9x8x7 M=2, transmissive")
+    shape = (9, 8, 7)
+    U = wl.perturbed_smooth_euler(shape, 61)
+    op, gp = make_pair(ader, 3, 2, shape, (0,) * 3, (1,) * 3, "transmissive")
+    s = ader.Solver(gp)
+    u, out = _step_level(ader, s, U, shape, 2, ["transmissive"] * 3, op.dx)
+    Uo, _ = oracle.step(op, U, oracle.cfl_dt(op, U))
+    assert rel_l1(from_device(out, shape), Uo) <= 1e-11
+
+
+def test_level_subset_band(ader):
+    say("level = band of rows 10..19 of a 40x40 KH mesh, M=3")
+    N = 40
+    U = wl.kelvin_helmholtz(N, seed=4, amp=0.05)
+    op, gp = make_pair(ader, 2, 3, (N, N), (0, 0), (1, 1))
+    s = ader.Solver(gp)
+    cells = np.array([[i, j] for j in range(10, 20) for i in range(N)])
+    dt = oracle.cfl_dt(op, U)
+    u, out = _step_level(ader, s, U, (N, N), 3, ["periodic"] * 2, op.dx, cells, dt)
+    got = from_device(out, (N, N))
+    ref, _ = oracle.step_cells(op, U, dt, cells)
+    assert rel_l1(got[:, cells[:, 0], cells[:, 1]], ref) <= 1e-11
+    mask = np.ones((N, N), bool)
+    mask[cells[:, 0], cells[:, 1]] = False
+    assert np.array_equal(got[:, mask], U[:, mask])   # cells outside the level untouched
+
+
+def test_level_bad_index_is_flagged(ader):
+    say("level with an out-of-range neighbour position")
+    shape = (8, 8)
+    U = wl.perturbed_smooth_euler(shape, 62)
+    op, gp = make_pair(ader, 2, 2, shape, (0, 0), (1, 1))
+    s = ader.Solver(gp)
+    pc, pp, up, nb = mesh_level_view(shape, 2, ["periodic"] * 2)
+    nb = nb.copy()
+    nb[5] = len(pc) + 7
+    u = to_device(U)
+    out = u.clone()
+    s.compute_dt(u)
+    s.step_level(_dev(pc), _dev(pp), _dev(up), _dev(nb), op.dx, u, out)
+    assert s.read_level_status()[0] & ader.FLAG_BADINDEX
