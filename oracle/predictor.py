@@ -21,8 +21,10 @@ iteration of eq. stdg.final,
 
 from the initial guess q_hat^0 = w_hat at every time node (the paper cites a
 MUSCL-type guess whose formula it does not give; the fixed point does not
-depend on the guess).  A cell stops when
-max |q^(k+1) - q^k| <= tol * max(1, max |q^(k+1)|).
+depend on the guess).  The paper gives no stopping rule; a cell stops at
+the first iteration with max |q^(k+1) - q^k| <= tol * max(1, max |w_hat|),
+the maxima taken over the cell's variables and nodes, so the threshold is
+fixed by the reconstructed data before the iteration starts.
 
 Index conventions: spatial nodal index a = p_x + n p_y (+ n^2 p_z); the
 space-time index is a + n^d s, time slowest.  F^0 is read with the spatial
@@ -99,6 +101,7 @@ def predict(system, w: np.ndarray, courant: list, M: int, dim: int,
     q = np.tile(wf, n)                                     # q^0 = w_hat
     iters = np.zeros(C, dtype=np.int64)
     done = np.zeros(C, dtype=bool)
+    scale = np.maximum(1.0, np.max(np.abs(wf), axis=(0, 2)))   # per cell
     for it in range(1, max_iter + 1):
         act = ~done
         qa = q[:, act]
@@ -107,10 +110,9 @@ def predict(system, w: np.ndarray, courant: list, M: int, dim: int,
             fk = system.flux(qa, k) * cour[k][act][None, :, None]
             qn -= fk @ Pk[k].T
         delta = np.max(np.abs(qn - qa), axis=(0, 2))
-        scale = np.maximum(1.0, np.max(np.abs(qn), axis=(0, 2)))
         q[:, act] = qn
         iters[act] = it
-        newly = delta <= tol * scale
+        newly = delta <= tol * scale[act]
         idx = np.flatnonzero(act)
         done[idx[newly]] = True
         if done.all():

@@ -35,6 +35,8 @@
 namespace ader {
 
 constexpr int kCellTX = 4;  // tile width of the cell kernel = cells per wavefront
+// lanes of matrix block b1 = 0 (b0 + 16 b2); block b1 is this mask << 4 b1
+constexpr uint64_t kCellLanes = 0x000F000F000F000FULL;
 
 // fp32 lane exchanges without the LDS crossbar (gfx950):
 //   lane ^ 1, ^ 2, ^ 3 : DPP quad permutations;
@@ -196,7 +198,13 @@ k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
 #pragma unroll
     for (int s = 0; s < n; ++s) q[v][s] = w[v];
 
-  const R tol = (R)mp.tol;
+  // stopping threshold of the cell, fixed before the iteration:
+  // tol * max(1, max |w_hat|) over the cell's variables and nodes
+  R wmax = R(0);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) wmax = fmax(wmax, fabs(w[v]));
+  const R thr = (R)mp.tol * fmax(R(1), cell_max_r<R>(node_ok ? wmax : R(0)));
+  const uint64_t cell_lanes = kCellLanes << (4 * b1);
   bool done = !cell_ok;
   int iters = 0;
   for (int it = 1; it <= mp.maxit; ++it) {
@@ -219,7 +227,7 @@ k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
         }
       }
     }
-    R delta = R(0), mag = R(0);
+    R delta = R(0);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
 #pragma unroll
@@ -230,13 +238,12 @@ k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
           acc += cget<R>(c.tinvw[s][sp], c.tinvw_f[s][sp]) * Rs[v][sp];
         const R qn = w[v] - acc;
         delta = fmax(delta, fabs(qn - q[v][s]));
-        mag = fmax(mag, fabs(qn));
         q[v][s] = qn;
       }
     }
-    delta = cell_max_r<R>(node_ok ? delta : R(0));
-    mag = cell_max_r<R>(node_ok ? mag : R(0));
-    if (!done && delta <= tol * fmax(R(1), mag)) {
+    // a cell has converged when none of its 16 lanes moved by more than thr
+    const uint64_t moved = __ballot(node_ok && !(delta <= thr));
+    if (!done && (moved & cell_lanes) == 0) {
       done = true;
       iters = it;
     }

@@ -383,14 +383,22 @@ k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
 #pragma unroll
     for (int s = 0; s < n; ++s) q[v][s] = w[v];
 
-  const R tol = (R)mp.tol;
+  // stopping threshold of the cell, fixed before the iteration:
+  // tol * max(1, max |w_hat|) over the cell's variables and nodes
+  if (tid < CPB) shMag[tid] = 0;
+  __syncthreads();
+  {
+    R wmax = R(0);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) wmax = fmax(wmax, fabs(w[v]));
+    if (active) atomicMax(&shMag[lc], Bits<R>::of(wmax));
+  }
+  __syncthreads();
+  const R thr = (R)mp.tol * fmax(R(1), lc < CPB ? Bits<R>::val(shMag[lc]) : R(0));
   bool done = !active;
   int iters = 0;
   for (int it = 1; it <= mp.maxit; ++it) {
-    if (tid < CPB) {
-      shDelta[tid] = 0;
-      shMag[tid] = 0;
-    }
+    if (tid < CPB) shDelta[tid] = 0;
     R Racc[NV][n];
 #pragma unroll
     for (int s = 0; s < n; ++s) {
@@ -422,7 +430,7 @@ k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
       }
       __syncthreads();
     }
-    R delta = R(0), mag = R(0);
+    R delta = R(0);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
 #pragma unroll
@@ -433,19 +441,14 @@ k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
           acc += cget<R>(c.tinvw[s][sp], c.tinvw_f[s][sp]) * Racc[v][sp];
         const R qn = w[v] - acc;
         delta = fmax(delta, fabs(qn - q[v][s]));
-        mag = fmax(mag, fabs(qn));
         if (!done) q[v][s] = qn;
       }
     }
-    if (!done) {
-      atomicMax(&shDelta[lc], Bits<R>::of(delta));
-      atomicMax(&shMag[lc], Bits<R>::of(mag));
-    }
+    if (!done) atomicMax(&shDelta[lc], Bits<R>::of(delta));
     __syncthreads();
     if (!done) {
       const R dcell = Bits<R>::val(shDelta[lc]);
-      const R mcell = Bits<R>::val(shMag[lc]);
-      if (dcell <= tol * fmax(R(1), mcell)) {
+      if (dcell <= thr) {
         done = true;
         iters = it;
       }

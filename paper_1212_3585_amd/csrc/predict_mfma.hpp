@@ -17,8 +17,9 @@
 //     p_y and returns the home layout, accumulated onto the x part;
 //   * time product with (time factor of K^1)^-1 diag(w) and the update
 //     q = w_hat - ... are lane-local.
-// A cell stops counting iterations when its relative update falls below the
-// tolerance; the wavefront sweeps until its last cell has converged.
+// A cell stops counting iterations when its largest update falls below
+// tol * max(1, max |w_hat|); the wavefront sweeps until its last cell has
+// converged.
 // Degrees M < 3 pad the node axes to four with zero matrix entries and a
 // benign state in the padding lanes.
 #pragma once
@@ -85,7 +86,13 @@ k_predict_mfma2d(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t nc
 #pragma unroll
     for (int s = 0; s < n; ++s) q[v][s] = w[v];
 
-  const double tol = mp.tol;
+  // stopping threshold of the cell, fixed before the iteration:
+  // tol * max(1, max |w_hat|) over the cell's variables and nodes
+  double wmax = 0.0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) wmax = fmax(wmax, fabs(w[v]));
+  const double thr = mp.tol * fmax(1.0, cell_max(node_ok ? wmax : 0.0));
+  const uint64_t cell_lanes = 0x000F000F000F000FULL << (4 * b1);
   bool done = !cell_ok;
   int iters = 0;
   for (int it = 1; it <= mp.maxit; ++it) {
@@ -104,7 +111,7 @@ k_predict_mfma2d(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t nc
         R[v][s] = __builtin_amdgcn_mfma_f64_4x4x4f64(gt, my, rx, 0, 0, 0);
       }
     }
-    double delta = 0.0, mag = 0.0;
+    double delta = 0.0;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
 #pragma unroll
@@ -114,17 +121,16 @@ k_predict_mfma2d(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t nc
         for (int sp = 0; sp < n; ++sp) acc += c.tinvw[s][sp] * R[v][sp];
         const double qn = w[v] - acc;
         delta = fmax(delta, fabs(qn - q[v][s]));
-        mag = fmax(mag, fabs(qn));
         // a cell that has converged keeps sweeping with its wavefront: each
         // further sweep moves q by less than the tolerance towards the fixed
         // point (its iteration count is the one at first convergence)
         q[v][s] = qn;
       }
     }
-    // padding lanes hold a constant state: their delta is zero
-    delta = cell_max(node_ok ? delta : 0.0);
-    mag = cell_max(node_ok ? mag : 0.0);
-    if (!done && delta <= tol * fmax(1.0, mag)) {
+    // converged: none of the cell's lanes moved by more than thr (padding
+    // lanes hold a constant state and take no part)
+    const uint64_t moved = __ballot(node_ok && !(delta <= thr));
+    if (!done && (moved & cell_lanes) == 0) {
       done = true;
       iters = it;
     }
