@@ -4,17 +4,19 @@
 // (fp32 FMAs on exchanged lane values, fp32 accumulation).
 //
 // k_cell2d   one block = a 4 x TY tile of cells, TY wavefronts; wavefront w
-//            holds the tile's row w, one cell per matrix block b1.
+//            holds the tile's row w (16 lanes per cell).
 //   1. the averages of the tile plus M ghost layers are staged in LDS
 //      (periodic or zero-gradient ghosts);
 //   2. WENO x pass (Section 2.2, eqs. rec.x, sigmas, omegas, weno) on every
 //      row of the tile and M rows above and below, into LDS;
 //   3. WENO y pass per x degree of freedom (eqs. rec.y, weno.y) -> w_h in LDS;
-//   4. Picard iteration of the space-time predictor on the matrix cores, as
-//      in predict_mfma.hpp (Section 2.3, eq. stdg.final);
+//   4. Picard iteration of the space-time predictor (Section 2.3, eq.
+//      stdg.final): fp64 on the matrix cores as in predict_mfma.hpp; fp32
+//      with DPP lane exchanges inside each cell's row of 16 lanes;
 //   5. predictor traces on the four faces at the face Gauss points in space
 //      and time (used by eqs. flux:F, flux:G): contraction with psi(0) and
-//      psi(1) along x by one MFMA, along y by a transpose and one MFMA.
+//      psi(1); fp64 along x by one MFMA, along y by a transpose and one
+//      MFMA; fp32 by the same DPP exchanges.
 //   Traces go to HBM as trace[face][cell][v][s][b] (b: transverse node,
 //   s: time node), face = x-low, x-high, y-low, y-high.
 //
@@ -38,47 +40,17 @@ constexpr int kCellTX = 4;  // tile width of the cell kernel = cells per wavefro
 // lanes of matrix block b1 = 0 (b0 + 16 b2); block b1 is this mask << 4 b1
 constexpr uint64_t kCellLanes = 0x000F000F000F000FULL;
 
-// fp32 lane exchanges without the LDS crossbar (gfx950):
-//   lane ^ 1, ^ 2, ^ 3 : DPP quad permutations;
-//   lane ^ 16          : v_permlane16_swap with both operands x -- the partner
-//                        value is returned in slot 1 on even rows of 16 lanes
-//                        and in slot 0 on odd rows;
-//   lane ^ 32          : v_permlane32_swap likewise (slot 1 for lanes < 32).
+// fp32 lane exchanges without the LDS crossbar: DPP quad permutations give
+// lane ^ 1, ^ 2, ^ 3 (the b0 axis); row rotations (below) the b1 axis.
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float x) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
 }
 constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kQuadXor3 = 0x1B;  // [1032] [2301] [3210]
 
-__device__ __forceinline__ float xor16_f(float x) {
-  const unsigned u = __float_as_uint(x);
-  const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
-  return __uint_as_float(((threadIdx.x >> 4) & 1) ? r[0] : r[1]);
-}
-__device__ __forceinline__ float xor32_f(float x) {
-  const unsigned u = __float_as_uint(x);
-  const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
-  return __uint_as_float(((threadIdx.x >> 5) & 1) ? r[0] : r[1]);
-}
-
-template <typename R>
-__device__ __forceinline__ R cell_max_r(R x);
-template <>
-__device__ __forceinline__ double cell_max_r<double>(double x) {
-  return cell_max(x);
-}
-template <>
-__device__ __forceinline__ float cell_max_r<float>(float x) {
-  x = fmaxf(x, dpp_f<kQuadXor1>(x));
-  x = fmaxf(x, dpp_f<kQuadXor2>(x));
-  x = fmaxf(x, xor16_f(x));
-  x = fmaxf(x, xor32_f(x));
-  return x;
-}
-
-// Lane-local coefficients of the exchange form (fp32 predictor): the node
-// p ^ m of the same line is fetched from lane ^ m (b0) or lane ^ 16 m (b2);
-// coef[m] = D[p][p ^ m] (zero where p ^ m is a padding node).
+// Lane-local coefficients of the quad exchange (fp32 predictor): the node
+// p ^ m of the same line is fetched from lane ^ m (b0 axis);
+// coef[m] = scale * D[p][p ^ m] (zero where p ^ m is a padding node).
 template <int n>
 __device__ __forceinline__ void xor_row(const DevConsts& c, int p, double scale, float (&coef)[4]) {
 #pragma unroll
@@ -93,14 +65,36 @@ __device__ __forceinline__ float xor_line_b0(float x, const float (&coef)[4]) {
   acc = fmaf(coef[3], dpp_f<kQuadXor3>(x), acc);
   return acc;
 }
-// sum_m coef[m] * x(lane ^ 16 m) across rows (the b2 axis), m = 0..3 in order
-__device__ __forceinline__ float xor_line_b2(float x, const float (&coef)[4]) {
-  const float x32 = xor32_f(x);
+// Row rotations inside each row of 16 lanes (DPP row_ror: lane i receives
+// lane (i - 4 m) mod 16 of its row for row_ror:4m), i.e. along the b1 axis
+// the lane with index p receives the value of index (p - m) mod 4.
+template <int CTRL>
+__device__ __forceinline__ float ror_f(float x) {
+  return dpp_f<CTRL>(x);
+}
+constexpr int kRowRor4 = 0x124, kRowRor8 = 0x128, kRowRor12 = 0x12C;
+
+// sum_m coef[m] * x(b1 index (p - m) mod 4), m = 0..3 in order
+__device__ __forceinline__ float ror_line_b1(float x, const float (&coef)[4]) {
   float acc = coef[0] * x;
-  acc = fmaf(coef[1], xor16_f(x), acc);
-  acc = fmaf(coef[2], x32, acc);
-  acc = fmaf(coef[3], xor16_f(x32), acc);
+  acc = fmaf(coef[1], ror_f<kRowRor4>(x), acc);
+  acc = fmaf(coef[2], ror_f<kRowRor8>(x), acc);
+  acc = fmaf(coef[3], ror_f<kRowRor12>(x), acc);
   return acc;
+}
+// coef[m] = scale * D[p][(p - m) mod 4] (zero where that node is padding)
+template <int n>
+__device__ __forceinline__ void ror_row(const DevConsts& c, int p, double scale, float (&coef)[4]) {
+#pragma unroll
+  for (int m = 0; m < 4; ++m) coef[m] = (float)(scale * pick_entry<n>(c.dmat, p, (p - m) & 3));
+}
+// maximum over the 16 lanes of a row
+__device__ __forceinline__ float row_max_f(float x) {
+  x = fmaxf(x, dpp_f<kQuadXor1>(x));
+  x = fmaxf(x, dpp_f<kQuadXor2>(x));
+  x = fmaxf(x, ror_f<kRowRor4>(x));
+  x = fmaxf(x, ror_f<kRowRor8>(x));
+  return x;
 }
 
 template <int M, int SYS, int TY, typename R>
@@ -164,34 +158,44 @@ k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
   }
   __syncthreads();
 
-  // 4. predictor: wavefront = tile row, b1 = tile column.  fp64: the
-  //    derivative products on the matrix cores; fp32: fp32 FMAs on values
-  //    fetched by xor shuffles (p_x across b2, p_y across b0)
+  // 4. predictor: wavefront = tile row, four cells per wavefront.  Lane
+  //    roles (b0, b1, b2) = (lane & 3, (lane >> 2) & 3, lane >> 4):
+  //    fp64: p_x = b2, p_y = b0, cell = b1 -- the matrix-core layout of
+  //          predict_mfma.hpp (one cell per matrix block);
+  //    fp32: p_x = b0, p_y = b1, cell = b2 -- a cell is a row of 16 lanes, so
+  //          both node axes are exchanged by DPP inside the row (p_x by quad
+  //          permutations, p_y by row rotations), fp32 FMAs, fp32 sums.
+  constexpr bool kMatrix = std::is_same<R, double>::value;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int b0 = lane & 3, b1 = (lane >> 2) & 3, b2 = lane >> 4;
-  const int gi = x0 + b1, gj = y0 + wave;
+  const int px = kMatrix ? b2 : b0;
+  const int py = kMatrix ? b0 : b1;
+  const int slot = kMatrix ? b1 : b2;
+  const int gi = x0 + slot, gj = y0 + wave;
   const bool cell_ok = gi < nx && gj < ny;
-  const bool node_ok = b0 < n && b2 < n;
+  const bool node_ok = px < n && py < n;
   const int64_t cell = gi + (int64_t)nx * gj;
-  const int cl = b1 + TX * wave;
+  const int cl = slot + TX * wave;
+  const bool lead = px == 0 && py == 0;  // first lane of the cell
+  // the 16 lanes of this lane's cell
+  const uint64_t cell_lanes = kMatrix ? kCellLanes << (4 * b1) : 0xFFFFULL << (16 * b2);
 
-  constexpr bool kMatrix = std::is_same<R, double>::value;
   const double dt = *dt_dev;
   const double dval = pick_entry<n>(c.dmat, b0, b2);
   const double mx = (dt / mp.dx[0]) * dval;
   const double my = (dt / mp.dx[1]) * dval;
   const double idv = (b0 == b2) ? 1.0 : 0.0;
-  float cxm[4], cym[4];
-  xor_row<n>(c, b2, dt / mp.dx[0], cxm);
-  xor_row<n>(c, b0, dt / mp.dx[1], cym);
+  float cxm[4], cyr[4];
+  xor_row<n>(c, px, dt / mp.dx[0], cxm);
+  ror_row<n>(c, py, dt / mp.dx[1], cyr);
   const R gamma = (R)mp.gamma;
   const R adv[3] = {(R)mp.adv[0], (R)mp.adv[1], (R)mp.adv[2]};
 
   R w[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v)
-    w[v] = node_ok ? (R)sWh[(cl * NV + v) * NS + b2 + n * b0] : (v == 0 || v == NV - 1 ? R(1) : R(0));
+    w[v] = node_ok ? (R)sWh[(cl * NV + v) * NS + px + n * py] : (v == 0 || v == NV - 1 ? R(1) : R(0));
   R q[NV][n];
 #pragma unroll
   for (int v = 0; v < NV; ++v)
@@ -203,8 +207,13 @@ k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
   R wmax = R(0);
 #pragma unroll
   for (int v = 0; v < NV; ++v) wmax = fmax(wmax, fabs(w[v]));
-  const R thr = (R)mp.tol * fmax(R(1), cell_max_r<R>(node_ok ? wmax : R(0)));
-  const uint64_t cell_lanes = kCellLanes << (4 * b1);
+  wmax = node_ok ? wmax : R(0);
+  R wcell;
+  if constexpr (kMatrix)
+    wcell = cell_max(wmax);
+  else
+    wcell = row_max_f(wmax);
+  const R thr = (R)mp.tol * fmax(R(1), wcell);
   bool done = !cell_ok;
   int iters = 0;
   for (int it = 1; it <= mp.maxit; ++it) {
@@ -223,7 +232,7 @@ k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
           const double gt = __builtin_amdgcn_mfma_f64_4x4x4f64(F[1][v], idv, 0.0, 0, 0, 0);
           Rs[v][s] = __builtin_amdgcn_mfma_f64_4x4x4f64(gt, my, rx, 0, 0, 0);
         } else {
-          Rs[v][s] = xor_line_b2(F[0][v], cxm) + xor_line_b0(F[1][v], cym);
+          Rs[v][s] = xor_line_b0(F[0][v], cxm) + ror_line_b1(F[1][v], cyr);
         }
       }
     }
@@ -250,16 +259,15 @@ k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
     if (!__any(!done)) break;
   }
   if (cell_ok && !done) iters = mp.maxit;
-  block_report(cell_ok && lane == 4 * b1 ? (unsigned)iters : 0u,
-               cell_ok && lane == 4 * b1 && !done ? kFlagNoConv : 0u, hdr);
+  block_report(cell_ok && lead ? (unsigned)iters : 0u,
+               cell_ok && lead && !done ? kFlagNoConv : 0u, hdr);
 
-  // 5. face traces.  x faces: operand A row 0 = psi(0), row 1 = psi(1)
+  // 5. face traces.  fp64: x faces: operand A row 0 = psi(0), row 1 = psi(1)
   //    (A[i=b0][k=b2]); result lane (b0 = y node, b2 = 0 / 1 = low / high).
-  //    y faces: transpose, then operand B column 0 = psi(0), column 1 = psi(1)
-  //    (B[k=b2][j=b0]); result lane (b0 = 0 / 1 = low / high, b2 = x node).
-  //    fp32: each lane forms, by lane exchanges, the four traces at its own
-  //    transverse node; lanes b2 = 0 write the x faces, lanes b0 = 0 the y
-  //    faces.
+  //    y faces: transpose, then operand B column 0 = psi(0), column 1 =
+  //    psi(1) (B[k=b2][j=b0]); result lane (b0 = 0 / 1 = low / high, b2 = x
+  //    node).  fp32: every lane forms the traces of its own line by DPP
+  //    exchanges; lanes p_x = 0 write the x faces, lanes p_y = 0 the y faces.
   const int64_t C = mp.ncells;
   constexpr int TRC = NV * n * n;  // values per trace
   if constexpr (kMatrix) {
@@ -286,16 +294,18 @@ k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
       }
     }
   } else {
+    // e?x[m]: weight of node p_x ^ m (quad exchange); e?y[m]: weight of
+    // node (p_y - m) mod 4 (row rotation); zero for padding nodes
     float e0x[4], e1x[4], e0y[4], e1y[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       float a0 = 0.f, a1 = 0.f, c0 = 0.f, c1 = 0.f;
 #pragma unroll
       for (int k = 0; k < n; ++k) {
-        a0 = ((b2 ^ m) == k) ? c.psi0_f[k] : a0;
-        a1 = ((b2 ^ m) == k) ? c.psi1_f[k] : a1;
-        c0 = ((b0 ^ m) == k) ? c.psi0_f[k] : c0;
-        c1 = ((b0 ^ m) == k) ? c.psi1_f[k] : c1;
+        a0 = ((px ^ m) == k) ? c.psi0_f[k] : a0;
+        a1 = ((px ^ m) == k) ? c.psi1_f[k] : a1;
+        c0 = (((py - m) & 3) == k) ? c.psi0_f[k] : c0;
+        c1 = (((py - m) & 3) == k) ? c.psi1_f[k] : c1;
       }
       e0x[m] = a0;
       e1x[m] = a1;
@@ -307,16 +317,16 @@ k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
 #pragma unroll
       for (int s = 0; s < n; ++s) {
         const R x = q[v][s];
-        const R tx0 = xor_line_b2(x, e0x), tx1 = xor_line_b2(x, e1x);
-        const R ty0 = xor_line_b0(x, e0y), ty1 = xor_line_b0(x, e1y);
+        const R tx0 = xor_line_b0(x, e0x), tx1 = xor_line_b0(x, e1x);
+        const R ty0 = ror_line_b1(x, e0y), ty1 = ror_line_b1(x, e1y);
         if (cell_ok) {
-          if (b2 == 0 && b0 < n) {
-            traces[((int64_t)0 * C + cell) * TRC + (v * n + s) * n + b0] = tx0;
-            traces[((int64_t)1 * C + cell) * TRC + (v * n + s) * n + b0] = tx1;
+          if (px == 0 && py < n) {
+            traces[((int64_t)0 * C + cell) * TRC + (v * n + s) * n + py] = tx0;
+            traces[((int64_t)1 * C + cell) * TRC + (v * n + s) * n + py] = tx1;
           }
-          if (b0 == 0 && b2 < n) {
-            traces[((int64_t)2 * C + cell) * TRC + (v * n + s) * n + b2] = ty0;
-            traces[((int64_t)3 * C + cell) * TRC + (v * n + s) * n + b2] = ty1;
+          if (py == 0 && px < n) {
+            traces[((int64_t)2 * C + cell) * TRC + (v * n + s) * n + px] = ty0;
+            traces[((int64_t)3 * C + cell) * TRC + (v * n + s) * n + px] = ty1;
           }
         }
       }
