@@ -208,6 +208,75 @@ ader_status ader_debug_constants(ader_plan plan, double* nodes, double* weights,
 ader_status ader_profile_begin(ader_plan plan);
 ader_status ader_profile_end(ader_plan plan, double* stage_ms, int64_t* stage_launches);
 
+/* ------------------------------------------------------------------------
+ * Solve server: continuous batching of independent 2D solves.
+ *
+ * A server keeps many independent solves (problem + initial averages + end
+ * time, each advanced with the CFL step of ader_compute_dt until t_end, as
+ * ader_step does) resident on one GPU and advances them together.
+ *   - Admission by HBM footprint: the server owns one device arena of
+ *     hbm_bytes; a submitted solve waits in a FIFO queue until a slot and
+ *     arena space for its two state buffers and its workspace are free
+ *     (ader_server_footprint gives the bytes).  It is then uploaded and joins
+ *     the next round of its kernel group.
+ *   - Rounds: all resident solves with the same (M, system, precision) form a
+ *     group; one round advances every solve of the group by one step with
+ *     three launches whose grids cover all of them (CFL step, cell kernel,
+ *     face kernel).  Each solve's time lives on the device: a round computes
+ *     its dt = min(CFL / max, t_end - t) and t += dt, and a solve that has
+ *     reached t_end costs nothing further.  Groups are spread over the
+ *     server's streams (default priority) and overlap on the device.
+ *   - The host reads a small table of solve clocks after each round (pinned
+ *     memory, asynchronous) to retire finished solves: their averages are
+ *     copied to the caller's output buffer and their slot and memory freed.
+ * The per-solve arithmetic is that of ader_step: a result is bitwise the
+ * same whichever other solves share its rounds.
+ *
+ * Threading: a server is driven from one host thread.  u0 and u_out are host
+ * arrays [nvar][cells] (x fastest); u0 is copied at submit, u_out must stay
+ * valid until the request is done.  Only dim = 2 problems are served. */
+typedef struct ader_server_s* ader_server;
+
+typedef struct {
+  size_t hbm_bytes;  /* device arena for resident solves (>= 1 MiB) */
+  int max_slots;     /* solves resident at once, 1..4096 */
+  int streams;       /* HIP streams the groups are spread over, 1..16 */
+  int rounds_ahead;  /* rounds a group may have in flight, 1..8 */
+} ader_server_config;
+
+typedef struct {
+  int state;                   /* 0 queued, 1 resident, 2 done, 3 failed */
+  uint32_t flags;              /* ADER_FLAG_* of the solve (when done) */
+  uint64_t steps;              /* steps taken */
+  uint64_t picard_iterations;  /* predictor iterations summed over cells and steps */
+  double t;                    /* time reached */
+  double submit_s, admit_s, done_s;  /* host monotonic clock, seconds */
+} ader_request_info;
+
+typedef struct {
+  size_t arena_bytes, bytes_in_use, peak_bytes_in_use;
+  int resident, peak_resident, queued;
+  int64_t rounds, launches, completed;
+} ader_server_stats;
+
+ader_status ader_server_create(const ader_server_config* config, ader_server* out);
+/* Waits for the device work of the server, then frees everything it owns.
+ * Requests not done by then stay not done. */
+ader_status ader_server_destroy(ader_server server);
+/* Device bytes a problem occupies while resident. */
+ader_status ader_server_footprint(const ader_problem* prob, size_t* bytes);
+/* Queue one solve: EINVAL / EUNSUPPORTED for a bad problem, t_end <= 0 or
+ * non-finite, or a footprint above the arena (it could never be admitted). */
+ader_status ader_server_submit(ader_server server, const ader_problem* prob,
+                               const double* u0, double t_end, double* u_out,
+                               int64_t* id);
+/* One scheduling pass: retire finished solves, admit queued ones, launch the
+ * next round of every group with room.  wait != 0 blocks until at least one
+ * in-flight round or retirement completes (if there is any). */
+ader_status ader_server_progress(ader_server server, int wait, int* resident, int* queued);
+ader_status ader_server_request(ader_server server, int64_t id, ader_request_info* info);
+ader_status ader_server_stats_get(ader_server server, ader_server_stats* stats);
+
 const char* ader_status_string(ader_status status);
 const char* ader_last_error(void);
 

@@ -28,8 +28,12 @@ EXPORTS = [
     "ader_debug_reconstruct", "ader_debug_predict", "ader_read_status",
     "ader_debug_constants", "ader_profile_begin", "ader_profile_end",
     "ader_level_workspace_bytes", "ader_step_level",
+    "ader_server_create", "ader_server_destroy", "ader_server_footprint",
+    "ader_server_submit", "ader_server_progress", "ader_server_request",
+    "ader_server_stats_get",
     "ader_status_string", "ader_last_error",
 ]
+REQ_QUEUED, REQ_RESIDENT, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 STAGES = ["dt", "weno", "predict", "flux", "update"]
 
 
@@ -57,6 +61,26 @@ class CLevelView(ctypes.Structure):
         ("pred_patch", ctypes.c_void_p), ("nupd", ctypes.c_int64),
         ("upd", ctypes.c_void_p), ("upd_nbr", ctypes.c_void_p),
     ]
+
+
+class CServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int),
+                ("streams", ctypes.c_int), ("rounds_ahead", ctypes.c_int)]
+
+
+class CRequestInfo(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int), ("flags", ctypes.c_uint32),
+                ("steps", ctypes.c_uint64), ("picard_iterations", ctypes.c_uint64),
+                ("t", ctypes.c_double), ("submit_s", ctypes.c_double),
+                ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
+class CServerStats(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_size_t), ("bytes_in_use", ctypes.c_size_t),
+                ("peak_bytes_in_use", ctypes.c_size_t), ("resident", ctypes.c_int),
+                ("peak_resident", ctypes.c_int), ("queued", ctypes.c_int),
+                ("rounds", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("completed", ctypes.c_int64)]
 
 
 _lib = None
@@ -89,6 +113,15 @@ def load_library():
         "ader_profile_end": [vp, vp, vp],
         "ader_level_workspace_bytes": [vp, i64, ctypes.POINTER(ctypes.c_size_t)],
         "ader_step_level": [vp, ctypes.POINTER(CLevelView), vp, vp, i64, vp, vp, vp],
+        "ader_server_create": [ctypes.POINTER(CServerConfig), ctypes.POINTER(vp)],
+        "ader_server_destroy": [vp],
+        "ader_server_footprint": [ctypes.POINTER(CProblem), ctypes.POINTER(ctypes.c_size_t)],
+        "ader_server_submit": [vp, ctypes.POINTER(CProblem), vp, dbl, vp,
+                               ctypes.POINTER(i64)],
+        "ader_server_progress": [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                 ctypes.POINTER(ctypes.c_int)],
+        "ader_server_request": [vp, i64, ctypes.POINTER(CRequestInfo)],
+        "ader_server_stats_get": [vp, ctypes.POINTER(CServerStats)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -319,3 +352,85 @@ class Solver:
             steps += 1
             a, b = b, a
         return a, t, steps
+
+
+class Server:
+    """Solve server (ader_server_*): queue independent 2D solves, drive them
+    with progress(), read results and per-request timings.
+
+    Initial averages are numpy arrays [nvar, cells] or [nvar, nx, ny]
+    (x fastest in the flat form); results come back in the same shape."""
+
+    def __init__(self, hbm_bytes=8 << 30, max_slots=256, streams=4, rounds_ahead=2):
+        self.lib = load_library()
+        cfg = CServerConfig(hbm_bytes, max_slots, streams, rounds_ahead)
+        h = ctypes.c_void_p()
+        _check(self.lib.ader_server_create(ctypes.byref(cfg), ctypes.byref(h)),
+               "ader_server_create")
+        self._h = h
+        self._out = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.ader_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @staticmethod
+    def footprint(problem: Problem) -> int:
+        b = ctypes.c_size_t()
+        cp = problem.to_c()
+        _check(load_library().ader_server_footprint(ctypes.byref(cp), ctypes.byref(b)),
+               "ader_server_footprint")
+        return b.value
+
+    def submit(self, problem: Problem, u0: np.ndarray, t_end: float) -> int:
+        u0c = np.ascontiguousarray(u0, dtype=np.float64)
+        shape = u0c.shape
+        flat = u0c.reshape(shape[0], -1)
+        if shape[1:] and len(shape) == 3:   # [nv, nx, ny] -> x fastest
+            flat = np.ascontiguousarray(np.transpose(u0c, (0, 2, 1))).reshape(shape[0], -1)
+        out = np.empty_like(flat)
+        cp = problem.to_c()
+        rid = ctypes.c_int64()
+        _check(self.lib.ader_server_submit(self._h, ctypes.byref(cp),
+                                           flat.ctypes.data_as(ctypes.c_void_p), float(t_end),
+                                           out.ctypes.data_as(ctypes.c_void_p),
+                                           ctypes.byref(rid)), "ader_server_submit")
+        self._out[rid.value] = (out, shape)
+        return rid.value
+
+    def progress(self, wait=False):
+        r, q = ctypes.c_int(), ctypes.c_int()
+        _check(self.lib.ader_server_progress(self._h, int(bool(wait)), ctypes.byref(r),
+                                             ctypes.byref(q)), "ader_server_progress")
+        return r.value, q.value
+
+    def info(self, rid: int) -> dict:
+        inf = CRequestInfo()
+        _check(self.lib.ader_server_request(self._h, rid, ctypes.byref(inf)),
+               "ader_server_request")
+        return {f: getattr(inf, f) for f, _ in CRequestInfo._fields_}
+
+    def result(self, rid: int) -> np.ndarray:
+        out, shape = self._out[rid]
+        if len(shape) == 3:
+            return np.transpose(out.reshape(shape[0], shape[2], shape[1]), (0, 2, 1)).copy()
+        return out.reshape(shape)
+
+    def stats(self) -> dict:
+        st = CServerStats()
+        _check(self.lib.ader_server_stats_get(self._h, ctypes.byref(st)),
+               "ader_server_stats_get")
+        return {f: getattr(st, f) for f, _ in CServerStats._fields_}
+
+    def drain(self, ids=None):
+        """Drive progress() until the given requests (default: all) are done
+        or failed."""
+        ids = list(self._out) if ids is None else list(ids)
+        while True:
+            self.progress(wait=True)
+            if all(self.info(i)["state"] >= REQ_DONE for i in ids):
+                return

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libaderweno.so")
-SOURCES = ["consts.cpp", "capi.cpp", "impl2d.hip", "impl3d.hip"]
+SOURCES = ["consts.cpp", "capi.cpp", "server.cpp", "impl2d.hip", "impl3d.hip", "batch2d.hip"]
 ARCH = "gfx950"
 
 

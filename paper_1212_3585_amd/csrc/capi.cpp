@@ -15,8 +15,11 @@ struct ader_plan_s {
 };
 
 namespace {
-
 thread_local std::string g_last_error;
+bool is_finite(double x) { return std::isfinite(x); }
+}  // namespace
+
+namespace ader {
 
 ader_status fail(ader_status st, const std::string& msg) {
   g_last_error = msg;
@@ -28,9 +31,90 @@ ader_status hip_status(hipError_t e, const char* where) {
   return fail(ADER_EHIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+ader_status validate_problem(const ader_problem& pr, int64_t* ncells_out) {
+  if (pr.dim != 2 && pr.dim != 3) return fail(ADER_EUNSUPPORTED, "dim must be 2 or 3");
+  if (pr.M < 0 || pr.M > 3) return fail(ADER_EUNSUPPORTED, "M must be in 0..3");
+  if (pr.system != ADER_SYS_LINADV && pr.system != ADER_SYS_EULER)
+    return fail(ADER_EUNSUPPORTED, "unknown system");
+  if (pr.precision != ADER_PREC_FP64 && pr.precision != ADER_PREC_FP32_PREDICTOR)
+    return fail(ADER_EINVAL, "unknown precision");
+  int64_t ncells = 1;
+  for (int k = 0; k < pr.dim; ++k) {
+    if (pr.n[k] < 1) return fail(ADER_EINVAL, "cells per axis must be >= 1");
+    if (!is_finite(pr.lo[k]) || !is_finite(pr.hi[k]) || !(pr.hi[k] > pr.lo[k]))
+      return fail(ADER_EINVAL, "domain bounds must be finite with hi > lo");
+    if (pr.bc[k] != ADER_BC_PERIODIC && pr.bc[k] != ADER_BC_TRANSMISSIVE)
+      return fail(ADER_EINVAL, "unknown boundary condition");
+    ncells *= pr.n[k];
+  }
+  if (ncells > (int64_t(1) << 28)) return fail(ADER_EUNSUPPORTED, "more than 2^28 cells");
+  if (!is_finite(pr.cfl) || !(pr.cfl > 0.0) || pr.cfl > 1.0)
+    return fail(ADER_EINVAL, "cfl must be in (0, 1]");
+  if (pr.system == ADER_SYS_EULER && (!is_finite(pr.gamma) || !(pr.gamma > 1.0)))
+    return fail(ADER_EINVAL, "gamma must be > 1");
+  if (pr.system == ADER_SYS_LINADV)
+    for (int k = 0; k < 3; ++k)
+      if (!is_finite(pr.adv[k])) return fail(ADER_EINVAL, "advection velocity must be finite");
+  if (!is_finite(pr.picard_tol) || !(pr.picard_tol > 0.0))
+    return fail(ADER_EINVAL, "picard_tol must be > 0");
+  if (pr.picard_max < 1 || pr.picard_max > 1000)
+    return fail(ADER_EINVAL, "picard_max must be in 1..1000");
 
-bool is_finite(double x) { return std::isfinite(x); }
+  *ncells_out = ncells;
+  return ADER_OK;
+}
+
+void fill_dev_consts(const RefConstants& r, int M, DevConsts* out) {
+  DevConsts& c = *out;
+  std::memset(&c, 0, sizeof(c));
+  const int n = M + 1;
+  for (int a = 0; a < n; ++a) {
+    c.psi0[a] = (double)r.psi0[a];
+    c.psi1[a] = (double)r.psi1[a];
+    c.w[a] = (double)r.weights[a];
+    c.psi0_f[a] = (float)r.psi0[a];
+    c.psi1_f[a] = (float)r.psi1[a];
+    for (int b = 0; b < n; ++b) {
+      c.dmat[a][b] = (double)r.dmat[a][b];
+      c.tinvw[a][b] = (double)r.time_inv_w[a][b];
+      c.dmat_f[a][b] = (float)r.dmat[a][b];
+      c.tinvw_f[a][b] = (float)r.time_inv_w[a][b];
+      c.sigma[a][b] = (double)r.sigma[a][b];
+      for (int al = 0; al < M; ++al) c.dnode[al][a][b] = (double)r.dnode[al][a][b];
+    }
+  }
+  for (int s = 0; s < r.nstencils; ++s) {
+    c.lam[s] = (double)r.lambda[s];
+    for (int pp = 0; pp < n; ++pp)
+      for (int e = 0; e < n; ++e) c.rec_inv[s][pp][e] = (double)r.rec_inv[s][pp][e];
+  }
+}
+
+void fill_mesh_params(const ader_problem& pr, int64_t ncells, MeshParams* out) {
+  MeshParams& mp = *out;
+  std::memset(&mp, 0, sizeof(mp));
+  for (int k = 0; k < 3; ++k) {
+    const bool used = k < pr.dim;
+    mp.n[k] = used ? pr.n[k] : 1;
+    mp.bc[k] = used ? pr.bc[k] : 0;
+    mp.dx[k] = used ? (pr.hi[k] - pr.lo[k]) / pr.n[k] : 1.0;
+    mp.adv[k] = pr.system == ADER_SYS_LINADV ? pr.adv[k] : 0.0;
+  }
+  mp.gamma = pr.gamma;
+  mp.tol = pr.picard_tol;
+  mp.maxit = pr.picard_max;
+  mp.ncells = ncells;
+  mp.ld = ncells;
+}
+
+}  // namespace ader
+
+using ader::fail;
+using ader::hip_status;
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 ader_status check_ws(const ader_plan p, const void* ws) {
   if (!ws) return fail(ADER_EWORKSPACE, "workspace pointer is null");
@@ -67,33 +151,8 @@ ader_status ader_plan_create(const ader_problem* prob, ader_plan* out) {
   if (!prob || !out) return fail(ADER_EINVAL, "null argument");
   *out = nullptr;
   const ader_problem& pr = *prob;
-  if (pr.dim != 2 && pr.dim != 3) return fail(ADER_EUNSUPPORTED, "dim must be 2 or 3");
-  if (pr.M < 0 || pr.M > 3) return fail(ADER_EUNSUPPORTED, "M must be in 0..3");
-  if (pr.system != ADER_SYS_LINADV && pr.system != ADER_SYS_EULER)
-    return fail(ADER_EUNSUPPORTED, "unknown system");
-  if (pr.precision != ADER_PREC_FP64 && pr.precision != ADER_PREC_FP32_PREDICTOR)
-    return fail(ADER_EINVAL, "unknown precision");
-  int64_t ncells = 1;
-  for (int k = 0; k < pr.dim; ++k) {
-    if (pr.n[k] < 1) return fail(ADER_EINVAL, "cells per axis must be >= 1");
-    if (!is_finite(pr.lo[k]) || !is_finite(pr.hi[k]) || !(pr.hi[k] > pr.lo[k]))
-      return fail(ADER_EINVAL, "domain bounds must be finite with hi > lo");
-    if (pr.bc[k] != ADER_BC_PERIODIC && pr.bc[k] != ADER_BC_TRANSMISSIVE)
-      return fail(ADER_EINVAL, "unknown boundary condition");
-    ncells *= pr.n[k];
-  }
-  if (ncells > (int64_t(1) << 28)) return fail(ADER_EUNSUPPORTED, "more than 2^28 cells");
-  if (!is_finite(pr.cfl) || !(pr.cfl > 0.0) || pr.cfl > 1.0)
-    return fail(ADER_EINVAL, "cfl must be in (0, 1]");
-  if (pr.system == ADER_SYS_EULER && (!is_finite(pr.gamma) || !(pr.gamma > 1.0)))
-    return fail(ADER_EINVAL, "gamma must be > 1");
-  if (pr.system == ADER_SYS_LINADV)
-    for (int k = 0; k < 3; ++k)
-      if (!is_finite(pr.adv[k])) return fail(ADER_EINVAL, "advection velocity must be finite");
-  if (!is_finite(pr.picard_tol) || !(pr.picard_tol > 0.0))
-    return fail(ADER_EINVAL, "picard_tol must be > 0");
-  if (pr.picard_max < 1 || pr.picard_max > 1000)
-    return fail(ADER_EINVAL, "picard_max must be in 1..1000");
+  int64_t ncells = 0;
+  if (ader_status st = ader::validate_problem(pr, &ncells)) return st;
 
   ader_plan p = new (std::nothrow) ader_plan_s();
   if (!p) return fail(ADER_EINVAL, "out of host memory");
@@ -113,44 +172,9 @@ ader_status ader_plan_create(const ader_problem* prob, ader_plan* out) {
     delete p;
     return fail(ADER_EINVAL, "singular reference matrix");
   }
-  ader::DevConsts& c = d.dc;
-  std::memset(&c, 0, sizeof(c));
-  const ader::RefConstants& r = d.ref;
-  for (int a = 0; a < d.n; ++a) {
-    c.psi0[a] = (double)r.psi0[a];
-    c.psi1[a] = (double)r.psi1[a];
-    c.w[a] = (double)r.weights[a];
-    c.psi0_f[a] = (float)r.psi0[a];
-    c.psi1_f[a] = (float)r.psi1[a];
-    for (int b = 0; b < d.n; ++b) {
-      c.dmat[a][b] = (double)r.dmat[a][b];
-      c.tinvw[a][b] = (double)r.time_inv_w[a][b];
-      c.dmat_f[a][b] = (float)r.dmat[a][b];
-      c.tinvw_f[a][b] = (float)r.time_inv_w[a][b];
-      c.sigma[a][b] = (double)r.sigma[a][b];
-      for (int al = 0; al < d.M; ++al) c.dnode[al][a][b] = (double)r.dnode[al][a][b];
-    }
-  }
-  for (int s = 0; s < r.nstencils; ++s) {
-    c.lam[s] = (double)r.lambda[s];
-    for (int pp = 0; pp < d.n; ++pp)
-      for (int e = 0; e < d.n; ++e) c.rec_inv[s][pp][e] = (double)r.rec_inv[s][pp][e];
-  }
-
-  ader::MeshParams& mp = d.mp;
-  std::memset(&mp, 0, sizeof(mp));
-  for (int k = 0; k < 3; ++k) {
-    const bool used = k < pr.dim;
-    mp.n[k] = used ? pr.n[k] : 1;
-    mp.bc[k] = used ? pr.bc[k] : 0;
-    mp.dx[k] = used ? (pr.hi[k] - pr.lo[k]) / pr.n[k] : 1.0;
-    mp.adv[k] = pr.system == ADER_SYS_LINADV ? pr.adv[k] : 0.0;
-  }
-  mp.gamma = pr.gamma;
-  mp.tol = pr.picard_tol;
-  mp.maxit = pr.picard_max;
-  mp.ncells = ncells;
-  mp.ld = ncells;
+  ader::fill_dev_consts(d.ref, d.M, &d.dc);
+  ader::fill_mesh_params(pr, ncells, &d.mp);
+  const ader::MeshParams& mp = d.mp;
 
   p->impl = pr.dim == 2 ? ader::make_impl_2d(pr.M, pr.system, pr.precision)
                         : ader::make_impl_3d(pr.M, pr.system, pr.precision);

@@ -97,10 +97,14 @@ __device__ __forceinline__ float row_max_f(float x) {
   return x;
 }
 
+// One 4 x TY tile (tile indices tile_x, tile_y) of the cell kernel.  Every
+// thread of the block calls it (it synchronises the block).
 template <int M, int SYS, int TY, typename R>
-__global__ void __launch_bounds__(64 * TY)
-k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
-         const double* __restrict__ dt_dev, MeshParams mp, DevConsts c, WsHeader* hdr) {
+__device__ __forceinline__ void cell2d_tile(int tile_x, int tile_y, const double* __restrict__ u,
+                                            int64_t ld, R* __restrict__ traces,
+                                            const double* __restrict__ dt_dev,
+                                            const MeshParams& mp, const DevConsts& c,
+                                            WsHeader* hdr) {
   constexpr int DIM = 2;
   constexpr int n = M + 1;
   constexpr int NS = n * n;
@@ -114,8 +118,8 @@ k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
   __shared__ double sWh[TX * TY * NV * NS];
 
   const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * TX;
-  const int y0 = blockIdx.y * TY;
+  const int x0 = tile_x * TX;
+  const int y0 = tile_y * TY;
   const int nx = mp.n[0], ny = mp.n[1];
 
   // 1. stage the averages (tile + M ghost layers)
@@ -334,6 +338,13 @@ k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
   }
 }
 
+template <int M, int SYS, int TY, typename R>
+__global__ void __launch_bounds__(64 * TY)
+k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
+         const double* __restrict__ dt_dev, MeshParams mp, DevConsts c, WsHeader* hdr) {
+  cell2d_tile<M, SYS, TY, R>(blockIdx.x, blockIdx.y, u, ld, traces, dt_dev, mp, c, hdr);
+}
+
 template <int M, int SYS>
 __device__ __forceinline__ void rusanov_point(const double (&qL)[NVars<SYS, 2>::v],
                                               const double (&qR)[NVars<SYS, 2>::v], int k,
@@ -351,11 +362,14 @@ __device__ __forceinline__ void rusanov_point(const double (&qL)[NVars<SYS, 2>::
 
 constexpr int kFaceTX = 16, kFaceTY = 4;
 
+// One 16 x 4 tile of the face kernel (every thread of the block calls it).
 template <int M, int SYS, typename TR>
-__global__ void __launch_bounds__(kBlock)
-k_face2d(const TR* __restrict__ traces, const double* __restrict__ u_in,
-         double* __restrict__ u_out, int64_t ld, const double* __restrict__ dt_dev,
-         MeshParams mp, DevConsts c, WsHeader* hdr) {
+__device__ __forceinline__ void face2d_tile(int tile_x, int tile_y, const TR* __restrict__ traces,
+                                            const double* __restrict__ u_in,
+                                            double* __restrict__ u_out, int64_t ld,
+                                            const double* __restrict__ dt_dev,
+                                            const MeshParams& mp, const DevConsts& c,
+                                            WsHeader* hdr) {
   constexpr int DIM = 2;
   constexpr int n = M + 1;
   constexpr int NV = NVars<SYS, DIM>::v;
@@ -370,7 +384,7 @@ k_face2d(const TR* __restrict__ traces, const double* __restrict__ u_in,
   const int tid = threadIdx.x;
   const int grp = tid >> 4;
   const int l = tid & 15;  // Gauss point l = b + n s of the face
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  const int x0 = tile_x * TX, y0 = tile_y * TY;
   const int nx = mp.n[0], ny = mp.n[1];
   const int64_t C = mp.ncells;
   const bool point_ok = l < n * n;
@@ -474,6 +488,14 @@ k_face2d(const TR* __restrict__ traces, const double* __restrict__ u_in,
   }
   block_report(0u, flags, hdr);
   (void)C;
+}
+
+template <int M, int SYS, typename TR>
+__global__ void __launch_bounds__(kBlock)
+k_face2d(const TR* __restrict__ traces, const double* __restrict__ u_in,
+         double* __restrict__ u_out, int64_t ld, const double* __restrict__ dt_dev,
+         MeshParams mp, DevConsts c, WsHeader* hdr) {
+  face2d_tile<M, SYS, TR>(blockIdx.x, blockIdx.y, traces, u_in, u_out, ld, dt_dev, mp, c, hdr);
 }
 
 }  // namespace ader

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
 #include <vector>
 
 #include "../../include/ader.h"
@@ -45,10 +46,10 @@ struct StageTimer {
   hipStream_t st;
   hipEvent_t a = nullptr;
   StageTimer(Profiler* p, int s, hipStream_t stream) : prof(p), stage(s), st(stream) {
-    if (prof && prof->on) prof->mark(stage, st, &a);
+    if (prof && prof->on) (void)prof->mark(stage, st, &a);
   }
   ~StageTimer() {
-    if (prof && prof->on && a) prof->close(stage, st, a);
+    if (prof && prof->on && a) (void)prof->close(stage, st, a);
   }
 };
 
@@ -67,6 +68,14 @@ struct PlanData {
   size_t ws_bytes = 0;
   mutable Profiler prof;
 };
+
+// Shared by the C ABI entry points (capi.cpp, server.cpp).
+ader_status fail(ader_status st, const std::string& msg);  // records ader_last_error
+ader_status hip_status(hipError_t e, const char* where);
+// Checks a problem description; on success *ncells_out is the cell count.
+ader_status validate_problem(const ader_problem& pr, int64_t* ncells_out);
+void fill_dev_consts(const RefConstants& r, int M, DevConsts* out);
+void fill_mesh_params(const ader_problem& pr, int64_t ncells, MeshParams* out);
 
 // A level view after validation (device pointers).
 struct LevelArgs {

@@ -155,3 +155,26 @@ def test_step_level_validates_before_launching(ader_mod):
     assert lib.ader_level_workspace_bytes(plan, 1000, ctypes.byref(b)) == 0 and b.value > 0
     assert lib.ader_level_workspace_bytes(plan, -1, ctypes.byref(b)) == -1
     lib.ader_plan_destroy(plan)
+
+
+def test_server_host_validation(ader_mod):
+    """Server arguments are checked on the host before any device call."""
+    lib = ader_mod.load_library()
+    h = ctypes.c_void_p()
+    for cfg in [(0, 4, 1, 1), (1 << 30, 0, 1, 1), (1 << 30, 5000, 1, 1),
+                (1 << 30, 4, 0, 1), (1 << 30, 4, 17, 1), (1 << 30, 4, 1, 0), (1 << 30, 4, 1, 9)]:
+        c = ader_mod.CServerConfig(*cfg)
+        assert lib.ader_server_create(ctypes.byref(c), ctypes.byref(h)) == ader_mod.EINVAL
+    b = ctypes.c_size_t()
+    p3 = ader_mod.Problem(dim=3, M=2, n=(8, 8, 8)).to_c()
+    assert lib.ader_server_footprint(ctypes.byref(p3), ctypes.byref(b)) == ader_mod.EUNSUPPORTED
+    bad = ader_mod.Problem(dim=2, M=5, n=(8, 8, 1)).to_c()
+    assert lib.ader_server_footprint(ctypes.byref(bad), ctypes.byref(b)) == ader_mod.EUNSUPPORTED
+    # footprint: two fp64 state copies, a 1 KiB header, the CFL partials and
+    # four face traces of nv * n^2 values per cell
+    for M, prec, el in [(3, 0, 8), (2, 1, 4), (1, 0, 8)]:
+        pr = ader_mod.Problem(dim=2, M=M, n=(64, 48, 1), precision=prec)
+        assert lib.ader_server_footprint(ctypes.byref(pr.to_c()), ctypes.byref(b)) == 0
+        n, C = M + 1, 64 * 48
+        expect = 2 * 4 * C * 8 + 1024 + 1024 + 4 * 4 * n * n * C * el
+        assert expect <= b.value <= expect + 4 * 256

@@ -1,0 +1,125 @@
+"""Solve server (ader_server_*): continuous batching of independent 2D
+solves.  Every result must be bitwise the one of the same solve run alone
+(and equal to the single-solve step loop); the config-1 vortex matches the
+oracle to 1e-11; admission respects the HBM arena."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1212_3585_amd import workloads as wl
+
+from gpu_helpers import make_pair, rel_l1, say, to_device, from_device
+
+pytestmark = pytest.mark.gpu
+
+
+def _kh(ader, n, M, precision=0, seed=1):
+    tol = 1e-14 if precision == 0 else 1e-6
+    return (ader.Problem(dim=2, M=M, n=(n, n, 1), precision=precision, picard_tol=tol),
+            wl.kelvin_helmholtz(n, seed=seed))
+
+
+def _mix(ader):
+    """(problem, U0, t_end) of several kernel groups and mesh shapes."""
+    cases = []
+    p, U = _kh(ader, 32, 2)
+    cases.append((p, U, 0.02))
+    p, U = _kh(ader, 64, 3, precision=1, seed=5)
+    cases.append((p, U, 0.015))
+    p = ader.Problem(dim=2, M=1, n=(48, 40, 1), lo=(0, 0, 0), hi=(1.2, 1.0, 1.0),
+                     bc=(ader.BC_TRANSMISSIVE, ader.BC_PERIODIC, 0))
+    cases.append((p, wl.perturbed_smooth_euler((48, 40), 7), 0.03))
+    p = ader.Problem(dim=2, M=2, n=(20, 20, 1), lo=(0, 0, 0), hi=(10, 10, 1))
+    cases.append((p, wl.isentropic_vortex(20), 0.3))
+    p = ader.Problem(dim=2, M=3, system=ader.SYS_LINADV, adv=(1.0, -0.5, 0.0), n=(24, 24, 1))
+    cases.append((p, wl.sine_wave(24), 0.1))
+    p, U = _kh(ader, 40, 1, seed=9)
+    cases.append((p, U, 0.02))
+    return cases
+
+
+def _alone(ader, p, U, t_end):
+    srv = ader.Server(hbm_bytes=1 << 30, max_slots=4)
+    rid = srv.submit(p, U, t_end)
+    srv.drain([rid])
+    out, info = srv.result(rid).copy(), srv.info(rid)
+    srv.close()
+    return out, info
+
+
+def test_server_result_equals_step_loop(ader):
+    say("server: one KH 32^2 M=2 solve vs the single-solve step loop")
+    p, U = _kh(ader, 32, 2)
+    out, info = _alone(ader, p, U, 0.02)
+    assert info["state"] == ader.REQ_DONE and info["flags"] == 0
+    s = ader.Solver(p)
+    u, t, steps = s.run(to_device(U), 0.02)
+    assert steps == info["steps"] and t == info["t"]
+    assert np.array_equal(out, from_device(u, (32, 32)))
+
+
+def test_server_mix_is_bitwise_alone(ader):
+    say("server: six solves in four kernel groups, mixed vs alone")
+    cases = _mix(ader)
+    alone = [_alone(ader, p, U, te) for p, U, te in cases]
+    srv = ader.Server(hbm_bytes=1 << 30, max_slots=16, streams=4, rounds_ahead=2)
+    ids = [srv.submit(p, U, te) for p, U, te in cases]
+    srv.drain(ids)
+    for rid, (ref, rinfo), (p, U, te) in zip(ids, alone, cases):
+        info = srv.info(rid)
+        assert info["state"] == ader.REQ_DONE, info
+        assert info["steps"] == rinfo["steps"] and info["t"] == rinfo["t"] == te
+        assert np.array_equal(srv.result(rid), ref)
+    st = srv.stats()
+    assert st["completed"] == len(cases) and st["resident"] == 0 and st["bytes_in_use"] == 0
+    assert st["peak_resident"] == len(cases)
+    srv.close()
+
+
+def test_server_vortex_matches_oracle(ader):
+    say("server: isentropic vortex 20^2 M=2 to t=1 vs oracle")
+    op, gp = make_pair(ader, 2, 2, (20, 20), (0, 0), (10, 10))
+    U0 = wl.isentropic_vortex(20)
+    srv = ader.Server(hbm_bytes=64 << 20, max_slots=2)
+    rid = srv.submit(gp, U0, 1.0)
+    srv.drain([rid])
+    Uo, t, steps, _ = oracle.run(op, U0, 1.0)
+    info = srv.info(rid)
+    assert info["steps"] == steps and info["t"] == t
+    assert rel_l1(srv.result(rid), Uo) <= 1e-11
+    srv.close()
+
+
+def test_server_admission_by_footprint(ader):
+    say("server: arena for two 64^2 M=3 solves, six submitted")
+    p, U = _kh(ader, 64, 3)
+    fp = ader.Server.footprint(p)
+    srv = ader.Server(hbm_bytes=int(2.5 * fp), max_slots=64)
+    ids = [srv.submit(p, U, 0.01) for _ in range(6)]
+    srv.drain(ids)
+    st = srv.stats()
+    assert st["peak_resident"] == 2 and st["peak_bytes_in_use"] <= st["arena_bytes"]
+    ref = srv.result(ids[0])
+    for rid in ids:
+        assert srv.info(rid)["state"] == ader.REQ_DONE
+        assert np.array_equal(srv.result(rid), ref)
+    # admission is FIFO: a later request is never admitted before an earlier one
+    admits = [srv.info(r)["admit_s"] for r in ids]
+    assert admits == sorted(admits)
+    srv.close()
+
+
+def test_server_arrivals_while_running(ader):
+    say("server: requests arriving while others are resident")
+    cases = _mix(ader)
+    srv = ader.Server(hbm_bytes=1 << 30, max_slots=16, rounds_ahead=3)
+    ids = [srv.submit(*cases[0]), srv.submit(*cases[1])]
+    for _ in range(5):
+        srv.progress()
+    assert srv.stats()["resident"] >= 1
+    ids += [srv.submit(*c) for c in cases[2:]]
+    srv.drain(ids)
+    for rid, (p, U, te) in zip(ids, cases):
+        ref, _ = _alone(ader, p, U, te)
+        assert np.array_equal(srv.result(rid), ref)
+    srv.close()
