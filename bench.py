@@ -126,6 +126,95 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+SERVE_SIZES = (32, 64, 128, 256, 512)
+SERVE_ORDERS = (1, 2, 3)
+SERVE_T_END = 0.5
+
+
+def serving_requests(ader, wl, count, seed=4):
+    """Seeded request mix of the serving workload: 2D Euler Kelvin-Helmholtz
+    solves with their own perturbation seeds, meshes 32^2..512^2 and degrees
+    M = 1..3 drawn uniformly, each to t = 0.5, fp64."""
+    import numpy as np
+    r = np.random.Generator(np.random.PCG64(seed))
+    reqs = []
+    for i in range(count):
+        n = int(r.choice(SERVE_SIZES))
+        M = int(r.choice(SERVE_ORDERS))
+        prob = ader.Problem(dim=2, M=M, n=(n, n, 1), precision=ader.PREC_FP64,
+                            picard_tol=1e-14)
+        reqs.append((prob, wl.kelvin_helmholtz(n, seed=100 + i), SERVE_T_END))
+    return reqs
+
+
+def serve(ader, reqs, arrivals, hbm_bytes):
+    """Run one request stream through a fresh server: request i is submitted
+    at arrivals[i] seconds (None: all at once).  Returns per-request latency
+    (submit to result in host memory), makespan and cell updates."""
+    import numpy as np
+    srv = ader.Server(hbm_bytes=hbm_bytes, max_slots=256, streams=4, rounds_ahead=2)
+    ids = []
+    t0 = time.monotonic()
+    i = 0
+    n = len(reqs)
+    while True:
+        now = time.monotonic() - t0
+        while i < n and (arrivals is None or arrivals[i] <= now):
+            ids.append(srv.submit(*reqs[i]))
+            i += 1
+        srv.progress(wait=(i == n))
+        if i == n and srv.stats()["completed"] == n:
+            break
+    makespan = time.monotonic() - t0
+    infos = [srv.info(rid) for rid in ids]
+    st = srv.stats()
+    srv.close()
+    lat = np.array([f["done_s"] - f["submit_s"] for f in infos])
+    cell_updates = sum(f["steps"] * p.n[0] * p.n[1] for f, (p, _, _) in zip(infos, reqs))
+    bad = [f["state"] for f in infos if f["state"] != ader.REQ_DONE]
+    return {"latency": lat, "makespan": makespan, "cell_updates": cell_updates,
+            "failed": len(bad), "peak_resident": st["peak_resident"],
+            "peak_bytes": st["peak_bytes_in_use"], "rounds": st["rounds"]}
+
+
+def serving_leg(ader, wl, count, hbm_bytes=16 << 30, seed=4):
+    """Closed loop (all requests at t = 0) for the maximum rate, then Poisson
+    arrivals (seed 5) at 0.5 and 0.9 of it: p50 / p99 latency and solves/s."""
+    import numpy as np
+    reqs = serving_requests(ader, wl, count, seed)
+    log(f"bench: serving, {count} requests, closed loop")
+    closed = serve(ader, reqs, None, hbm_bytes)
+    mu = count / closed["makespan"]
+    out = {
+        "workload": f"{count} independent 2D Euler KH solves to t = {SERVE_T_END}, meshes "
+                    f"{SERVE_SIZES[0]}^2..{SERVE_SIZES[-1]}^2, M in {list(SERVE_ORDERS)}, fp64, "
+                    f"drawn uniformly (PCG64 seed {seed}); server arena {hbm_bytes >> 30} GiB, "
+                    "4 streams",
+        "max_solves_per_s": mu,
+        "closed_loop": {"makespan_s": closed["makespan"],
+                        "cell_updates_per_s": closed["cell_updates"] / closed["makespan"],
+                        "p50_latency_s": float(np.percentile(closed["latency"], 50)),
+                        "p99_latency_s": float(np.percentile(closed["latency"], 99)),
+                        "peak_resident": closed["peak_resident"],
+                        "peak_arena_bytes": closed["peak_bytes"], "failed": closed["failed"]},
+        "poisson": [],
+    }
+    r = np.random.Generator(np.random.PCG64(seed + 1))
+    gaps = r.exponential(1.0, size=count)
+    for frac in (0.5, 0.9):
+        lam = frac * mu
+        arrivals = np.cumsum(gaps) / lam
+        log(f"bench: serving, Poisson arrivals at {lam:.2f} solves/s")
+        res = serve(ader, reqs, arrivals, hbm_bytes)
+        out["poisson"].append({
+            "offered_solves_per_s": lam, "solves_per_s": count / res["makespan"],
+            "cell_updates_per_s": res["cell_updates"] / res["makespan"],
+            "p50_latency_s": float(np.percentile(res["latency"], 50)),
+            "p99_latency_s": float(np.percentile(res["latency"], 99)),
+            "peak_resident": res["peak_resident"], "failed": res["failed"]})
+    return out
+
+
 def time_form(ader, wl, torch, precision, tol, steps, warmup, u0):
     """Warm up, then time `steps` steps.  Every launch of this solver (warmup,
     timed steps, and the later check step) is bracketed by HIP events on its
@@ -173,6 +262,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=256,
                     help="mesh rows of the CPU-oracle sample (512 cells each)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests of the serving leg (0 skips it)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run the launches that the HBM counters calibrate")
     args = ap.parse_args()
@@ -245,6 +336,10 @@ def main():
         for k in ("fp64", "fp32"):
             l1[k] = float(np.abs(outs[k] - ref).sum() / np.abs(ref).sum())
 
+    serving = None
+    if args.serve_requests > 0:
+        serving = serving_leg(ader, wl, args.serve_requests)
+
     line = {
         "metric": "cell-updates/s (FP32-predictor vs FP64) at stated L1 err; "
                   "p50/p99 solve latency",
@@ -281,6 +376,7 @@ def main():
                      "flops_per_launch": flops_launch,
                      "avg_launch_ms": avg_s * 1e3},
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 

@@ -150,7 +150,7 @@ k_dt_batch(const SolveDesc* __restrict__ ds, int ns, SolveClock* __restrict__ mi
 }
 
 template <int M, int SYS, int TY, typename R>
-__global__ void __launch_bounds__(64 * TY)
+__global__ void __launch_bounds__(64 * TY, kCellWavesPerSimd<R>::v)
 k_cell2d_batch(const SolveDesc* __restrict__ ds, int ns, DevConsts c) {
   const int si = find_solve<&SolveDesc::cell_block0>(ds, ns, blockIdx.x);
   const SolveDesc& d = ds[si];
