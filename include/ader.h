@@ -48,10 +48,15 @@ typedef enum {
   ADER_EWORKSPACE = -4     /* workspace pointer null or misaligned */
 } ader_status;
 
-/* Balance law: scalar linear advection with constant velocity adv[], or the
+/* Balance law: scalar linear advection with constant velocity adv[]; the
  * Euler equations of an ideal gas (Section 4.1, eq. Euler-system) with
- * conserved variables (rho, rho v_x, rho v_y, [rho v_z,] E): nvar = dim + 2. */
-typedef enum { ADER_SYS_LINADV = 0, ADER_SYS_EULER = 1 } ader_system;
+ * conserved variables (rho, rho v_x, rho v_y, [rho v_z,] E): nvar = dim + 2;
+ * or ideal MHD with hyperbolic GLM divergence cleaning (Section 4.2) with
+ * (rho, rho v_x, rho v_y, rho v_z, E, B_x, B_y, B_z, psi): nvar = 9 in 2D and
+ * 3D, magnetic terms in the paper's units (|B|^2 / 8 pi, B B / 4 pi), cleaning
+ * speed ch; Rusanov and CFL use max(|v_n| + c_f, ch) with the fast
+ * magnetosonic speed c_f. */
+typedef enum { ADER_SYS_LINADV = 0, ADER_SYS_EULER = 1, ADER_SYS_MHD_GLM = 2 } ader_system;
 
 /* FP64: every stage in double precision.  FP32_PREDICTOR: the Picard
  * iteration of the predictor and its face traces in single precision with
@@ -67,7 +72,8 @@ typedef struct {
   int dim;            /* 2 or 3 */
   int M;              /* polynomial degree 0..3 (order of accuracy M+1) */
   int system;         /* ader_system */
-  double gamma;       /* ratio of specific heats (Euler) */
+  double gamma;       /* ratio of specific heats (Euler, MHD) */
+  double ch;          /* GLM divergence-cleaning speed (MHD), > 0 */
   double adv[3];      /* advection velocity (linear advection) */
   int n[3];           /* cells per axis (n[2] ignored for dim 2); each >= 1 */
   double lo[3];       /* domain lower corner */
@@ -83,7 +89,7 @@ typedef struct ader_plan_s* ader_plan;
 
 /* Device status bits (ader_read_status). */
 #define ADER_FLAG_NAN 1u          /* a NaN appeared in the new averages or dt */
-#define ADER_FLAG_NONPHYSICAL 2u  /* rho <= 0 or p <= 0 in the new averages */
+#define ADER_FLAG_NONPHYSICAL 2u  /* rho <= 0 or p <= 0 (gas pressure) in the new averages */
 #define ADER_FLAG_NOCONV 4u       /* predictor reached picard_max */
 #define ADER_FLAG_BADINDEX 8u     /* a level view held an index out of range */
 
@@ -99,7 +105,7 @@ ader_status ader_plan_create(const ader_problem* prob, ader_plan* out);
 /* Release a plan (NULL is accepted). */
 ader_status ader_plan_destroy(ader_plan plan);
 
-/* Number of conserved variables of the plan's system (1, 4 or 5). */
+/* Number of conserved variables of the plan's system (1; 4 or 5; 9). */
 ader_status ader_plan_nvar(ader_plan plan, int* nvar);
 
 /* Bytes of device workspace every compute call of this plan needs.  The
@@ -112,7 +118,8 @@ ader_status ader_workspace_bytes(ader_plan plan, size_t* bytes);
 ader_status ader_clear_status(ader_plan plan, void* ws, void* stream);
 
 /* Time step from the CFL rule on the averages u at time t:
- *   dt = cfl / max_cells sum_k (|v_k| + c) / dx_k     (|a_k| for advection),
+ *   dt = cfl / max_cells sum_k (|v_k| + c) / dx_k     (|a_k| for advection,
+ *   max(|v_k| + c_f, ch) for MHD),
  * then dt = min(dt, t_end - t).  Written to dt_dev (one device double).
  * The paper states no formula for dt; this is the rule the library uses. */
 ader_status ader_compute_dt(ader_plan plan, const double* u, int64_t ld,

@@ -12,7 +12,8 @@ the method's arithmetic.
 Modules:
   basis      nodal Lagrange basis at Gauss-Legendre nodes, exact 1D integrals
   weno       dimension-by-dimension polynomial WENO (Section 2.2)
-  physics    Euler (Section 4.1) and linear-advection fluxes and wave speeds
+  physics    Euler (Section 4.1), GLM-MHD (Section 4.2) and linear-advection
+             fluxes and wave speeds
   predictor  space-time DG predictor with Picard iteration (Section 2.3)
   scheme     CFL time step, Rusanov face fluxes, finite-volume update (2.1)
   brute      independent brute-force routes used to pin the above
@@ -20,7 +21,7 @@ Modules:
 Every function is fp64 numpy; batching over cells is the only vectorisation.
 """
 from .basis import Basis1D, basis, gauss_legendre  # noqa: F401
-from .physics import Euler, LinearAdvection  # noqa: F401
+from .physics import Euler, GLMMHD, LinearAdvection  # noqa: F401
 from .predictor import predict, spacetime_matrices  # noqa: F401
 from .scheme import (Problem, all_cells, cfl_dt, run, step,  # noqa: F401
                      step_cells)

@@ -16,7 +16,7 @@ import numpy as np
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libaderweno.so")
 
 OK, EINVAL, EUNSUPPORTED, EHIP, EWORKSPACE = 0, -1, -2, -3, -4
-SYS_LINADV, SYS_EULER = 0, 1
+SYS_LINADV, SYS_EULER, SYS_MHD_GLM = 0, 1, 2
 PREC_FP64, PREC_FP32_PREDICTOR = 0, 1
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
 FLAG_NAN, FLAG_NONPHYSICAL, FLAG_NOCONV, FLAG_BADINDEX = 1, 2, 4, 8
@@ -46,7 +46,7 @@ class AderError(RuntimeError):
 class CProblem(ctypes.Structure):
     _fields_ = [
         ("dim", ctypes.c_int), ("M", ctypes.c_int), ("system", ctypes.c_int),
-        ("gamma", ctypes.c_double), ("adv", ctypes.c_double * 3),
+        ("gamma", ctypes.c_double), ("ch", ctypes.c_double), ("adv", ctypes.c_double * 3),
         ("n", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
         ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int * 3),
         ("cfl", ctypes.c_double), ("precision", ctypes.c_int),
@@ -155,6 +155,7 @@ class Problem:
     M: int = 2
     system: int = SYS_EULER
     gamma: float = 1.4
+    ch: float = 2.0
     adv: tuple = (1.0, 1.0, 1.0)
     n: tuple = (20, 20, 1)
     lo: tuple = (0.0, 0.0, 0.0)
@@ -169,6 +170,7 @@ class Problem:
         c = CProblem()
         c.dim, c.M, c.system = self.dim, self.M, self.system
         c.gamma = self.gamma
+        c.ch = self.ch
         c.adv[:] = list(self.adv)[:3] + [0.0] * (3 - len(self.adv))
         c.n[:] = list(self.n)[:3] + [1] * (3 - len(self.n))
         c.lo[:] = list(self.lo)[:3] + [0.0] * (3 - len(self.lo))

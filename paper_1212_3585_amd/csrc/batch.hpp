@@ -72,7 +72,7 @@ __device__ __forceinline__ double cell_speed_sum(const double* __restrict__ u, i
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     double f[NV], sp;
-    phys_flux_dir<SYS, 2>(q, k, mp.gamma, adv, f, sp);
+    phys_flux_dir<SYS, 2>(q, k, mp.gamma, mp.ch, adv, f, sp);
     s += sp / mp.dx[k];
   }
   return s;
@@ -150,7 +150,7 @@ k_dt_batch(const SolveDesc* __restrict__ ds, int ns, SolveClock* __restrict__ mi
 }
 
 template <int M, int SYS, int TY, typename R>
-__global__ void __launch_bounds__(64 * TY, kCellWavesPerSimd<R>::v)
+__global__ void __launch_bounds__(64 * TY, (CellWavesPerSimd<SYS, R>::v))
 k_cell2d_batch(const SolveDesc* __restrict__ ds, int ns, DevConsts c) {
   const int si = find_solve<&SolveDesc::cell_block0>(ds, ns, blockIdx.x);
   const SolveDesc& d = ds[si];

@@ -35,6 +35,7 @@ const BatchImplBase* pick_sys(int system, int precision) {
   switch (system) {
     case ADER_SYS_LINADV: return pick_prec<M, 0>(precision);
     case ADER_SYS_EULER: return pick_prec<M, 1>(precision);
+    case ADER_SYS_MHD_GLM: return pick_prec<M, 2>(precision);
   }
   return nullptr;
 }

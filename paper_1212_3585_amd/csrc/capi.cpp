@@ -34,7 +34,8 @@ ader_status hip_status(hipError_t e, const char* where) {
 ader_status validate_problem(const ader_problem& pr, int64_t* ncells_out) {
   if (pr.dim != 2 && pr.dim != 3) return fail(ADER_EUNSUPPORTED, "dim must be 2 or 3");
   if (pr.M < 0 || pr.M > 3) return fail(ADER_EUNSUPPORTED, "M must be in 0..3");
-  if (pr.system != ADER_SYS_LINADV && pr.system != ADER_SYS_EULER)
+  if (pr.system != ADER_SYS_LINADV && pr.system != ADER_SYS_EULER &&
+      pr.system != ADER_SYS_MHD_GLM)
     return fail(ADER_EUNSUPPORTED, "unknown system");
   if (pr.precision != ADER_PREC_FP64 && pr.precision != ADER_PREC_FP32_PREDICTOR)
     return fail(ADER_EINVAL, "unknown precision");
@@ -50,8 +51,10 @@ ader_status validate_problem(const ader_problem& pr, int64_t* ncells_out) {
   if (ncells > (int64_t(1) << 28)) return fail(ADER_EUNSUPPORTED, "more than 2^28 cells");
   if (!is_finite(pr.cfl) || !(pr.cfl > 0.0) || pr.cfl > 1.0)
     return fail(ADER_EINVAL, "cfl must be in (0, 1]");
-  if (pr.system == ADER_SYS_EULER && (!is_finite(pr.gamma) || !(pr.gamma > 1.0)))
+  if (pr.system != ADER_SYS_LINADV && (!is_finite(pr.gamma) || !(pr.gamma > 1.0)))
     return fail(ADER_EINVAL, "gamma must be > 1");
+  if (pr.system == ADER_SYS_MHD_GLM && (!is_finite(pr.ch) || !(pr.ch > 0.0)))
+    return fail(ADER_EINVAL, "the cleaning speed ch must be > 0");
   if (pr.system == ADER_SYS_LINADV)
     for (int k = 0; k < 3; ++k)
       if (!is_finite(pr.adv[k])) return fail(ADER_EINVAL, "advection velocity must be finite");
@@ -101,6 +104,7 @@ void fill_mesh_params(const ader_problem& pr, int64_t ncells, MeshParams* out) {
     mp.adv[k] = pr.system == ADER_SYS_LINADV ? pr.adv[k] : 0.0;
   }
   mp.gamma = pr.gamma;
+  mp.ch = pr.system == ADER_SYS_MHD_GLM ? pr.ch : 0.0;
   mp.tol = pr.picard_tol;
   mp.maxit = pr.picard_max;
   mp.ncells = ncells;
@@ -162,7 +166,7 @@ ader_status ader_plan_create(const ader_problem* prob, ader_plan* out) {
   d.dim = pr.dim;
   d.M = pr.M;
   d.n = pr.M + 1;
-  d.nv = pr.system == ADER_SYS_LINADV ? 1 : pr.dim + 2;
+  d.nv = pr.system == ADER_SYS_LINADV ? 1 : (pr.system == ADER_SYS_EULER ? pr.dim + 2 : 9);
   d.ns = 1;
   for (int k = 0; k < pr.dim; ++k) d.ns *= d.n;
   d.nst = d.ns * d.n;

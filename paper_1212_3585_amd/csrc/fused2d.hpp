@@ -38,9 +38,12 @@ namespace ader {
 
 constexpr int kCellTX = 4;  // tile width of the cell kernel = cells per wavefront
 // Occupancy the cell kernel is compiled for (waves per SIMD; the register
-// budget is 512 / waves VGPRs per lane): fp64 4 (<= 128 VGPRs), fp32 5.
-template <typename R> struct kCellWavesPerSimd { static constexpr int v = 4; };
-template <> struct kCellWavesPerSimd<float> { static constexpr int v = 5; };
+// budget is 512 / waves VGPRs per lane): Euler and advection fp64 4
+// (<= 128 VGPRs), fp32 5; GLM-MHD (nine variables) fp64 2, fp32 3.
+template <int SYS, typename R> struct CellWavesPerSimd {
+  static constexpr bool f64 = std::is_same<R, double>::value;
+  static constexpr int v = SYS == 2 ? (f64 ? 2 : 3) : (f64 ? 4 : 5);
+};
 // lanes of matrix block b1 = 0 (b0 + 16 b2); block b1 is this mask << 4 b1
 constexpr uint64_t kCellLanes = 0x000F000F000F000FULL;
 
@@ -213,6 +216,7 @@ __device__ __forceinline__ void cell2d_tile(int tile_x, int tile_y, const double
   xor_row<n>(c, px, dt / mp.dx[0], cxm);
   ror_row<n>(c, py, dt / mp.dx[1], cyr);
   const R gamma = (R)mp.gamma;
+  const R ch = (R)mp.ch;
   const R adv[3] = {(R)mp.adv[0], (R)mp.adv[1], (R)mp.adv[2]};
 
   R w[NV];
@@ -247,7 +251,7 @@ __device__ __forceinline__ void cell2d_tile(int tile_x, int tile_y, const double
 #pragma unroll
       for (int v = 0; v < NV; ++v) qs[v] = q[v][s];
       R F[DIM][NV];
-      phys_fluxes<SYS, DIM, R>(qs, gamma, adv, F);
+      phys_fluxes<SYS, DIM, R>(qs, gamma, ch, adv, F);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         if constexpr (kMatrix) {
@@ -358,7 +362,7 @@ __device__ __forceinline__ void cell2d_tile(int tile_x, int tile_y, const double
 }
 
 template <int M, int SYS, int TY, typename R>
-__global__ void __launch_bounds__(64 * TY, kCellWavesPerSimd<R>::v)
+__global__ void __launch_bounds__(64 * TY, (CellWavesPerSimd<SYS, R>::v))
 k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
          const double* __restrict__ dt_dev, MeshParams mp, DevConsts c, WsHeader* hdr) {
   cell2d_tile<M, SYS, TY, R>(blockIdx.x, blockIdx.y, u, ld, traces, dt_dev, mp, c, hdr);
@@ -372,8 +376,8 @@ __device__ __forceinline__ void rusanov_point(const double (&qL)[NVars<SYS, 2>::
   constexpr int NV = NVars<SYS, 2>::v;
   const double adv[3] = {mp.adv[0], mp.adv[1], mp.adv[2]};
   double fL[NV], fR[NV], sL, sR;
-  phys_flux_dir<SYS, 2>(qL, k, mp.gamma, adv, fL, sL);
-  phys_flux_dir<SYS, 2>(qR, k, mp.gamma, adv, fR, sR);
+  phys_flux_dir<SYS, 2>(qL, k, mp.gamma, mp.ch, adv, fL, sL);
+  phys_flux_dir<SYS, 2>(qR, k, mp.gamma, mp.ch, adv, fR, sR);
   const double smax = fmax(sL, sR);
 #pragma unroll
   for (int v = 0; v < NV; ++v) F[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * smax * (qR[v] - qL[v]);
@@ -496,13 +500,7 @@ __device__ __forceinline__ void face2d_tile(int tile_x, int tile_y, const TR* __
 #pragma unroll
       for (int v = 0; v < NV; ++v)
         if (q[v] != q[v]) flags |= kFlagNan;
-      if constexpr (SYS == 1) {
-        double kin = 0.0;
-#pragma unroll
-        for (int m = 0; m < DIM; ++m) kin += q[1 + m] * q[1 + m] / q[0];
-        const double p = (mp.gamma - 1.0) * (q[DIM + 1] - 0.5 * kin);
-        if (!(q[0] > 0.0) || !(p > 0.0)) flags |= kFlagNonPhysical;
-      }
+      if (!state_physical<SYS, DIM>(q, mp.gamma)) flags |= kFlagNonPhysical;
     }
   }
   block_report(0u, flags, hdr);

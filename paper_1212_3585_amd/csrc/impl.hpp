@@ -247,8 +247,11 @@ const ImplBase* pick_impl(int sys, int prec) {
   static const Impl<DIM, M, 0, float> b;
   static const Impl<DIM, M, 1, double> c;
   static const Impl<DIM, M, 1, float> d;
+  static const Impl<DIM, M, 2, double> e;
+  static const Impl<DIM, M, 2, float> f;
   if (sys == 0) return prec == 0 ? (const ImplBase*)&a : (const ImplBase*)&b;
-  return prec == 0 ? (const ImplBase*)&c : (const ImplBase*)&d;
+  if (sys == 1) return prec == 0 ? (const ImplBase*)&c : (const ImplBase*)&d;
+  return prec == 0 ? (const ImplBase*)&e : (const ImplBase*)&f;
 }
 
 }  // namespace ader

@@ -45,6 +45,7 @@ struct MeshParams {
   int bc[3];          // 0 periodic, 1 transmissive
   double dx[3];
   double gamma;
+  double ch;          // GLM cleaning speed (MHD)
   double adv[3];
   double tol;
   int maxit;
@@ -94,7 +95,12 @@ template <int B, int E> struct Pow { static constexpr int v = B * Pow<B, E - 1>:
 template <int B> struct Pow<B, 0> { static constexpr int v = 1; };
 
 // number of conserved variables: linear advection 1, Euler dim + 2
-template <int SYS, int DIM> struct NVars { static constexpr int v = SYS == 0 ? 1 : DIM + 2; };
+// conserved variables: linear advection 1, Euler d + 2, GLM-MHD 9
+template <int SYS, int DIM> struct NVars {
+  static constexpr int v = SYS == 0 ? 1 : (SYS == 1 ? DIM + 2 : 9);
+};
+constexpr double kInv4Pi = 0.25 / 3.14159265358979323846;  // 1 / (4 pi)
+constexpr double kInv8Pi = 0.125 / 3.14159265358979323846;  // 1 / (8 pi)
 
 // ---------------------------------------------------------------- physics
 // 1/x from the hardware reciprocal estimate refined by Newton-Raphson
@@ -115,13 +121,13 @@ __device__ __forceinline__ float recip(float x) {
 // Physical fluxes of all DIM directions at one state (eq. Euler-system, or
 // linear advection f_k = a_k u).  F[k][v].
 template <int SYS, int DIM, typename R>
-__device__ __forceinline__ void phys_fluxes(const R (&q)[NVars<SYS, DIM>::v], R gamma,
+__device__ __forceinline__ void phys_fluxes(const R (&q)[NVars<SYS, DIM>::v], R gamma, R ch,
                                             const R (&adv)[3],
                                             R (&F)[DIM][NVars<SYS, DIM>::v]) {
   if constexpr (SYS == 0) {
 #pragma unroll
     for (int k = 0; k < DIM; ++k) F[k][0] = adv[k] * q[0];
-  } else {
+  } else if constexpr (SYS == 1) {
     const R inv_rho = recip(q[0]);
     R vel[DIM];
     R kin = R(0);
@@ -140,18 +146,45 @@ __device__ __forceinline__ void phys_fluxes(const R (&q)[NVars<SYS, DIM>::v], R 
       F[k][1 + k] += p;
       F[k][DIM + 1] = vel[k] * (E + p);
     }
+  } else {
+    // GLM-MHD (Section 4.2): (rho, rho v (3), E, B (3), psi)
+    const R inv_rho = recip(q[0]);
+    R vel[3], B[3];
+    R kin = R(0), B2 = R(0), vB = R(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      vel[i] = q[1 + i] * inv_rho;
+      B[i] = q[5 + i];
+      kin += q[1 + i] * vel[i];
+      B2 += B[i] * B[i];
+      vB += vel[i] * B[i];
+    }
+    const R E = q[4], psi = q[8];
+    const R pm = B2 * R(kInv8Pi);
+    const R pt = (gamma - R(1)) * (E - R(0.5) * kin - pm) + pm;  // p + |B|^2 / 8 pi
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      F[k][0] = q[1 + k];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) F[k][1 + i] = q[1 + i] * vel[k] - B[i] * B[k] * R(kInv4Pi);
+      F[k][1 + k] += pt;
+      F[k][4] = vel[k] * (E + pt) - B[k] * vB * R(kInv4Pi);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) F[k][5 + i] = i == k ? psi : vel[k] * B[i] - vel[i] * B[k];
+      F[k][8] = ch * ch * B[k];
+    }
   }
 }
 
 // flux along one axis k and |largest eigenvalue| along k (fp64)
 template <int SYS, int DIM>
 __device__ __forceinline__ void phys_flux_dir(const double (&q)[NVars<SYS, DIM>::v], int k,
-                                              double gamma, const double (&adv)[3],
+                                              double gamma, double ch, const double (&adv)[3],
                                               double (&f)[NVars<SYS, DIM>::v], double& speed) {
   if constexpr (SYS == 0) {
     f[0] = adv[k] * q[0];
     speed = fabs(adv[k]);
-  } else {
+  } else if constexpr (SYS == 1) {
     const double rho = q[0];
     double vel[DIM];
     double kin = 0.0;
@@ -174,6 +207,67 @@ __device__ __forceinline__ void phys_flux_dir(const double (&q)[NVars<SYS, DIM>:
       if (m == k) f[1 + m] += p;
     f[DIM + 1] = vk * (E + p);
     speed = fabs(vk) + sqrt(gamma * p / rho);
+  } else {
+    // GLM-MHD (Section 4.2); |largest eigenvalue| = max(|v_k| + c_f, c_h)
+    // with the textbook fast magnetosonic speed c_f
+    const double rho = q[0];
+    double vel[3], B[3];
+    double kin = 0.0, B2 = 0.0, vB = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      vel[i] = q[1 + i] / rho;
+      B[i] = q[5 + i];
+      kin += q[1 + i] * vel[i];
+      B2 += B[i] * B[i];
+      vB += vel[i] * B[i];
+    }
+    double vk = 0.0, mk = 0.0, Bk = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      if (i == k) { vk = vel[i]; mk = q[1 + i]; Bk = B[i]; }
+    const double E = q[4], psi = q[8];
+    const double pm = B2 * kInv8Pi;
+    const double p = (gamma - 1.0) * (E - 0.5 * kin - pm);
+    const double pt = p + pm;
+    f[0] = mk;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) f[1 + i] = q[1 + i] * vk - B[i] * Bk * kInv4Pi;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      if (i == k) f[1 + i] += pt;
+    f[4] = vk * (E + pt) - Bk * vB * kInv4Pi;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) f[5 + i] = i == k ? psi : vk * B[i] - vel[i] * Bk;
+    f[8] = ch * ch * Bk;
+    const double a2 = gamma * p / rho;
+    const double b2 = B2 * kInv4Pi / rho, bk2 = Bk * Bk * kInv4Pi / rho;
+    const double sum = a2 + b2;
+    const double cf = sqrt(0.5 * (sum + sqrt(fmax(sum * sum - 4.0 * a2 * bk2, 0.0))));
+    speed = fmax(fabs(vk) + cf, ch);
+  }
+}
+
+// Density and pressure positive (Euler, GLM-MHD); always true for advection.
+template <int SYS, int DIM>
+__device__ __forceinline__ bool state_physical(const double (&q)[NVars<SYS, DIM>::v],
+                                               double gamma) {
+  if constexpr (SYS == 0) {
+    return true;
+  } else if constexpr (SYS == 1) {
+    double kin = 0.0;
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) kin += q[1 + m] * q[1 + m] / q[0];
+    const double p = (gamma - 1.0) * (q[DIM + 1] - 0.5 * kin);
+    return q[0] > 0.0 && p > 0.0;
+  } else {
+    double kin = 0.0, B2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      kin += q[1 + i] * q[1 + i] / q[0];
+      B2 += q[5 + i] * q[5 + i];
+    }
+    const double p = (gamma - 1.0) * (q[4] - 0.5 * kin - B2 * kInv8Pi);
+    return q[0] > 0.0 && p > 0.0;
   }
 }
 
@@ -367,6 +461,7 @@ k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
 #pragma unroll
   for (int k = 0; k < DIM; ++k) cour[k] = (R)(dt / mp.dx[k]);
   const R gamma = (R)mp.gamma;
+  const R ch = (R)mp.ch;
   R adv[3] = {(R)mp.adv[0], (R)mp.adv[1], (R)mp.adv[2]};
 
   R drow[DIM][n];
@@ -406,7 +501,7 @@ k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
 #pragma unroll
       for (int v = 0; v < NV; ++v) qs[v] = q[v][s];
       R F[DIM][NV];
-      phys_fluxes<SYS, DIM, R>(qs, gamma, adv, F);
+      phys_fluxes<SYS, DIM, R>(qs, gamma, ch, adv, F);
 #pragma unroll
       for (int k = 0; k < DIM; ++k)
 #pragma unroll
@@ -546,8 +641,8 @@ k_face_flux(const R* __restrict__ qh, double* __restrict__ F, int64_t nfaces, Me
     }
     double fL[NV], fR[NV], sL, sR;
     const double adv[3] = {mp.adv[0], mp.adv[1], mp.adv[2]};
-    phys_flux_dir<SYS, DIM>(qL, K, mp.gamma, adv, fL, sL);
-    phys_flux_dir<SYS, DIM>(qR, K, mp.gamma, adv, fR, sR);
+    phys_flux_dir<SYS, DIM>(qL, K, mp.gamma, mp.ch, adv, fL, sL);
+    phys_flux_dir<SYS, DIM>(qR, K, mp.gamma, mp.ch, adv, fR, sR);
     const double smax = fmax(sL, sR);
     double wt = c.w[s];
     {
@@ -609,13 +704,7 @@ k_update(const double* __restrict__ u_in, double* __restrict__ u_out, const doub
 #pragma unroll
   for (int v = 0; v < NV; ++v)
     if (q[v] != q[v]) flags |= kFlagNan;
-  if constexpr (SYS == 1) {
-    double kin = 0.0;
-#pragma unroll
-    for (int m = 0; m < DIM; ++m) kin += q[1 + m] * q[1 + m] / q[0];
-    const double p = (mp.gamma - 1.0) * (q[DIM + 1] - 0.5 * kin);
-    if (!(q[0] > 0.0) || !(p > 0.0)) flags |= kFlagNonPhysical;
-  }
+  if (!state_physical<SYS, DIM>(q, mp.gamma)) flags |= kFlagNonPhysical;
   block_report(0u, in ? flags : 0u, hdr);
 }
 
@@ -654,7 +743,7 @@ k_dt(const double* __restrict__ u, MeshParams mp, WsHeader* hdr, double* partial
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
       double f[NV], sp;
-      phys_flux_dir<SYS, DIM>(q, k, mp.gamma, adv, f, sp);
+      phys_flux_dir<SYS, DIM>(q, k, mp.gamma, mp.ch, adv, f, sp);
       s += sp / mp.dx[k];
     }
     // a NaN must win the maximum so that it reaches dt and the status word

@@ -163,8 +163,8 @@ k_level_update(const R* __restrict__ qh, const int32_t* __restrict__ pred_cells,
               for (int v = 0; v < NV; ++v) qR[v] = qL[v];
             }
             double fL[NV], fR[NV], sL, sR;
-            phys_flux_dir<SYS, DIM>(qL, k, mp.gamma, adv, fL, sL);
-            phys_flux_dir<SYS, DIM>(qR, k, mp.gamma, adv, fR, sR);
+            phys_flux_dir<SYS, DIM>(qL, k, mp.gamma, mp.ch, adv, fL, sL);
+            phys_flux_dir<SYS, DIM>(qR, k, mp.gamma, mp.ch, adv, fR, sR);
             const double smax = fmax(sL, sR);
             double wt = c.w[s];
             {
@@ -185,13 +185,7 @@ k_level_update(const R* __restrict__ qh, const int32_t* __restrict__ pred_cells,
       u_out[(int64_t)v * ld + cell] = q[v];
       if (q[v] != q[v]) flags |= kFlagNan;
     }
-    if constexpr (SYS == 1) {
-      double kin = 0.0;
-#pragma unroll
-      for (int m = 0; m < DIM; ++m) kin += q[1 + m] * q[1 + m] / q[0];
-      const double p = (mp.gamma - 1.0) * (q[DIM + 1] - 0.5 * kin);
-      if (!(q[0] > 0.0) || !(p > 0.0)) flags |= kFlagNonPhysical;
-    }
+    if (!state_physical<SYS, DIM>(q, mp.gamma)) flags |= kFlagNonPhysical;
   }
   block_report(0u, flags, hdr);
 }

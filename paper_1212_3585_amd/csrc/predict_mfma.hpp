@@ -103,7 +103,7 @@ k_predict_mfma2d(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t nc
 #pragma unroll
       for (int v = 0; v < NV; ++v) qs[v] = q[v][s];
       double F[DIM][NV];
-      phys_fluxes<SYS, DIM, double>(qs, gamma, adv, F);
+      phys_fluxes<SYS, DIM, double>(qs, gamma, mp.ch, adv, F);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const double rx = __builtin_amdgcn_mfma_f64_4x4x4f64(mx, F[0][v], 0.0, 0, 0, 0);

@@ -117,7 +117,7 @@ struct Footprint {
 
 Footprint footprint(const ader_problem& pr, int64_t ncells, size_t trace_elem) {
   Footprint f;
-  f.nv = pr.system == ADER_SYS_LINADV ? 1 : pr.dim + 2;
+  f.nv = pr.system == ADER_SYS_LINADV ? 1 : (pr.system == ADER_SYS_EULER ? pr.dim + 2 : 9);
   f.n = pr.M + 1;
   f.ncells = ncells;
   f.ld = (ncells + 31) / 32 * 32;  // every variable row 256-byte aligned

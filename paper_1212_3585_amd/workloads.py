@@ -118,6 +118,41 @@ def blast_3d(n=64, seed=3, amp=0.01, radius=0.3, gamma=GAMMA, nq=4):
     return U
 
 
+def mhd_conserved(rho, vel, p, B, psi=None, gamma=5.0 / 3.0):
+    """GLM-MHD conserved variables (rho, rho v (3), E, B (3), psi) with
+    E = p / (gamma - 1) + rho |v|^2 / 2 + |B|^2 / 8 pi."""
+    z = np.zeros_like(rho)
+    vel = [np.asarray(v) + z for v in vel]
+    B = [np.asarray(b) + z for b in B]
+    E = p / (gamma - 1.0) + 0.5 * rho * sum(v * v for v in vel) + \
+        sum(b * b for b in B) / (8.0 * np.pi)
+    psi = z if psi is None else psi + z
+    return np.stack([rho] + [rho * v for v in vel] + [E] + B + [psi])
+
+
+def orszag_tang(n, seed=None, amp=0.05, gamma=5.0 / 3.0):
+    """Orszag-Tang vortex (Section 4.2) on the periodic square [0, 2 pi]^2:
+    (rho, v_x, v_y, p, B_x, B_y) = (gamma^2, -sin y, sin x, gamma,
+    -sqrt(4 pi) sin y, sqrt(4 pi) sin 2x), v_z = B_z = psi = 0.  With a seed,
+    each sine gets a random phase and each amplitude a factor 1 + amp U(-1,1)
+    (PCG64): a divergence-free family of the same shape."""
+    ph = np.zeros(4)
+    fac = np.ones(4)
+    if seed is not None:
+        r = np.random.Generator(np.random.PCG64(seed))
+        ph = r.uniform(0.0, 2.0 * np.pi, 4)
+        fac = 1.0 + amp * r.uniform(-1.0, 1.0, 4)
+    s4 = np.sqrt(4.0 * np.pi)
+
+    def fn(x, y):
+        rho = gamma * gamma + 0 * x
+        vel = [-fac[0] * np.sin(y + ph[0]), fac[1] * np.sin(x + ph[1]), 0 * x]
+        B = [-s4 * fac[2] * np.sin(y + ph[2]), s4 * fac[3] * np.sin(2 * x + ph[3]), 0 * x]
+        return mhd_conserved(rho, vel, gamma + 0 * x, B, gamma=gamma)
+    L = 2.0 * np.pi
+    return _cell_average(fn, (n, n), (0.0, 0.0), (L, L))
+
+
 def sine_wave(n, dim=2, L=1.0):
     """Average of sin(2 pi (x + y [+ z]) / L) on the periodic cube [0, L]^d."""
     fn = lambda *c: np.sin(2.0 * np.pi * sum(c) / L)[None]

@@ -4,7 +4,7 @@ import sys
 import numpy as np
 
 import oracle
-from oracle import Euler, LinearAdvection, Problem as OProblem
+from oracle import Euler, GLMMHD, LinearAdvection, Problem as OProblem
 from paper_1212_3585_amd import workloads as wl
 
 BCS = {"periodic": 0, "transmissive": 1}
@@ -17,13 +17,19 @@ def say(msg):
 
 
 def make_pair(ader, dim, M, n, lo, hi, bc="periodic", system="euler", adv=(1.0, 0.5, 0.25),
-              precision=0, cfl=0.9, tol=1e-14, maxit=64, gamma=1.4):
-    """(oracle problem, GPU problem) describing the same mesh and scheme."""
+              precision=0, cfl=0.9, tol=1e-14, maxit=64, gamma=None, ch=2.0):
+    """(oracle problem, GPU problem) describing the same mesh and scheme.
+    system: "euler" (gamma 1.4), "mhd" (GLM-MHD, gamma 5/3, cleaning speed ch)
+    or "linadv"."""
     bcs = [bc] * dim if isinstance(bc, str) else list(bc)
-    sysobj = Euler(dim, gamma) if system == "euler" else LinearAdvection(dim, adv)
+    if gamma is None:
+        gamma = 5.0 / 3.0 if system == "mhd" else 1.4
+    sysobj = {"euler": lambda: Euler(dim, gamma), "mhd": lambda: GLMMHD(dim, gamma, ch),
+              "linadv": lambda: LinearAdvection(dim, adv)}[system]()
+    sys_id = {"euler": ader.SYS_EULER, "mhd": ader.SYS_MHD_GLM, "linadv": ader.SYS_LINADV}[system]
     op = OProblem(dim, M, sysobj, tuple(n), tuple(lo), tuple(hi), bcs, cfl=cfl,
                   tol=tol, max_iter=maxit)
-    gp = ader.Problem(dim=dim, M=M, system=ader.SYS_EULER if system == "euler" else ader.SYS_LINADV,
+    gp = ader.Problem(dim=dim, M=M, system=sys_id, ch=ch,
                       gamma=gamma, adv=tuple(adv), n=tuple(n) + (1,) * (3 - dim),
                       lo=tuple(lo) + (0.0,) * (3 - dim), hi=tuple(hi) + (1.0,) * (3 - dim),
                       bc=tuple(BCS[b] for b in bcs) + (0,) * (3 - dim), cfl=cfl,
