@@ -132,18 +132,28 @@ SERVE_T_END = 0.5
 
 
 def serving_requests(ader, wl, count, seed=4):
-    """Seeded request mix of the serving workload: 2D Euler Kelvin-Helmholtz
-    solves with their own perturbation seeds, meshes 32^2..512^2 and degrees
-    M = 1..3 drawn uniformly, each to t = 0.5, fp64."""
+    """Seeded request mix of the serving workload: half 2D Euler
+    Kelvin-Helmholtz solves (unit square, gamma 1.4), half GLM-MHD
+    Orszag-Tang solves ([0, 2 pi]^2, gamma 5/3, c_h = 2, random phases and
+    amplitudes), each with its own seed; meshes 32^2..512^2 and degrees
+    M = 1..3 drawn uniformly; each to t = 0.5, fp64."""
     import numpy as np
     r = np.random.Generator(np.random.PCG64(seed))
     reqs = []
     for i in range(count):
         n = int(r.choice(SERVE_SIZES))
         M = int(r.choice(SERVE_ORDERS))
-        prob = ader.Problem(dim=2, M=M, n=(n, n, 1), precision=ader.PREC_FP64,
-                            picard_tol=1e-14)
-        reqs.append((prob, wl.kelvin_helmholtz(n, seed=100 + i), SERVE_T_END))
+        if i % 2 == 0:
+            prob = ader.Problem(dim=2, M=M, n=(n, n, 1), precision=ader.PREC_FP64,
+                                picard_tol=1e-14)
+            U0 = wl.kelvin_helmholtz(n, seed=100 + i)
+        else:
+            L = 2.0 * np.pi
+            prob = ader.Problem(dim=2, M=M, system=ader.SYS_MHD_GLM, gamma=5.0 / 3.0, ch=2.0,
+                                n=(n, n, 1), lo=(0.0, 0.0, 0.0), hi=(L, L, 1.0),
+                                precision=ader.PREC_FP64, picard_tol=1e-14)
+            U0 = wl.orszag_tang(n, seed=100 + i)
+        reqs.append((prob, U0, SERVE_T_END))
     return reqs
 
 
@@ -186,7 +196,8 @@ def serving_leg(ader, wl, count, hbm_bytes=16 << 30, seed=4):
     closed = serve(ader, reqs, None, hbm_bytes)
     mu = count / closed["makespan"]
     out = {
-        "workload": f"{count} independent 2D Euler KH solves to t = {SERVE_T_END}, meshes "
+        "workload": f"{count} independent 2D solves (alternately Euler KH and GLM-MHD "
+                    f"Orszag-Tang) to t = {SERVE_T_END}, meshes "
                     f"{SERVE_SIZES[0]}^2..{SERVE_SIZES[-1]}^2, M in {list(SERVE_ORDERS)}, fp64, "
                     f"drawn uniformly (PCG64 seed {seed}); server arena {hbm_bytes >> 30} GiB, "
                     "4 streams",
