@@ -6,7 +6,9 @@ One step (Section 2):
   1. time step from the CFL condition on the current averages;
   2. WENO reconstruction w_h of every cell (Section 2.2, oracle/weno.py);
   3. space-time predictor q_h of every cell (Section 2.3, oracle/predictor.py);
-  4. numerical fluxes: Rusanov flux (eq. rusanov) between the two predictor
+  4. numerical fluxes: Rusanov flux (eq. rusanov), or the Osher-type flux
+     (eq. osher) with a 3-point Gauss-Legendre path integral of |A| taken
+     from the eigendecomposition of the flux Jacobian, between the two predictor
      traces at the tensor Gauss-Legendre points of each face in the transverse
      directions and in time, summed with the Gauss weights, which is the
      space-time average of eqs. flux:F, flux:G, flux:H on the unit reference
@@ -46,6 +48,7 @@ class Problem:
     cfl: float = 0.9
     tol: float = 1e-14
     max_iter: int = 64
+    flux: str = "rusanov"             # "rusanov" (eq. rusanov) or "osher" (eq. osher)
 
     @property
     def dx(self):
@@ -89,6 +92,50 @@ def rusanov(system, qL: np.ndarray, qR: np.ndarray, k: int) -> np.ndarray:
     """Rusanov / local Lax-Friedrichs flux of eq. rusanov along axis k."""
     smax = np.maximum(system.max_speed(qL, k), system.max_speed(qR, k))
     return 0.5 * (system.flux(qL, k) + system.flux(qR, k)) - 0.5 * smax * (qR - qL)
+
+
+def flux_jacobian(system, Q: np.ndarray, k: int) -> np.ndarray:
+    """A = d f_k / d u at the states Q[nv, N] -> [N, nv, nv], by complex-step
+    differentiation (exact to rounding for the rational fluxes used here)."""
+    nv, npts = Q.shape
+    J = np.empty((npts, nv, nv))
+    h = 1e-30
+    for j in range(nv):
+        dq = Q.astype(complex)
+        dq[j] += 1j * h
+        J[:, :, j] = (system.flux(dq, k).imag / h).T
+    return J
+
+
+def abs_matrix(A: np.ndarray) -> np.ndarray:
+    """|A| = R |Lambda| R^-1 from the eigendecomposition of A[..., nv, nv]
+    (hyperbolic: real eigenvalues, a complete set of eigenvectors)."""
+    lam, R = np.linalg.eig(A)
+    return np.real(R @ (np.abs(lam)[..., :, None] * np.linalg.inv(R)))
+
+
+OSHER_NODES = 3  # Gauss-Legendre points of the path integral (the paper asks for >= 2)
+
+
+def osher(system, qL: np.ndarray, qR: np.ndarray, k: int) -> np.ndarray:
+    """Osher-type flux of eq. osher along axis k: the path integral of |A|
+    along psi(s) = qL + s (qR - qL) by Gauss-Legendre quadrature in s."""
+    from .basis import gauss_legendre
+    s, w = gauss_legendre(OSHER_NODES)
+    shape = qL.shape
+    a = qL.reshape(shape[0], -1)
+    dq = qR.reshape(shape[0], -1) - a
+    Aint = sum(w[j] * abs_matrix(flux_jacobian(system, a + s[j] * dq, k))
+               for j in range(OSHER_NODES))                      # [N, nv, nv]
+    diss = np.einsum("pij,jp->ip", Aint, dq)
+    central = 0.5 * (system.flux(qL, k) + system.flux(qR, k))
+    return central - 0.5 * diss.reshape(shape)
+
+
+def numerical_flux(prob, qL: np.ndarray, qR: np.ndarray, k: int) -> np.ndarray:
+    if prob.flux == "osher":
+        return osher(prob.system, qL, qR, k)
+    return rusanov(prob.system, qL, qR, k)
 
 
 def face_average(Ft: np.ndarray, prob: Problem) -> np.ndarray:
@@ -155,7 +202,7 @@ def step(prob: Problem, U: np.ndarray, dt: float):
             qR[:, nf - 1] = qL[:, nf - 1]
             qL = qL.reshape(qL.shape[0], nf * rest, *qL.shape[3:])
             qR = qR.reshape(qR.shape[0], nf * rest, *qR.shape[3:])
-        F = face_average(rusanov(prob.system, qL, qR, k), prob)  # [v, nf*rest]
+        F = face_average(numerical_flux(prob, qL, qR, k), prob)  # [v, nf*rest]
         F = F.reshape(F.shape[0], nf, rest)
         lo_face = np.arange(nk)
         hi_face = np.arange(1, nk + 1) % nf if periodic else np.arange(1, nk + 1)
@@ -208,7 +255,7 @@ def step_cells(prob: Problem, U: np.ndarray, dt: float, cells: np.ndarray):
                 qL, qR = tr1[:, me].copy(), tr0[:, other].copy()
                 if prob.bc[k] != "periodic":
                     qR[:, outside] = qL[:, outside]
-            fluxes.append(face_average(rusanov(prob.system, qL, qR, k), prob))
+            fluxes.append(face_average(numerical_flux(prob, qL, qR, k), prob))
         out -= (dt / prob.dx[k]) * (fluxes[1] - fluxes[0])
     return out, iters[me]
 
