@@ -7,7 +7,8 @@
  * volume scheme (Section 2): dimension-by-dimension polynomial WENO
  * reconstruction (Section 2.2), element-local space-time DG predictor solved
  * by Picard iteration (Section 2.3, eq. stdg.final), Rusanov fluxes at the
- * space-time Gauss-Legendre points of every face (eqs. flux:F-H, rusanov) and
+ * space-time Gauss-Legendre points of every face (eqs. flux:F-H, rusanov; or
+ * the Osher-type flux of eq. osher) and
  * the conservative update (eq. finite_vol).
  *
  * Conventions shared by every call:
@@ -64,6 +65,15 @@ typedef enum { ADER_SYS_LINADV = 0, ADER_SYS_EULER = 1, ADER_SYS_MHD_GLM = 2 } a
  * nonlinear weights), Rusanov flux, flux quadrature and update stay fp64. */
 typedef enum { ADER_PREC_FP64 = 0, ADER_PREC_FP32_PREDICTOR = 1 } ader_precision;
 
+/* Numerical flux at the space-time Gauss points of a face: Rusanov (eq.
+ * rusanov, local Lax-Friedrichs) or the Osher-type flux (eq. osher): the
+ * path integral of |A| = R |Lambda| R^-1 of the flux Jacobian along the
+ * straight segment between the two traces by 3-point Gauss-Legendre
+ * quadrature, with the analytic Euler eigenvectors.  Osher is available
+ * for the Euler equations; for linear advection both fluxes are the upwind
+ * flux; GLM-MHD takes Rusanov only (EUNSUPPORTED otherwise). */
+typedef enum { ADER_FLUX_RUSANOV = 0, ADER_FLUX_OSHER = 1 } ader_flux;
+
 /* Periodic, or transmissive: zero-gradient ghost averages for the WENO
  * stencils and, on a boundary face, outer predictor trace = inner trace. */
 typedef enum { ADER_BC_PERIODIC = 0, ADER_BC_TRANSMISSIVE = 1 } ader_bc;
@@ -80,6 +90,7 @@ typedef struct {
   double hi[3];       /* domain upper corner */
   int bc[3];          /* ader_bc per axis (both sides of an axis alike) */
   double cfl;         /* Courant number of the time-step rule, in (0, 1] */
+  int flux;           /* ader_flux */
   int precision;      /* ader_precision */
   double picard_tol;  /* relative stop tolerance of the predictor iteration */
   int picard_max;     /* iteration cap (1..1000); reaching it sets a flag */

@@ -19,6 +19,7 @@ OK, EINVAL, EUNSUPPORTED, EHIP, EWORKSPACE = 0, -1, -2, -3, -4
 SYS_LINADV, SYS_EULER, SYS_MHD_GLM = 0, 1, 2
 PREC_FP64, PREC_FP32_PREDICTOR = 0, 1
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
+FLUX_RUSANOV, FLUX_OSHER = 0, 1
 FLAG_NAN, FLAG_NONPHYSICAL, FLAG_NOCONV, FLAG_BADINDEX = 1, 2, 4, 8
 
 # every symbol declared in include/ader.h
@@ -49,7 +50,7 @@ class CProblem(ctypes.Structure):
         ("gamma", ctypes.c_double), ("ch", ctypes.c_double), ("adv", ctypes.c_double * 3),
         ("n", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
         ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int * 3),
-        ("cfl", ctypes.c_double), ("precision", ctypes.c_int),
+        ("cfl", ctypes.c_double), ("flux", ctypes.c_int), ("precision", ctypes.c_int),
         ("picard_tol", ctypes.c_double), ("picard_max", ctypes.c_int),
     ]
 
@@ -162,6 +163,7 @@ class Problem:
     hi: tuple = (1.0, 1.0, 1.0)
     bc: tuple = (BC_PERIODIC, BC_PERIODIC, BC_PERIODIC)
     cfl: float = 0.9
+    flux: int = FLUX_RUSANOV
     precision: int = PREC_FP64
     picard_tol: float = 1e-14
     picard_max: int = 64
@@ -177,6 +179,7 @@ class Problem:
         c.hi[:] = list(self.hi)[:3] + [1.0] * (3 - len(self.hi))
         c.bc[:] = list(self.bc)[:3] + [0] * (3 - len(self.bc))
         c.cfl = self.cfl
+        c.flux = self.flux
         c.precision = self.precision
         c.picard_tol = self.picard_tol
         c.picard_max = self.picard_max

@@ -58,6 +58,10 @@ ader_status validate_problem(const ader_problem& pr, int64_t* ncells_out) {
   if (pr.system == ADER_SYS_LINADV)
     for (int k = 0; k < 3; ++k)
       if (!is_finite(pr.adv[k])) return fail(ADER_EINVAL, "advection velocity must be finite");
+  if (pr.flux != ADER_FLUX_RUSANOV && pr.flux != ADER_FLUX_OSHER)
+    return fail(ADER_EINVAL, "unknown numerical flux");
+  if (pr.flux == ADER_FLUX_OSHER && pr.system == ADER_SYS_MHD_GLM)
+    return fail(ADER_EUNSUPPORTED, "the Osher-type flux is built for Euler and advection");
   if (!is_finite(pr.picard_tol) || !(pr.picard_tol > 0.0))
     return fail(ADER_EINVAL, "picard_tol must be > 0");
   if (pr.picard_max < 1 || pr.picard_max > 1000)
@@ -86,6 +90,10 @@ void fill_dev_consts(const RefConstants& r, int M, DevConsts* out) {
       for (int al = 0; al < M; ++al) c.dnode[al][a][b] = (double)r.dnode[al][a][b];
     }
   }
+  for (int j = 0; j < kOsherNodes; ++j) {
+    c.path_s[j] = (double)r.path_s[j];
+    c.path_w[j] = (double)r.path_w[j];
+  }
   for (int s = 0; s < r.nstencils; ++s) {
     c.lam[s] = (double)r.lambda[s];
     for (int pp = 0; pp < n; ++pp)
@@ -105,6 +113,7 @@ void fill_mesh_params(const ader_problem& pr, int64_t ncells, MeshParams* out) {
   }
   mp.gamma = pr.gamma;
   mp.ch = pr.system == ADER_SYS_MHD_GLM ? pr.ch : 0.0;
+  mp.flux = pr.system == ADER_SYS_EULER ? pr.flux : ADER_FLUX_RUSANOV;
   mp.tol = pr.picard_tol;
   mp.maxit = pr.picard_max;
   mp.ncells = ncells;

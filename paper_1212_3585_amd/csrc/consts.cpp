@@ -118,6 +118,7 @@ bool build_ref_constants(int M, RefConstants* out) {
   c.M = M;
   c.n = n;
   gauss_legendre(n, c.nodes, c.weights);
+  gauss_legendre(kOsherNodes, c.path_s, c.path_w);
   if (n == 1) {
     c.nodes[0] = 0.5L;
     c.weights[0] = 1.0L;

@@ -14,6 +14,8 @@ namespace ader {
 
 constexpr int kMaxN = 4;  // n = M + 1 <= 4  (M <= 3)
 
+constexpr int kOsherNodes = 3;  // path-integral points (the paper asks for >= 2)
+
 struct RefConstants {
   int M = 0;
   int n = 1;
@@ -31,6 +33,8 @@ struct RefConstants {
   long double sigma[kMaxN][kMaxN];           // oscillation matrix
   // dnode[alpha-1][k][p] = d^alpha psi_p / dxi^alpha at node k, alpha = 1..M
   long double dnode[kMaxN - 1][kMaxN][kMaxN];
+  // Gauss-Legendre rule on [0, 1] of the Osher path integral (eq. osher)
+  long double path_s[kOsherNodes], path_w[kOsherNodes];
 };
 
 // Fills 'out' for degree M (0..3). Returns false if a matrix is singular.

@@ -22,7 +22,7 @@
 //
 // k_face2d   one block = a 16 x 4 tile of cells; one 16-lane group per face,
 //            one lane per space-time Gauss point of the face: Rusanov flux
-//            (eq. rusanov) between the two traces, weighted by the Gauss
+//            (eq. rusanov) or Osher-type flux (eq. osher) between the two traces, weighted by the Gauss
 //            weights and summed over the group (eqs. flux:F, flux:G); then the
 //            conservative update of the tile's cells (eq. finite_vol).  A face
 //            on a tile edge is computed by both tiles with the same code and
@@ -368,21 +368,6 @@ k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
   cell2d_tile<M, SYS, TY, R>(blockIdx.x, blockIdx.y, u, ld, traces, dt_dev, mp, c, hdr);
 }
 
-template <int M, int SYS>
-__device__ __forceinline__ void rusanov_point(const double (&qL)[NVars<SYS, 2>::v],
-                                              const double (&qR)[NVars<SYS, 2>::v], int k,
-                                              const MeshParams& mp,
-                                              double (&F)[NVars<SYS, 2>::v]) {
-  constexpr int NV = NVars<SYS, 2>::v;
-  const double adv[3] = {mp.adv[0], mp.adv[1], mp.adv[2]};
-  double fL[NV], fR[NV], sL, sR;
-  phys_flux_dir<SYS, 2>(qL, k, mp.gamma, mp.ch, adv, fL, sL);
-  phys_flux_dir<SYS, 2>(qR, k, mp.gamma, mp.ch, adv, fR, sR);
-  const double smax = fmax(sL, sR);
-#pragma unroll
-  for (int v = 0; v < NV; ++v) F[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * smax * (qR[v] - qL[v]);
-}
-
 constexpr int kFaceTX = 16, kFaceTY = 4;
 
 // One 16 x 4 tile of the face kernel (every thread of the block calls it).
@@ -460,7 +445,7 @@ __device__ __forceinline__ void face2d_tile(int tile_x, int tile_y, const TR* __
         }
       }
       double Fpt[NV];
-      rusanov_point<M, SYS>(qL, qR, k, mp, Fpt);
+      numerical_flux<SYS, 2>(qL, qR, k, mp, c, Fpt);
 #pragma unroll
       for (int v = 0; v < NV; ++v) Fp[v] = wts * Fpt[v];
     }

@@ -35,6 +35,7 @@ struct DevConsts {
   double sigma[4][4];
   double dnode[3][4][4];  // [alpha-1][k][p]: alpha-th derivative of psi_p at node k
   double lam[4];
+  double path_s[3], path_w[3];  // Osher path-integral Gauss-Legendre rule on [0, 1]
   float dmat_f[4][4];
   float tinvw_f[4][4];
   float psi0_f[4], psi1_f[4];
@@ -46,6 +47,7 @@ struct MeshParams {
   double dx[3];
   double gamma;
   double ch;          // GLM cleaning speed (MHD)
+  int flux;           // 0 Rusanov, 1 Osher-type
   double adv[3];
   double tol;
   int maxit;
@@ -245,6 +247,90 @@ __device__ __forceinline__ void phys_flux_dir(const double (&q)[NVars<SYS, DIM>:
     const double cf = sqrt(0.5 * (sum + sqrt(fmax(sum * sum - 4.0 * a2 * bk2, 0.0))));
     speed = fmax(fabs(vk) + cf, ch);
   }
+}
+
+// |A(q)| dq for the Euler flux along axis k: sum_i |lambda_i| r_i (l_i . dq)
+// with the textbook right and left eigenvectors in conserved variables
+// (lambda = v_k - c, v_k (entropy, d - 1 shear), v_k + c).
+template <int DIM>
+__device__ __forceinline__ void euler_abs_jacobian_apply(const double (&q)[DIM + 2], int k,
+                                                         double gamma,
+                                                         const double (&dq)[DIM + 2],
+                                                         double (&out)[DIM + 2]) {
+  const double rho = q[0];
+  const double ir = 1.0 / rho;
+  double v[DIM], q2 = 0.0, vdm = 0.0;
+#pragma unroll
+  for (int m = 0; m < DIM; ++m) {
+    v[m] = q[1 + m] * ir;
+    q2 += v[m] * v[m];
+    vdm += v[m] * dq[1 + m];
+  }
+  const double p = (gamma - 1.0) * (q[DIM + 1] - 0.5 * rho * q2);
+  const double c = sqrt(gamma * p * ir);
+  const double H = (q[DIM + 1] + p) * ir;
+  double un = 0.0, dmk = 0.0;
+#pragma unroll
+  for (int m = 0; m < DIM; ++m)
+    if (m == k) { un = v[m]; dmk = dq[1 + m]; }
+  const double b1 = (gamma - 1.0) / (c * c), b2 = 0.5 * b1 * q2;
+  const double base = b1 * (dq[DIM + 1] - vdm);  // b1 (dE - v . dm)
+  // characteristic amplitudes, each times |lambda|
+  const double a1 = fabs(un - c) * 0.5 * (b2 * dq[0] + base - (dmk - un * dq[0]) / c);
+  const double a4 = fabs(un + c) * 0.5 * (b2 * dq[0] + base + (dmk - un * dq[0]) / c);
+  const double ae = fabs(un) * ((1.0 - b2) * dq[0] - base);
+  out[0] = a1 + ae + a4;
+#pragma unroll
+  for (int m = 0; m < DIM; ++m) {
+    // shear amplitude of direction m != k: (dm_m - v_m drho) |v_k|
+    const double at = m == k ? 0.0 : fabs(un) * (dq[1 + m] - v[m] * dq[0]);
+    out[1 + m] = (a1 + ae + a4) * v[m] + at + (m == k ? c * (a4 - a1) : 0.0);
+  }
+  double shear_e = 0.0;
+#pragma unroll
+  for (int m = 0; m < DIM; ++m)
+    if (m != k) shear_e += fabs(un) * (dq[1 + m] - v[m] * dq[0]) * v[m];
+  out[DIM + 1] = (a1 + a4) * H + un * c * (a4 - a1) + ae * 0.5 * q2 + shear_e;
+}
+
+// Numerical flux between traces qL | qR across a face normal to axis k:
+// Rusanov (eq. rusanov) or the Osher-type flux (eq. osher, Euler only; for
+// linear advection it equals the upwind flux, which Rusanov already is).
+template <int SYS, int DIM>
+__device__ __forceinline__ void numerical_flux(const double (&qL)[NVars<SYS, DIM>::v],
+                                               const double (&qR)[NVars<SYS, DIM>::v], int k,
+                                               const MeshParams& mp, const DevConsts& c,
+                                               double (&F)[NVars<SYS, DIM>::v]) {
+  constexpr int NV = NVars<SYS, DIM>::v;
+  const double adv[3] = {mp.adv[0], mp.adv[1], mp.adv[2]};
+  double fL[NV], fR[NV], sL, sR;
+  phys_flux_dir<SYS, DIM>(qL, k, mp.gamma, mp.ch, adv, fL, sL);
+  phys_flux_dir<SYS, DIM>(qR, k, mp.gamma, mp.ch, adv, fR, sR);
+  if constexpr (SYS == 1) {
+    if (mp.flux == 1) {
+      double dq[NV], acc[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        dq[v] = qR[v] - qL[v];
+        acc[v] = 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double qs[NV], t[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) qs[v] = qL[v] + c.path_s[j] * dq[v];
+        euler_abs_jacobian_apply<DIM>(qs, k, mp.gamma, dq, t);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] += c.path_w[j] * t[v];
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) F[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * acc[v];
+      return;
+    }
+  }
+  const double smax = fmax(sL, sR);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) F[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * smax * (qR[v] - qL[v]);
 }
 
 // Density and pressure positive (Euler, GLM-MHD); always true for advection.
@@ -639,11 +725,8 @@ k_face_flux(const R* __restrict__ qh, double* __restrict__ F, int64_t nfaces, Me
         for (int v = 0; v < NV; ++v) qR[v] = qL[v];
       }
     }
-    double fL[NV], fR[NV], sL, sR;
-    const double adv[3] = {mp.adv[0], mp.adv[1], mp.adv[2]};
-    phys_flux_dir<SYS, DIM>(qL, K, mp.gamma, mp.ch, adv, fL, sL);
-    phys_flux_dir<SYS, DIM>(qR, K, mp.gamma, mp.ch, adv, fR, sR);
-    const double smax = fmax(sL, sR);
+    double Fpt[NV];
+    numerical_flux<SYS, DIM>(qL, qR, K, mp, c, Fpt);
     double wt = c.w[s];
     {
       int ti = 0;
@@ -657,7 +740,7 @@ k_face_flux(const R* __restrict__ qh, double* __restrict__ F, int64_t nfaces, Me
     wpt = wt;
 #pragma unroll
     for (int v = 0; v < NV; ++v)
-      sh[v * kBlock + tid] = wt * (0.5 * (fL[v] + fR[v]) - 0.5 * smax * (qR[v] - qL[v]));
+      sh[v * kBlock + tid] = wt * Fpt[v];
   }
   (void)wpt;
   __syncthreads();

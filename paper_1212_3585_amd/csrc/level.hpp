@@ -14,7 +14,8 @@
 //   (predictor)           the uniform-mesh predictor kernels on the list.
 //   k_level_update        per updated cell: predictor traces of the cell and
 //                         of each face neighbour at the face Gauss points,
-//                         Rusanov flux (eq. rusanov), Gauss sum (eqs.
+//                         Rusanov (eq. rusanov) or Osher-type (eq. osher)
+//                         flux, Gauss sum (eqs.
 //                         flux:F-H) and the update (eq. finite_vol).  A face
 //                         shared by two updated cells is evaluated by both
 //                         with the same operand order, hence bitwise equal.
@@ -133,7 +134,6 @@ k_level_update(const R* __restrict__ qh, const int32_t* __restrict__ pred_cells,
   if (in && me >= 0 && cell >= 0 && cell < ld) {
     const double dt = *dt_dev;
     const double dxk[3] = {dx0, dx1, dx2};
-    const double adv[3] = {mp.adv[0], mp.adv[1], mp.adv[2]};
     double q[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) q[v] = u_in[(int64_t)v * ld + cell];
@@ -162,10 +162,8 @@ k_level_update(const R* __restrict__ qh, const int32_t* __restrict__ pred_cells,
 #pragma unroll
               for (int v = 0; v < NV; ++v) qR[v] = qL[v];
             }
-            double fL[NV], fR[NV], sL, sR;
-            phys_flux_dir<SYS, DIM>(qL, k, mp.gamma, mp.ch, adv, fL, sL);
-            phys_flux_dir<SYS, DIM>(qR, k, mp.gamma, mp.ch, adv, fR, sR);
-            const double smax = fmax(sL, sR);
+            double Fpt[NV];
+            numerical_flux<SYS, DIM>(qL, qR, k, mp, c, Fpt);
             double wt = c.w[s];
             {
               int tt[2] = {tb % n, tb / n};
@@ -173,7 +171,7 @@ k_level_update(const R* __restrict__ qh, const int32_t* __restrict__ pred_cells,
             }
 #pragma unroll
             for (int v = 0; v < NV; ++v)
-              F[side][v] += wt * (0.5 * (fL[v] + fR[v]) - 0.5 * smax * (qR[v] - qL[v]));
+              F[side][v] += wt * Fpt[v];
           }
         }
       }

@@ -17,7 +17,7 @@ def say(msg):
 
 
 def make_pair(ader, dim, M, n, lo, hi, bc="periodic", system="euler", adv=(1.0, 0.5, 0.25),
-              precision=0, cfl=0.9, tol=1e-14, maxit=64, gamma=None, ch=2.0):
+              precision=0, cfl=0.9, tol=1e-14, maxit=64, gamma=None, ch=2.0, flux="rusanov"):
     """(oracle problem, GPU problem) describing the same mesh and scheme.
     system: "euler" (gamma 1.4), "mhd" (GLM-MHD, gamma 5/3, cleaning speed ch)
     or "linadv"."""
@@ -28,8 +28,9 @@ def make_pair(ader, dim, M, n, lo, hi, bc="periodic", system="euler", adv=(1.0, 
               "linadv": lambda: LinearAdvection(dim, adv)}[system]()
     sys_id = {"euler": ader.SYS_EULER, "mhd": ader.SYS_MHD_GLM, "linadv": ader.SYS_LINADV}[system]
     op = OProblem(dim, M, sysobj, tuple(n), tuple(lo), tuple(hi), bcs, cfl=cfl,
-                  tol=tol, max_iter=maxit)
+                  tol=tol, max_iter=maxit, flux=flux)
     gp = ader.Problem(dim=dim, M=M, system=sys_id, ch=ch,
+                      flux={"rusanov": ader.FLUX_RUSANOV, "osher": ader.FLUX_OSHER}[flux],
                       gamma=gamma, adv=tuple(adv), n=tuple(n) + (1,) * (3 - dim),
                       lo=tuple(lo) + (0.0,) * (3 - dim), hi=tuple(hi) + (1.0,) * (3 - dim),
                       bc=tuple(BCS[b] for b in bcs) + (0,) * (3 - dim), cfl=cfl,

@@ -208,3 +208,16 @@ def test_orszag_tang_field_is_divergence_free():
     assert np.allclose(Bx, Bx[:1, :], atol=1e-14)   # independent of x
     assert np.allclose(By, By[:, :1], atol=1e-14)   # independent of y
     assert np.all(U[8] == 0) and np.all(U[3] == 0) and np.all(U[7] == 0)
+
+
+def test_flux_selector_validation(ader_mod):
+    lib = ader_mod.load_library()
+    h = ctypes.c_void_p()
+    ok = ader_mod.Problem(dim=2, M=2, n=(8, 8, 1), flux=ader_mod.FLUX_OSHER)
+    assert lib.ader_plan_create(ctypes.byref(ok.to_c()), ctypes.byref(h)) == 0
+    lib.ader_plan_destroy(h)
+    bad = ader_mod.Problem(dim=2, M=2, n=(8, 8, 1), flux=2)
+    assert lib.ader_plan_create(ctypes.byref(bad.to_c()), ctypes.byref(h)) == ader_mod.EINVAL
+    mhd = ader_mod.Problem(dim=2, M=2, system=ader_mod.SYS_MHD_GLM, gamma=5 / 3, n=(8, 8, 1),
+                           flux=ader_mod.FLUX_OSHER)
+    assert lib.ader_plan_create(ctypes.byref(mhd.to_c()), ctypes.byref(h)) == ader_mod.EUNSUPPORTED
