@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY.  This package is the plain, slow, obviously-correct
 definition of what the hot path computes, written from the paper (Dumbser,
 Zanotti, Hidalgo, Balsara, "ADER-WENO finite volume schemes with space-time
-adaptive mesh refinement"), Section 2.  Only the tests, the package's smoke
+adaptive mesh refinement"), Sections 2 and 3.  Only the tests, the package's smoke
 check and the benchmark's CPU-baseline leg may import it; the HIP product path
 never does, and it shares no code, headers, tables or constant generators with
 it.  Seeded inputs come from paper_1212_3585_amd.workloads, which holds none of
@@ -15,7 +15,9 @@ Modules:
   physics    Euler (Section 4.1), GLM-MHD (Section 4.2) and linear-advection
              fluxes and wave speeds
   predictor  space-time DG predictor with Picard iteration (Section 2.3)
-  scheme     CFL time step, Rusanov face fluxes, finite-volume update (2.1)
+  scheme     CFL time step, Rusanov / Osher face fluxes, finite-volume update (2.1)
+  amr        cell-by-cell AMR with local time stepping: Loehner indicator,
+             projection, averaging, memory-variable flux sums (Section 3)
   brute      independent brute-force routes used to pin the above
 
 Every function is fp64 numpy; batching over cells is the only vectorisation.
