@@ -295,6 +295,78 @@ ader_status ader_server_progress(ader_server server, int wait, int* resident, in
 ader_status ader_server_request(ader_server server, int64_t id, ader_request_info* info);
 ader_status ader_server_stats_get(ader_server server, ader_server_stats* stats);
 
+/* ------------------------------------------------------------------------
+ * Cell-by-cell AMR with time-accurate local time stepping (Section 3).
+ *
+ * Mesh: level 0 is the problem's uniform mesh; level l refines it by r^l per
+ * axis (eq. refine-factor, max(M, 2) <= r <= 4, levels 0..max_level <= 5).
+ * Every level is held on the device as a dense array over its whole index
+ * space ([nvar][cells], x fastest, the layout of ader_step) with a status per
+ * cell: active (updated by the scheme), virtual child (projection of the
+ * mother's space-time predictor, Section 3.1.3), virtual mother (average of
+ * its children, eq. average) or absent.  Children of a cell are the r^d
+ * consecutive-index blocks i*r + a; the mother of i is i / r.
+ *
+ * ader_amr_build constructs the mesh once from the initial averages of
+ * every level: the Loehner indicator (eq. indicator, index units; filter
+ * eps (|P+| + 2|P| + |P-|) on the diagonal pairs, the mean of the four
+ * diagonal neighbours on the cross pairs) of variable indicator_var above
+ * chi_ref flags cells of levels 0..max_level-1, plus 'buffer' layers of
+ * their Voronoi neighbours (ader_amr_set_flags replaces the indicator for a
+ * level; such flags are taken as given).  Flags are closed so that Voronoi neighbours differ by at
+ * most one level and a refined cell's Voronoi neighbours exist on the finer
+ * level; children of flagged cells are active, children of their active
+ * Voronoi neighbours are virtual.  EINVAL if an active cell's (2M+1)^d
+ * stencil would leave the mesh.  The mesh is static afterwards.
+ *
+ * ader_amr_step: one level-0 step, Delta t_0 = min over levels of
+ * r^l CFL / max over active cells of sum_k speed_k / dx_(l,k), clipped to
+ * t_end (an empty step once t_end is reached); level l takes r^l substeps of
+ * Delta t_0 / r^l, finest first (Section 3.1.2): averaging, projection,
+ * reconstruction and predictor, the finer level's substeps, then the update.
+ * A face between a fine active cell and a coarser active cell takes the
+ * coarse predictor at the fine face's space-time Gauss points; the fine
+ * fluxes are kept in memory variables and their average is the coarse
+ * cell's flux (eq. memory.sum): the scheme is conservative.  Time, end time
+ * and level steps live on the device; use_graph records one step as a HIP
+ * graph once and replays it.  Asynchronous on 'stream' (NULL: the object's
+ * own stream); ader_amr_clock synchronises and reads the time.
+ *
+ * The object owns its device memory (allocated by ader_amr_build). */
+typedef struct ader_amr_s* ader_amr;
+
+typedef struct {
+  int r;              /* refinement factor */
+  int max_level;      /* finest level L */
+  int indicator_var;  /* conserved variable fed to the indicator */
+  double chi_ref;     /* refine where chi > chi_ref */
+  double eps;         /* indicator filter (0.01 in the paper) */
+  int buffer;         /* Voronoi layers added around indicator flags (0..4) */
+  int use_graph;      /* replay one recorded step per ader_amr_step */
+} ader_amr_config;
+
+ader_status ader_amr_create(const ader_problem* prob, const ader_amr_config* config,
+                            ader_amr* out);
+ader_status ader_amr_destroy(ader_amr amr);
+/* Dense cells per axis of a level. */
+ader_status ader_amr_level_cells(ader_amr amr, int level, int n[3]);
+/* Initial averages of a level's whole index space (host, [nvar][cells]). */
+ader_status ader_amr_set_level(ader_amr amr, int level, const double* u);
+/* Refinement flags of a level < max_level (host, [cells], nonzero = refine). */
+ader_status ader_amr_set_flags(ader_amr amr, int level, const uint8_t* flags);
+ader_status ader_amr_build(ader_amr amr);
+ader_status ader_amr_step(ader_amr amr, double t_end, void* stream);
+ader_status ader_amr_clock(ader_amr amr, double* t, int64_t* steps, double* dt0);
+/* Level averages (host [nvar][cells]; absent cells NaN) and status (host
+ * [cells]: -2 absent, -1 virtual mother, 0 active, 1 virtual child). */
+ader_status ader_amr_get_level(ader_amr amr, int level, double* u, int8_t* status);
+/* counts[0..2] = active, virtual children, virtual mothers of a level. */
+ader_status ader_amr_counts(ader_amr amr, int level, int64_t counts[3]);
+/* Status bits, predictor iterations and cell updates (active cells times
+ * substeps) since the mesh was built. */
+ader_status ader_amr_stats(ader_amr amr, uint32_t* flags, uint64_t* picard_iterations,
+                           uint64_t* cell_updates);
+
 const char* ader_status_string(ader_status status);
 const char* ader_last_error(void);
 

@@ -17,7 +17,10 @@ are the r^d cells i*r + a, 0 <= a < r (consecutive blocks).
 
 Refinement (built once from the initial data).  A cell of level l < L is
 flagged when the Loehner indicator (eq. indicator) of its level's initial
-averages exceeds chi_ref.  Flags are closed so that the rules of Section 3.1
+averages exceeds chi_ref, and so are its Voronoi neighbours up to 'buffer'
+layers (the paper names no buffer; without one, a single unflagged cell on a
+front leaves a hole of virtual cells in the refined region, whose projected
+averages spoil the fine stencils next to the front).  Flags are closed so that the rules of Section 3.1
 hold: the mother of any cell within the Voronoi neighbourhood of a flagged
 cell is flagged (levels of Voronoi neighbours differ by at most one, and a
 refined cell's Voronoi neighbours exist on the finer level), and flags nest.
@@ -154,7 +157,7 @@ class Hierarchy:
     """Dense per-level state and status arrays of a static AMR mesh."""
 
     def __init__(self, prob: Problem, r: int, L: int, U_levels, chi_ref: float = 0.2,
-                 eps: float = 0.01, indicator_var: int = 0, flags=None):
+                 eps: float = 0.01, indicator_var: int = 0, flags=None, buffer: int = 1):
         if r < max(prob.M, 2):
             raise ValueError("the refinement factor must satisfy r >= M (and r >= 2)")
         self.prob, self.r, self.L, self.d = prob, r, L, prob.dim
@@ -164,6 +167,8 @@ class Hierarchy:
         if flags is None:
             flags = [lohner(U_levels[l][indicator_var], self.bcs, eps) > chi_ref
                      for l in range(L)]
+            for _ in range(buffer):          # buffer layers around indicator flags
+                flags = [_dilate(f, self.bcs) for f in flags]
         F = [np.asarray(f, dtype=bool).copy() for f in flags]
         for l in range(L - 1, 0, -1):
             F[l - 1] |= _mothers(_dilate(F[l], self.bcs), r)

@@ -32,8 +32,12 @@ EXPORTS = [
     "ader_server_create", "ader_server_destroy", "ader_server_footprint",
     "ader_server_submit", "ader_server_progress", "ader_server_request",
     "ader_server_stats_get",
+    "ader_amr_create", "ader_amr_destroy", "ader_amr_level_cells", "ader_amr_set_level",
+    "ader_amr_set_flags", "ader_amr_build", "ader_amr_step", "ader_amr_clock",
+    "ader_amr_get_level", "ader_amr_counts", "ader_amr_stats",
     "ader_status_string", "ader_last_error",
 ]
+AMR_ABSENT, AMR_VMOTHER, AMR_ACTIVE, AMR_VCHILD = -2, -1, 0, 1
 REQ_QUEUED, REQ_RESIDENT, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 STAGES = ["dt", "weno", "predict", "flux", "update"]
 
@@ -84,6 +88,12 @@ class CServerStats(ctypes.Structure):
                 ("completed", ctypes.c_int64)]
 
 
+class CAmrConfig(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int), ("max_level", ctypes.c_int),
+                ("indicator_var", ctypes.c_int), ("chi_ref", ctypes.c_double),
+                ("eps", ctypes.c_double), ("buffer", ctypes.c_int), ("use_graph", ctypes.c_int)]
+
+
 _lib = None
 
 
@@ -123,6 +133,19 @@ def load_library():
                                  ctypes.POINTER(ctypes.c_int)],
         "ader_server_request": [vp, i64, ctypes.POINTER(CRequestInfo)],
         "ader_server_stats_get": [vp, ctypes.POINTER(CServerStats)],
+        "ader_amr_create": [ctypes.POINTER(CProblem), ctypes.POINTER(CAmrConfig),
+                            ctypes.POINTER(vp)],
+        "ader_amr_destroy": [vp],
+        "ader_amr_level_cells": [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
+        "ader_amr_set_level": [vp, ctypes.c_int, vp],
+        "ader_amr_set_flags": [vp, ctypes.c_int, vp],
+        "ader_amr_build": [vp],
+        "ader_amr_step": [vp, dbl, vp],
+        "ader_amr_clock": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl)],
+        "ader_amr_get_level": [vp, ctypes.c_int, vp, vp],
+        "ader_amr_counts": [vp, ctypes.c_int, ctypes.POINTER(i64)],
+        "ader_amr_stats": [vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64),
+                           ctypes.POINTER(ctypes.c_uint64)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -439,3 +462,104 @@ class Server:
             self.progress(wait=True)
             if all(self.info(i)["state"] >= REQ_DONE for i in ids):
                 return
+
+
+def _flat_x_fastest(U):
+    """[nv, nx, ny(, nz)] -> [nv, cells] with x fastest."""
+    nv = U.shape[0]
+    d = U.ndim - 1
+    return np.ascontiguousarray(np.transpose(U, (0,) + tuple(range(d, 0, -1)))).reshape(nv, -1)
+
+
+def _unflat_x_fastest(F, shape):
+    d = len(shape)
+    G = F.reshape((F.shape[0],) + tuple(reversed(shape)))
+    return np.ascontiguousarray(np.transpose(G, (0,) + tuple(range(d, 0, -1))))
+
+
+class Amr:
+    """AMR mesh with local time stepping (ader_amr_*).  Level data are numpy
+    arrays [nvar, nx, ny(, nz)] over each level's whole index space."""
+
+    def __init__(self, problem: Problem, r=3, max_level=1, indicator_var=0, chi_ref=0.2,
+                 eps=0.01, buffer=1, use_graph=True):
+        self.lib = load_library()
+        self.problem = problem
+        self.L = max_level
+        cfg = CAmrConfig(r, max_level, indicator_var, chi_ref, eps, buffer, int(bool(use_graph)))
+        h = ctypes.c_void_p()
+        _check(self.lib.ader_amr_create(ctypes.byref(problem.to_c()), ctypes.byref(cfg),
+                                        ctypes.byref(h)), "ader_amr_create")
+        self._h = h
+        self.shapes = []
+        for l in range(max_level + 1):
+            n = (ctypes.c_int * 3)()
+            _check(self.lib.ader_amr_level_cells(h, l, n), "ader_amr_level_cells")
+            self.shapes.append(tuple(n[:problem.dim]))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.ader_amr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_level(self, level, U):
+        F = np.ascontiguousarray(_flat_x_fastest(np.asarray(U, dtype=np.float64)))
+        _check(self.lib.ader_amr_set_level(self._h, level, F.ctypes.data_as(ctypes.c_void_p)),
+               "ader_amr_set_level")
+
+    def set_flags(self, level, flags):
+        f = np.ascontiguousarray(_flat_x_fastest(np.asarray(flags, dtype=np.uint8)[None])[0])
+        _check(self.lib.ader_amr_set_flags(self._h, level, f.ctypes.data_as(ctypes.c_void_p)),
+               "ader_amr_set_flags")
+
+    def build(self):
+        _check(self.lib.ader_amr_build(self._h), "ader_amr_build")
+
+    def step(self, t_end, stream=None):
+        _check(self.lib.ader_amr_step(self._h, float(t_end), _stream(stream)), "ader_amr_step")
+
+    def clock(self):
+        t, dt0 = ctypes.c_double(), ctypes.c_double()
+        steps = ctypes.c_int64()
+        _check(self.lib.ader_amr_clock(self._h, ctypes.byref(t), ctypes.byref(steps),
+                                       ctypes.byref(dt0)), "ader_amr_clock")
+        return t.value, steps.value, dt0.value
+
+    def run(self, t_end, max_steps=10 ** 9):
+        """Level-0 steps until t_end (reads the clock after each step)."""
+        t, steps, _ = self.clock()
+        while t < t_end and steps < max_steps:
+            self.step(t_end)
+            t, steps, _ = self.clock()
+        return t, steps
+
+    def level(self, level):
+        """(U[nvar, *shape], status[*shape]) of a level."""
+        nv = self.nvar
+        N = int(np.prod(self.shapes[level]))
+        F = np.empty((nv, N))
+        st = np.empty(N, dtype=np.int8)
+        _check(self.lib.ader_amr_get_level(self._h, level, F.ctypes.data_as(ctypes.c_void_p),
+                                           st.ctypes.data_as(ctypes.c_void_p)),
+               "ader_amr_get_level")
+        return (_unflat_x_fastest(F, self.shapes[level]),
+                _unflat_x_fastest(st[None], self.shapes[level])[0])
+
+    @property
+    def nvar(self):
+        s = self.problem.system
+        return 1 if s == SYS_LINADV else (self.problem.dim + 2 if s == SYS_EULER else 9)
+
+    def counts(self, level):
+        c = (ctypes.c_int64 * 3)()
+        _check(self.lib.ader_amr_counts(self._h, level, c), "ader_amr_counts")
+        return {"active": c[0], "vchild": c[1], "vmother": c[2]}
+
+    def stats(self):
+        f, it, cu = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(self.lib.ader_amr_stats(self._h, ctypes.byref(f), ctypes.byref(it),
+                                       ctypes.byref(cu)), "ader_amr_stats")
+        return {"flags": f.value, "picard_iterations": it.value, "cell_updates": cu.value}

@@ -16,7 +16,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libaderweno.so")
-SOURCES = ["consts.cpp", "capi.cpp", "server.cpp", "impl2d.hip", "impl3d.hip", "batch2d.hip"]
+SOURCES = ["consts.cpp", "capi.cpp", "server.cpp", "amr.cpp", "impl2d.hip", "impl3d.hip",
+           "batch2d.hip", "amr2d.hip", "amr3d.hip"]
 ARCH = "gfx950"
 
 
@@ -45,7 +46,7 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build_library(jobs: int = 4) -> str:
+def build_library(jobs: int = 8) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))

@@ -1,0 +1,563 @@
+// AMR driver: mesh construction on the host, per-level device data, and the
+// local-time-stepping schedule of one level-0 step (Section 3), optionally
+// recorded once as a HIP graph and replayed.
+//
+// Mesh construction (ader_amr_build), from the initial averages of every
+// level's full index space:
+//   1. flags: Loehner indicator (eq. indicator) > chi_ref on levels 0..L-1,
+//      widened by 'buffer' Voronoi layers (or flags given by the caller);
+//   2. closure: the mother of every cell in the Voronoi neighbourhood of a
+//      flagged level-l cell is flagged on level l-1 (Voronoi neighbours
+//      differ by at most one level; refined cells have all their Voronoi
+//      neighbours on the finer level); flags nest;
+//   3. status: children of flagged cells are active (virtual mothers if
+//      flagged themselves); children of the active Voronoi neighbours of
+//      flagged cells are virtual children;
+//   4. every active cell's (2M+1)^d stencil must lie in the mesh (r >= M).
+// The indicator is evaluated in plain double arithmetic, term by term, so the
+// integer refinement decisions are reproducible.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "amr_plan.hpp"
+#include "plan.hpp"
+
+using ader::fail;
+using ader::hip_status;
+
+struct ader_amr_s {
+  ader_problem prob{};
+  ader_amr_config cfg{};
+  int d = 2, M = 0, nv = 1, r = 2, L = 0;
+  ader::DevConsts dc{};
+  ader::AmrConsts ac{};
+  const ader::AmrImplBase* impl = nullptr;
+  std::vector<ader::AmrLevel> lv;
+  std::vector<std::vector<double>> h_init;
+  std::vector<std::vector<uint8_t>> h_flags;
+  std::vector<std::vector<int8_t>> h_status;
+  std::vector<void*> dev_allocs;
+  double* partial = nullptr;
+  ader::AmrClock* clock = nullptr;
+  ader::AmrClock* h_clock = nullptr;  // pinned staging
+  hipStream_t stream = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool built = false;
+  double t_end_set = -1.0;
+  uint64_t cell_updates = 0, updates_per_step = 0;
+  ader::AmrDtArgs dtargs{};
+};
+
+namespace {
+
+int64_t ipow(int b, int e) {
+  int64_t r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+struct Grid {
+  int d;
+  int n[3];
+  int64_t cells() const { return (int64_t)n[0] * n[1] * n[2]; }
+  int64_t idx(const int* c) const { return c[0] + (int64_t)n[0] * (c[1] + (int64_t)n[1] * c[2]); }
+  void coords(int64_t i, int* c) const {
+    c[0] = (int)(i % n[0]);
+    c[1] = (int)((i / n[0]) % n[1]);
+    c[2] = (int)(i / ((int64_t)n[0] * n[1]));
+  }
+};
+
+int map_bc(int i, int n, int bc) {
+  if (bc == ADER_BC_PERIODIC) return ((i % n) + n) % n;
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// Loehner indicator on a dense level grid (index units), as the oracle
+// defines it term by term.
+std::vector<double> lohner(const Grid& g, const double* Phi, const int* bc, double eps) {
+  const int64_t N = g.cells();
+  std::vector<double> chi(N, 0.0);
+  auto at = [&](const int* c, const int* o) {
+    int cc[3] = {c[0], c[1], c[2]};
+    for (int k = 0; k < g.d; ++k) cc[k] = map_bc(c[k] + o[k], g.n[k], bc[k]);
+    return Phi[g.idx(cc)];
+  };
+  for (int64_t i = 0; i < N; ++i) {
+    int c[3];
+    g.coords(i, c);
+    const double P = Phi[i];
+    double num = 0.0, den = 0.0;
+    for (int k = 0; k < g.d; ++k) {
+      for (int m = 0; m < g.d; ++m) {
+        double D, De;
+        if (k == m) {
+          int e[3] = {0, 0, 0}, f[3] = {0, 0, 0};
+          e[k] = 1;
+          f[k] = -1;
+          const double p = at(c, e), q = at(c, f);
+          D = p - 2.0 * P + q;
+          De = std::fabs(p - P) + std::fabs(P - q) +
+               eps * (std::fabs(p) + 2.0 * std::fabs(P) + std::fabs(q));
+        } else {
+          int o[3] = {0, 0, 0};
+          auto s = [&](int a, int b) {
+            o[0] = o[1] = o[2] = 0;
+            o[k] = a;
+            o[m] = b;
+            return at(c, o);
+          };
+          const double pp = s(1, 1), pm = s(1, -1), mp = s(-1, 1), mm = s(-1, -1);
+          const double A = pp - mp, B = pm - mm;
+          D = 0.25 * (A - B);
+          De = 0.25 * (std::fabs(A) + std::fabs(B)) +
+               0.25 * eps * (std::fabs(pp) + std::fabs(pm) + std::fabs(mp) + std::fabs(mm));
+        }
+        num += D * D;
+        den += De * De;
+      }
+    }
+    chi[i] = den > 0.0 ? std::sqrt(num / den) : 0.0;
+  }
+  return chi;
+}
+
+std::vector<uint8_t> dilate(const Grid& g, const std::vector<uint8_t>& F, const int* bc) {
+  std::vector<uint8_t> out(F);
+  const int64_t N = g.cells();
+  const int span[3] = {1, g.d > 1 ? 1 : 0, g.d > 2 ? 1 : 0};
+  for (int64_t i = 0; i < N; ++i) {
+    if (!F[i]) continue;
+    int c[3];
+    g.coords(i, c);
+    for (int dz = -span[2]; dz <= span[2]; ++dz)
+      for (int dy = -span[1]; dy <= span[1]; ++dy)
+        for (int dx = -span[0]; dx <= span[0]; ++dx) {
+          const int o[3] = {dx, dy, dz};
+          int cc[3] = {0, 0, 0};
+          bool ok = true;
+          for (int k = 0; k < g.d; ++k) {
+            const int raw = c[k] + o[k];
+            if (bc[k] != ADER_BC_PERIODIC && (raw < 0 || raw >= g.n[k])) ok = false;
+            cc[k] = map_bc(raw, g.n[k], bc[k]);
+          }
+          if (ok) out[g.idx(cc)] = 1;
+        }
+  }
+  return out;
+}
+
+std::vector<uint8_t> mothers(const Grid& fine, const Grid& coarse, const std::vector<uint8_t>& F,
+                             int r) {
+  std::vector<uint8_t> out(coarse.cells(), 0);
+  for (int64_t i = 0; i < fine.cells(); ++i) {
+    if (!F[i]) continue;
+    int c[3];
+    fine.coords(i, c);
+    for (int k = 0; k < fine.d; ++k) c[k] /= r;
+    out[coarse.idx(c)] = 1;
+  }
+  return out;
+}
+
+std::vector<uint8_t> children(const Grid& coarse, const Grid& fine, const std::vector<uint8_t>& F,
+                              int r) {
+  std::vector<uint8_t> out(fine.cells(), 0);
+  for (int64_t i = 0; i < fine.cells(); ++i) {
+    int c[3];
+    fine.coords(i, c);
+    for (int k = 0; k < fine.d; ++k) c[k] /= r;
+    out[i] = F[coarse.idx(c)];
+  }
+  return out;
+}
+
+template <typename T>
+ader_status upload(ader_amr a, T** dst, const void* src, size_t bytes) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes > 0 ? bytes : 256);
+  if (e != hipSuccess) return hip_status(e, "ader_amr_build (allocation)");
+  a->dev_allocs.push_back(p);
+  if (src && bytes) {
+    e = hipMemcpy(p, src, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_status(e, "ader_amr_build (upload)");
+  }
+  *dst = static_cast<T*>(p);
+  return ADER_OK;
+}
+
+ader_status record_advance(ader_amr a, int l, int sub, hipStream_t st) {
+  const ader::AmrImplBase* im = a->impl;
+  hipError_t e = hipSuccess;
+  for (int lev = a->L - 1; lev >= l && e == hipSuccess; --lev)
+    e = im->average(a->lv[lev], a->lv[lev + 1], a->r, st);
+  if (e == hipSuccess && l > 0) e = im->project(a->lv[l], a->lv[l - 1], a->ac, sub, st);
+  if (e == hipSuccess) e = im->predict(a->lv[l], &a->clock->dt[l], a->dc, st);
+  if (e != hipSuccess) return hip_status(e, "ader_amr_step");
+  if (l < a->L) {
+    const ader::AmrLevel& f = a->lv[l + 1];
+    e = ader::launch_fill(f.mem, (int64_t)a->d * 2 * a->nv * f.ncells, 0.0, st);
+    if (e != hipSuccess) return hip_status(e, "ader_amr_step");
+    for (int s = 0; s < a->r; ++s)
+      if (ader_status stt = record_advance(a, l + 1, s, st)) return stt;
+  }
+  e = im->update(a->lv[l], l > 0 ? &a->lv[l - 1] : nullptr, l < a->L ? &a->lv[l + 1] : nullptr,
+                 &a->clock->dt[l], sub, a->dc, a->ac, st);
+  return hip_status(e, "ader_amr_step");
+}
+
+ader_status record_step(ader_amr a, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  for (int l = 0; l <= a->L && e == hipSuccess; ++l)
+    if (a->dtargs.nb[l] > 0)
+      e = a->impl->cfl(a->lv[l], a->partial + (size_t)l * ader::kDtMaxBlocks, a->dtargs.nb[l], st);
+  if (e == hipSuccess) e = ader::launch_amr_dt(a->partial, a->dtargs, a->clock, a->lv[0].hdr, st);
+  if (e != hipSuccess) return hip_status(e, "ader_amr_step");
+  if (ader_status s = record_advance(a, 0, 0, st)) return s;
+  for (int lev = a->L - 1; lev >= 0 && e == hipSuccess; --lev)
+    e = a->impl->average(a->lv[lev], a->lv[lev + 1], a->r, st);
+  return hip_status(e, "ader_amr_step");
+}
+
+}  // namespace
+
+extern "C" {
+
+ader_status ader_amr_create(const ader_problem* prob, const ader_amr_config* cfg, ader_amr* out) {
+  if (!prob || !cfg || !out) return fail(ADER_EINVAL, "null argument");
+  *out = nullptr;
+  int64_t ncells = 0;
+  if (ader_status s = ader::validate_problem(*prob, &ncells)) return s;
+  if (cfg->max_level < 0 || cfg->max_level >= ader::kAmrMaxLevels)
+    return fail(ADER_EINVAL, "max_level must be in 0..5");
+  const int rmin = prob->M > 2 ? prob->M : 2;
+  if (cfg->r < rmin || cfg->r > ader::kAmrMaxR)
+    return fail(ADER_EINVAL, "the refinement factor must satisfy max(M, 2) <= r <= 4");
+  const int nv = prob->system == ADER_SYS_LINADV ? 1
+                 : (prob->system == ADER_SYS_EULER ? prob->dim + 2 : 9);
+  if (cfg->indicator_var < 0 || cfg->indicator_var >= nv)
+    return fail(ADER_EINVAL, "indicator_var out of range");
+  if (!std::isfinite(cfg->chi_ref) || !std::isfinite(cfg->eps) || cfg->eps < 0.0)
+    return fail(ADER_EINVAL, "chi_ref and eps must be finite, eps >= 0");
+  if (cfg->buffer < 0 || cfg->buffer > 4) return fail(ADER_EINVAL, "buffer must be in 0..4");
+  // every level's cell count and the indices of the finest level must fit
+  int64_t fine = ncells * ipow(cfg->r, cfg->max_level * prob->dim);
+  if (fine > (int64_t(1) << 30)) return fail(ADER_EUNSUPPORTED, "more than 2^30 cells on a level");
+  ader_amr a = new (std::nothrow) ader_amr_s();
+  if (!a) return fail(ADER_EINVAL, "out of host memory");
+  a->prob = *prob;
+  if (prob->dim == 2) a->prob.n[2] = 1;
+  a->cfg = *cfg;
+  a->d = prob->dim;
+  a->M = prob->M;
+  a->nv = nv;
+  a->r = cfg->r;
+  a->L = cfg->max_level;
+  a->impl = a->d == 2 ? ader::make_amr_impl_2d(a->M, prob->system, prob->precision)
+                      : ader::make_amr_impl_3d(a->M, prob->system, prob->precision);
+  ader::RefConstants ref;
+  ader::AmrTables tab;
+  if (!a->impl || !ader::build_ref_constants(a->M, &ref) ||
+      !ader::build_amr_tables(a->M, a->r, &tab)) {
+    delete a;
+    return fail(ADER_EUNSUPPORTED, "no AMR kernels or tables for this configuration");
+  }
+  ader::fill_dev_consts(ref, a->M, &a->dc);
+  std::memset(&a->ac, 0, sizeof(a->ac));
+  a->ac.r = a->r;
+  for (int i = 0; i < a->r; ++i)
+    for (int p = 0; p <= a->M; ++p) {
+      a->ac.sub_avg[i][p] = (double)tab.sub_avg[i][p];
+      a->ac.at_sub[i][p] = (double)tab.at_sub[i][p];
+      a->ac.at_face[i][0][p] = (double)tab.at_face[i][0][p];
+      a->ac.at_face[i][1][p] = (double)tab.at_face[i][1][p];
+      for (int b = 0; b <= a->M; ++b) a->ac.at_nodes[i][b][p] = (double)tab.at_nodes[i][b][p];
+    }
+  a->lv.resize(a->L + 1);
+  a->h_init.resize(a->L + 1);
+  a->h_flags.resize(a->L + 1);
+  for (int l = 0; l <= a->L; ++l) {
+    ader::AmrLevel& v = a->lv[l];
+    const int64_t f = ipow(a->r, l);
+    for (int k = 0; k < 3; ++k) v.n[k] = k < a->d ? (int)(a->prob.n[k] * f) : 1;
+    v.ncells = (int64_t)v.n[0] * v.n[1] * v.n[2];
+  }
+  *out = a;
+  return ADER_OK;
+}
+
+ader_status ader_amr_destroy(ader_amr a) {
+  if (!a) return ADER_OK;
+  if (a->stream) (void)hipStreamSynchronize(a->stream);
+  if (a->exec) (void)hipGraphExecDestroy(a->exec);
+  for (void* p : a->dev_allocs) (void)hipFree(p);
+  if (a->h_clock) (void)hipHostFree(a->h_clock);
+  if (a->stream) (void)hipStreamDestroy(a->stream);
+  delete a;
+  return ADER_OK;
+}
+
+ader_status ader_amr_level_cells(ader_amr a, int level, int n[3]) {
+  if (!a || !n || level < 0 || level > a->L) return fail(ADER_EINVAL, "bad level");
+  for (int k = 0; k < 3; ++k) n[k] = a->lv[level].n[k];
+  return ADER_OK;
+}
+
+ader_status ader_amr_set_level(ader_amr a, int level, const double* u) {
+  if (!a || !u || level < 0 || level > a->L) return fail(ADER_EINVAL, "bad level or pointer");
+  if (a->built) return fail(ADER_EINVAL, "the mesh is already built");
+  const int64_t N = a->lv[level].ncells;
+  a->h_init[level].assign(u, u + (size_t)a->nv * N);
+  return ADER_OK;
+}
+
+ader_status ader_amr_set_flags(ader_amr a, int level, const uint8_t* flags) {
+  if (!a || !flags || level < 0 || level >= a->L) return fail(ADER_EINVAL, "bad level or pointer");
+  if (a->built) return fail(ADER_EINVAL, "the mesh is already built");
+  const int64_t N = a->lv[level].ncells;
+  a->h_flags[level].assign(flags, flags + N);
+  for (auto& x : a->h_flags[level]) x = x ? 1 : 0;
+  return ADER_OK;
+}
+
+ader_status ader_amr_build(ader_amr a) {
+  if (!a) return fail(ADER_EINVAL, "null argument");
+  if (a->built) return fail(ADER_EINVAL, "the mesh is already built");
+  const int d = a->d, r = a->r, L = a->L, nv = a->nv;
+  const int* bc = a->prob.bc;
+  std::vector<Grid> g(L + 1);
+  for (int l = 0; l <= L; ++l) {
+    g[l].d = d;
+    for (int k = 0; k < 3; ++k) g[l].n[k] = a->lv[l].n[k];
+    if (a->h_init[l].size() != (size_t)nv * g[l].cells())
+      return fail(ADER_EINVAL, "initial averages missing for level " + std::to_string(l));
+  }
+  // 1. flags
+  std::vector<std::vector<uint8_t>> F(L);
+  for (int l = 0; l < L; ++l) {
+    if (!a->h_flags[l].empty()) {
+      F[l] = a->h_flags[l];
+    } else {
+      const double* Phi = a->h_init[l].data() + (size_t)a->cfg.indicator_var * g[l].cells();
+      std::vector<double> chi = lohner(g[l], Phi, bc, a->cfg.eps);
+      F[l].resize(chi.size());
+      for (size_t i = 0; i < chi.size(); ++i) F[l][i] = chi[i] > a->cfg.chi_ref ? 1 : 0;
+      for (int b = 0; b < a->cfg.buffer; ++b) F[l] = dilate(g[l], F[l], bc);
+    }
+  }
+  // 2. closure and nesting
+  for (int l = L - 1; l >= 1; --l) {
+    std::vector<uint8_t> m = mothers(g[l], g[l - 1], dilate(g[l], F[l], bc), r);
+    for (size_t i = 0; i < m.size(); ++i) F[l - 1][i] |= m[i];
+  }
+  for (int l = 1; l < L; ++l) {
+    std::vector<uint8_t> c = children(g[l - 1], g[l], F[l - 1], r);
+    for (size_t i = 0; i < c.size(); ++i) F[l][i] &= c[i];
+  }
+  // 3. status
+  a->h_status.assign(L + 1, {});
+  a->h_status[0].assign(g[0].cells(), ader::kActive);
+  if (L > 0)
+    for (int64_t i = 0; i < g[0].cells(); ++i)
+      if (F[0][i]) a->h_status[0][i] = ader::kVMother;
+  for (int l = 1; l <= L; ++l) {
+    std::vector<uint8_t> near = dilate(g[l - 1], F[l - 1], bc);
+    for (size_t i = 0; i < near.size(); ++i) near[i] = near[i] && !F[l - 1][i];
+    std::vector<uint8_t> vch = children(g[l - 1], g[l], near, r);
+    std::vector<uint8_t> kids = children(g[l - 1], g[l], F[l - 1], r);
+    std::vector<int8_t>& s = a->h_status[l];
+    s.assign(g[l].cells(), ader::kAbsent);
+    for (int64_t i = 0; i < g[l].cells(); ++i) {
+      if (vch[i]) s[i] = ader::kVChild;
+      if (kids[i]) s[i] = (l < L && F[l][i]) ? ader::kVMother : ader::kActive;
+    }
+  }
+  // 4. every active stencil lies in the mesh
+  const int M = a->M;
+  for (int l = 0; l <= L; ++l) {
+    const std::vector<int8_t>& s = a->h_status[l];
+    for (int64_t i = 0; i < g[l].cells(); ++i) {
+      if (s[i] != ader::kActive) continue;
+      int c[3];
+      g[l].coords(i, c);
+      const int spanz = d > 2 ? M : 0;
+      for (int oz = -spanz; oz <= spanz; ++oz)
+        for (int oy = -M; oy <= M; ++oy)
+          for (int ox = -M; ox <= M; ++ox) {
+            const int o[3] = {ox, oy, oz};
+            int cc[3] = {0, 0, 0};
+            for (int k = 0; k < d; ++k) cc[k] = map_bc(c[k] + o[k], g[l].n[k], bc[k]);
+            if (s[g[l].idx(cc)] == ader::kAbsent)
+              return fail(ADER_EINVAL, "an active cell's stencil leaves the mesh");
+          }
+    }
+  }
+  // 5. device data
+  hipError_t e = hipStreamCreateWithFlags(&a->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_status(e, "ader_amr_build");
+  const double dx0[3] = {(a->prob.hi[0] - a->prob.lo[0]) / a->prob.n[0],
+                         (a->prob.hi[1] - a->prob.lo[1]) / a->prob.n[1],
+                         d > 2 ? (a->prob.hi[2] - a->prob.lo[2]) / a->prob.n[2] : 1.0};
+  a->updates_per_step = 0;
+  for (int l = 0; l <= L; ++l) {
+    ader::AmrLevel& v = a->lv[l];
+    const int64_t N = v.ncells;
+    const std::vector<int8_t>& s = a->h_status[l];
+    std::vector<int32_t> act, vc, vm, pos(N, -1);
+    for (int64_t i = 0; i < N; ++i) {
+      if (s[i] == ader::kActive) {
+        pos[i] = (int32_t)act.size();
+        act.push_back((int32_t)i);
+      } else if (s[i] == ader::kVChild) {
+        vc.push_back((int32_t)i);
+      } else if (s[i] == ader::kVMother) {
+        vm.push_back((int32_t)i);
+      }
+    }
+    v.nact = (int64_t)act.size();
+    v.nvc = (int64_t)vc.size();
+    v.nvm = (int64_t)vm.size();
+    a->updates_per_step += (uint64_t)v.nact * (uint64_t)ipow(r, l);
+    std::vector<double> u0(a->h_init[l]);
+    for (int64_t i = 0; i < N; ++i)
+      if (s[i] == ader::kAbsent)
+        for (int q = 0; q < nv; ++q) u0[(size_t)q * N + i] = std::nan("");
+    ader_status st = ADER_OK;
+    if (!st) st = upload(a, &v.u, u0.data(), sizeof(double) * nv * N);
+    if (!st) st = upload(a, &v.st, s.data(), N);
+    if (!st) st = upload(a, &v.pos, pos.data(), sizeof(int32_t) * N);
+    if (!st) st = upload(a, &v.act, act.data(), sizeof(int32_t) * act.size());
+    if (!st) st = upload(a, &v.vc, vc.data(), sizeof(int32_t) * vc.size());
+    if (!st) st = upload(a, &v.vm, vm.data(), sizeof(int32_t) * vm.size());
+    if (!st && l > 0) st = upload(a, &v.mem, nullptr, sizeof(double) * d * 2 * nv * N);
+    const size_t na = (size_t)v.nact;
+    if (!st) st = upload(a, &v.wa, nullptr, sizeof(double) * a->impl->weno_scratch_per_cell() * na);
+    v.wb = v.wa ? v.wa + (size_t)nv * (M + 1) * ipow(2 * M + 1, d - 1) * na : nullptr;
+    if (!st) st = upload(a, &v.wh, nullptr, sizeof(double) * a->impl->wh_per_cell() * na);
+    if (!st)
+      st = upload(a, &v.qh, nullptr, a->impl->qh_elem_size() * nv * ipow(M + 1, d + 1) * na);
+    std::vector<char> zero(ader::kHeaderBytes, 0);
+    if (!st) st = upload(a, &v.hdr, zero.data(), ader::kHeaderBytes);
+    if (st) return st;
+    ader_problem pl = a->prob;
+    for (int k = 0; k < d; ++k) pl.n[k] = v.n[k];
+    ader::fill_mesh_params(pl, N, &v.mp);
+    for (int k = 0; k < d; ++k) v.dx[k] = v.mp.dx[k] = dx0[k] / (double)ipow(r, l);
+    v.mp.ld = N;
+    a->dtargs.nb[l] = v.nact == 0 ? 0
+                      : (int)std::min<int64_t>((v.nact + ader::kBlock - 1) / ader::kBlock,
+                                               ader::kDtMaxBlocks);
+  }
+  a->dtargs.nlev = L + 1;
+  a->dtargs.r = r;
+  a->dtargs.cfl = a->prob.cfl;
+  if (ader_status st = upload(a, &a->partial, nullptr,
+                              sizeof(double) * ader::kDtMaxBlocks * (L + 1)))
+    return st;
+  std::vector<char> clk(sizeof(ader::AmrClock), 0);
+  if (ader_status st = upload(a, &a->clock, clk.data(), clk.size())) return st;
+  e = hipHostMalloc(&a->h_clock, sizeof(ader::AmrClock), hipHostMallocDefault);
+  if (e != hipSuccess) return hip_status(e, "ader_amr_build");
+  std::memset(a->h_clock, 0, sizeof(ader::AmrClock));
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_status(e, "ader_amr_build");
+  a->built = true;
+  return ADER_OK;
+}
+
+ader_status ader_amr_step(ader_amr a, double t_end, void* stream) {
+  if (!a) return fail(ADER_EINVAL, "null argument");
+  if (!a->built) return fail(ADER_EINVAL, "build the mesh first");
+  if (!std::isfinite(t_end)) return fail(ADER_EINVAL, "t_end must be finite");
+  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : a->stream;
+  hipError_t e = hipSuccess;
+  if (t_end != a->t_end_set) {
+    // the end time lives in the device clock (the recorded step reads it)
+    e = hipStreamSynchronize(st);
+    if (e == hipSuccess)
+      e = hipMemcpy(&a->clock->t_end, &t_end, sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_status(e, "ader_amr_step");
+    a->t_end_set = t_end;
+  }
+  if (a->cfg.use_graph) {
+    if (!a->exec) {
+      hipGraph_t graph = nullptr;
+      e = hipStreamBeginCapture(a->stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return hip_status(e, "ader_amr_step (capture)");
+      ader_status rs = record_step(a, a->stream);
+      e = hipStreamEndCapture(a->stream, &graph);
+      if (rs) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rs;
+      }
+      if (e == hipSuccess) e = hipGraphInstantiate(&a->exec, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return hip_status(e, "ader_amr_step (graph)");
+    }
+    e = hipGraphLaunch(a->exec, st);
+    if (e != hipSuccess) return hip_status(e, "ader_amr_step (graph launch)");
+  } else {
+    if (ader_status rs = record_step(a, st)) return rs;
+  }
+  a->cell_updates += a->updates_per_step;
+  return ADER_OK;
+}
+
+ader_status ader_amr_clock(ader_amr a, double* t, int64_t* steps, double* dt0) {
+  if (!a || !a->built) return fail(ADER_EINVAL, "mesh not built");
+  hipError_t e = hipStreamSynchronize(a->stream);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess)
+    e = hipMemcpy(a->h_clock, a->clock, sizeof(ader::AmrClock), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_status(e, "ader_amr_clock");
+  if (t) *t = a->h_clock->t;
+  if (steps) *steps = (int64_t)a->h_clock->steps;
+  if (dt0) *dt0 = a->h_clock->dt[0];
+  return ADER_OK;
+}
+
+ader_status ader_amr_get_level(ader_amr a, int level, double* u, int8_t* status) {
+  if (!a || !a->built || level < 0 || level > a->L) return fail(ADER_EINVAL, "bad level");
+  hipError_t e = hipDeviceSynchronize();
+  const ader::AmrLevel& v = a->lv[level];
+  if (e == hipSuccess && u)
+    e = hipMemcpy(u, v.u, sizeof(double) * a->nv * v.ncells, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_status(e, "ader_amr_get_level");
+  if (status) std::memcpy(status, a->h_status[level].data(), v.ncells);
+  return ADER_OK;
+}
+
+ader_status ader_amr_counts(ader_amr a, int level, int64_t counts[3]) {
+  if (!a || !a->built || !counts || level < 0 || level > a->L)
+    return fail(ADER_EINVAL, "bad level");
+  counts[0] = a->lv[level].nact;
+  counts[1] = a->lv[level].nvc;
+  counts[2] = a->lv[level].nvm;
+  return ADER_OK;
+}
+
+ader_status ader_amr_stats(ader_amr a, uint32_t* flags, uint64_t* picard_iterations,
+                           uint64_t* cell_updates) {
+  if (!a || !a->built) return fail(ADER_EINVAL, "mesh not built");
+  hipError_t e = hipDeviceSynchronize();
+  uint32_t f = 0;
+  uint64_t it = 0;
+  for (int l = 0; l <= a->L && e == hipSuccess; ++l) {
+    ader::WsHeader h;
+    e = hipMemcpy(&h, a->lv[l].hdr, sizeof(h), hipMemcpyDeviceToHost);
+    f |= h.status;
+    for (int k = 0; k < ader::kCounterSlots; ++k) it += h.iters[k];
+  }
+  if (e != hipSuccess) return hip_status(e, "ader_amr_stats");
+  if (flags) *flags = f;
+  if (picard_iterations) *picard_iterations = it;
+  if (cell_updates) *cell_updates = a->cell_updates;
+  return ADER_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,412 @@
+// Kernels of cell-by-cell AMR with local time stepping (Section 3) on the
+// dense per-level representation (amr_plan.hpp): every level is an array over
+// its whole index space with a status per cell; the work runs over per-level
+// lists (active cells, virtual children, virtual mothers).
+//
+//   k_amr_cfl       block maxima of sum_k speed_k / dx_k over a level's
+//                   active cells (the CFL rule, reading R1, per level)
+//   k_amr_dt        level-0 step from all levels' maxima, level steps, clock
+//   k_amr_average   virtual mothers = mean of their r^d children (eq. average)
+//   k_amr_project   virtual children = sub-cell average of the mother's
+//                   space-time predictor at the substep's mother-local time
+//                   (Section 3.1.3)
+//   k_amr_weno_x    first WENO pass of the active cells, stencil indices from
+//                   the dense grid; later passes and the predictor are the
+//                   level-list kernels (level.hpp, predictor kernels)
+//   k_amr_update    finite-volume update of the active cells: same-level
+//                   faces as on a uniform mesh; a face to a virtual child
+//                   (coarser neighbour) takes the coarse predictor at this
+//                   face's Gauss points and this substep's time nodes and
+//                   stores the flux in the virtual child's memory; a face to
+//                   a virtual mother (finer neighbour) averages the memory of
+//                   this cell's virtual children on that face (eq. memory.sum)
+#pragma once
+
+#include "amr_plan.hpp"
+#include "level.hpp"
+
+namespace ader {
+
+template <int DIM>
+__device__ __forceinline__ void dense_coords(int64_t idx, const int (&n)[3], int (&c)[3]) {
+  c[0] = (int)(idx % n[0]);
+  c[1] = DIM > 1 ? (int)((idx / n[0]) % n[1]) : 0;
+  c[2] = DIM > 2 ? (int)(idx / ((int64_t)n[0] * n[1])) : 0;
+}
+
+template <int DIM>
+__device__ __forceinline__ int64_t dense_index(const int (&c)[3], const int (&n)[3]) {
+  return c[0] + (int64_t)n[0] * (c[1] + (int64_t)n[1] * (DIM > 2 ? c[2] : 0));
+}
+
+__device__ __forceinline__ double nan_max_d(double a, double b) {
+  return (b != b || b > a) ? b : a;  // a NaN wins, so it reaches dt
+}
+
+template <int DIM, int SYS>
+__global__ void __launch_bounds__(kBlock)
+k_amr_cfl(const double* __restrict__ u, const int32_t* __restrict__ act, int64_t nact,
+          MeshParams mp, double* __restrict__ partial) {
+  constexpr int NV = NVars<SYS, DIM>::v;
+  __shared__ double sw[kBlock / 64];
+  const double adv[3] = {mp.adv[0], mp.adv[1], mp.adv[2]};
+  double m = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nact;
+       i += (int64_t)gridDim.x * kBlock) {
+    const int64_t cell = act[i];
+    double q[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) q[v] = u[v * mp.ld + cell];
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      double f[NV], sp;
+      phys_flux_dir<SYS, DIM>(q, k, mp.gamma, mp.ch, adv, f, sp);
+      s += sp / mp.dx[k];
+    }
+    m = nan_max_d(m, s);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = nan_max_d(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = sw[0];
+#pragma unroll
+    for (int i = 1; i < kBlock / 64; ++i) b = nan_max_d(b, sw[i]);
+    partial[blockIdx.x] = b;
+  }
+}
+
+// one thread: the level-0 step of the AMR run and the level steps
+// (a template so that the header can be included by several units)
+template <int TAG>
+__global__ void k_amr_dt(const double* __restrict__ partial, AmrDtArgs a, AmrClock* clock,
+                         WsHeader* hdr) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double best = 1.0 / 0.0;
+  double rl = 1.0;  // r^l
+  for (int l = 0; l < a.nlev; ++l) {
+    if (a.nb[l] > 0) {
+      double m = 0.0;
+      for (int i = 0; i < a.nb[l]; ++i) m = nan_max_d(m, partial[l * kDtMaxBlocks + i]);
+      const double cand = rl * a.cfl / m;
+      best = (cand != cand || cand < best) ? cand : best;
+    }
+    rl *= a.r;
+  }
+  const double t = clock->t;
+  const double rest = clock->t_end - t;
+  double dt = rest < best ? rest : best;
+  if (!(dt > 0.0)) dt = dt != dt ? dt : 0.0;  // finished runs take empty steps
+  if (dt != dt) atomicOr(&hdr->status, kFlagNan);
+  clock->dt[0] = dt;
+  for (int l = 1; l < a.nlev; ++l) clock->dt[l] = clock->dt[l - 1] / a.r;
+  clock->t = t + dt;
+  clock->steps = clock->steps + 1;
+}
+
+template <int TAG>
+__global__ void k_fill(double* __restrict__ p, int64_t n, double value) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock)
+    p[i] = value;
+}
+
+template <int DIM, int NV>
+__global__ void __launch_bounds__(kBlock)
+k_amr_average(double* __restrict__ uc, int64_t ldc, const double* __restrict__ uf, int64_t ldf,
+              const int32_t* __restrict__ vm, int64_t nvm, int nc0, int nc1, int nc2, int nf0,
+              int nf1, int nf2, int r) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nvm) return;
+  const int nc[3] = {nc0, nc1, nc2}, nf[3] = {nf0, nf1, nf2};
+  const int64_t cell = vm[i];
+  int c[3];
+  dense_coords<DIM>(cell, nc, c);
+  const int nchild = DIM == 2 ? r * r : r * r * r;
+  double sum[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) sum[v] = 0.0;
+  for (int a = 0; a < nchild; ++a) {
+    int f[3] = {c[0] * r + a % r, DIM > 1 ? c[1] * r + (a / r) % r : 0,
+                DIM > 2 ? c[2] * r + a / (r * r) : 0};
+    const int64_t child = dense_index<DIM>(f, nf);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sum[v] += uf[v * ldf + child];
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) uc[v * ldc + cell] = sum[v] / nchild;
+}
+
+// Value of a coarse cell's predictor q (nodal, [v][s][pz][py][px]) at the
+// tensor point with per-axis basis weights wax[axis][p] and time weights wt[s].
+template <int DIM, int M, int NV, typename R>
+__device__ __forceinline__ void eval_predictor(const R* __restrict__ q, const double (&wt)[4],
+                                               const double (&wax)[3][4], double (&out)[NV]) {
+  constexpr int n = M + 1;
+  constexpr int NS = Pow<n, DIM>::v;
+  constexpr int NST = NS * n;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double acc = 0.0;
+#pragma unroll
+    for (int s = 0; s < n; ++s) {
+      double sp = 0.0;
+#pragma unroll
+      for (int a = 0; a < NS; ++a) {
+        const int px = a % n, py = (a / n) % n, pz = a / (n * n);
+        double w = wax[0][px] * wax[1][py];
+        if (DIM == 3) w *= wax[2][pz];
+        sp += w * (double)q[v * NST + a + NS * s];
+      }
+      acc += wt[s] * sp;
+    }
+    out[v] = acc;
+  }
+}
+
+template <int DIM, int M, int NV, typename R>
+__global__ void __launch_bounds__(kBlock)
+k_amr_project(double* __restrict__ u, int64_t ld, const int32_t* __restrict__ vc, int64_t nvc,
+              int n0, int n1, int n2, const int32_t* __restrict__ pos_c, int nc0, int nc1,
+              int nc2, const R* __restrict__ qh_c, AmrConsts ac, int sub, WsHeader* hdr) {
+  constexpr int n = M + 1;
+  constexpr int NST = Pow<n, DIM + 1>::v;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  unsigned int flags = 0;
+  if (i < nvc) {
+    const int nn[3] = {n0, n1, n2}, ncc[3] = {nc0, nc1, nc2};
+    const int64_t cell = vc[i];
+    int c[3], m[3], o[3];
+    dense_coords<DIM>(cell, nn, c);
+    for (int k = 0; k < 3; ++k) {
+      m[k] = c[k] / ac.r;
+      o[k] = c[k] % ac.r;
+    }
+    const int32_t mp = pos_c[dense_index<DIM>(m, ncc)];
+    if (mp < 0) {
+      flags |= kFlagBadIndex;  // a virtual child whose mother is not active
+    } else {
+      double wt[4], wax[3][4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        wt[p] = p < n ? ac.at_sub[sub][p] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) wax[k][p] = p < n ? ac.sub_avg[o[k]][p] : 0.0;
+      }
+      double val[NV];
+      eval_predictor<DIM, M, NV, R>(qh_c + (int64_t)mp * NV * NST, wt, wax, val);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) u[v * ld + cell] = val[v];
+    }
+  }
+  block_report(0u, flags, hdr);
+}
+
+// First WENO pass (along x) of the active cells; the (2M+1)^d stencil is
+// addressed on the dense grid with the boundary maps.  Output layout as
+// k_level_weno_pass<K = 0>.
+template <int DIM, int M, int NV>
+__global__ void __launch_bounds__(kBlock)
+k_amr_weno_x(const double* __restrict__ u, int64_t ld, const int32_t* __restrict__ act,
+             int64_t nact, MeshParams mp, double* __restrict__ dst, DevConsts c) {
+  constexpr int n = M + 1;
+  constexpr int S = 2 * M + 1;
+  constexpr int LINES = Pow<S, DIM - 1>::v;
+  constexpr int OUT = n * LINES;
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= nact * NV * LINES) return;
+  const int line = (int)(t % LINES);
+  const int64_t pv = t / LINES;
+  const int v = (int)(pv % NV);
+  const int64_t p = pv / NV;
+  int cc[3];
+  dense_coords<DIM>(act[p], mp.n, cc);
+  const int oy = line % S, oz = line / S;
+  const int gy = DIM > 1 ? bc_map(cc[1] + oy - M, mp.n[1], mp.bc[1]) : 0;
+  const int gz = DIM > 2 ? bc_map(cc[2] + oz - M, mp.n[2], mp.bc[2]) : 0;
+  const int64_t row = (int64_t)mp.n[0] * (gy + (int64_t)mp.n[1] * gz);
+  double vals[S];
+#pragma unroll
+  for (int o = 0; o < S; ++o)
+    vals[o] = u[(int64_t)v * ld + row + bc_map(cc[0] + o - M, mp.n[0], mp.bc[0])];
+  double w[n];
+  weno_line<M>(vals, c, w);
+  double* dp = dst + pv * OUT;
+#pragma unroll
+  for (int q = 0; q < n; ++q) dp[q + n * line] = w[q];
+}
+
+struct AmrUpdArgs {
+  double* u;
+  const int8_t* st;
+  const int32_t* pos;
+  const int32_t* act;
+  int64_t nact;
+  const void* qh;
+  const int32_t* pos_c;  // coarser level (null on level 0)
+  const void* qh_c;
+  int nc[3];
+  double* mem;            // this level's memory [DIM][2][NV][ncells] (null on level 0)
+  const double* mem_f;    // finer level's memory (null on the finest level)
+  int nf[3];
+  int64_t ldf;
+  const double* dt;
+  int sub;
+  int r;
+};
+
+template <int DIM, int M, int SYS, typename R>
+__global__ void __launch_bounds__(kBlock)
+k_amr_update(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, WsHeader* hdr) {
+  constexpr int n = M + 1;
+  constexpr int NV = NVars<SYS, DIM>::v;
+  constexpr int NST = Pow<n, DIM + 1>::v;
+  constexpr int NT = Pow<n, DIM - 1>::v;  // transverse nodes of a face
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  unsigned int flags = 0;
+  if (i < a.nact) {
+    const int64_t ld = mp.ld;
+    const int64_t cell = a.act[i];
+    int cc[3];
+    dense_coords<DIM>(cell, mp.n, cc);
+    const R* qme = static_cast<const R*>(a.qh) + i * NV * NST;
+    const double dt = *a.dt;
+    double q[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) q[v] = a.u[v * ld + cell];
+    for (int k = 0; k < DIM; ++k) {
+      double F[2][NV];
+      for (int side = 0; side < 2; ++side) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) F[side][v] = 0.0;
+        const int raw = cc[k] + (side ? 1 : -1);
+        const bool outside = raw < 0 || raw >= mp.n[k];
+        int nbc[3] = {cc[0], cc[1], cc[2]};
+        nbc[k] = bc_map(raw, mp.n[k], mp.bc[k]);
+        const int64_t nb = dense_index<DIM>(nbc, mp.n);
+        int type;  // 0 same level, 1 outflow, 2 coarser (virtual child), 3 finer (virtual mother)
+        const R* qnb = nullptr;
+        int off[3] = {0, 0, 0};
+        if (outside && mp.bc[k] != 0) {
+          type = 1;
+        } else {
+          const int8_t s = a.st[nb];
+          if (s == kActive) {
+            type = 0;
+            const int32_t pn = a.pos[nb];
+            if (pn < 0) {
+              flags |= kFlagBadIndex;
+              continue;
+            }
+            qnb = static_cast<const R*>(a.qh) + (int64_t)pn * NV * NST;
+          } else if (s == kVChild && a.pos_c) {
+            type = 2;
+            int m[3];
+            for (int ax = 0; ax < 3; ++ax) {
+              m[ax] = nbc[ax] / a.r;
+              off[ax] = nbc[ax] % a.r;
+            }
+            const int32_t pm = a.pos_c[dense_index<DIM>(m, a.nc)];
+            if (pm < 0) {
+              flags |= kFlagBadIndex;
+              continue;
+            }
+            qnb = static_cast<const R*>(a.qh_c) + (int64_t)pm * NV * NST;
+          } else if (s == kVMother && a.mem_f) {
+            type = 3;
+          } else {
+            flags |= kFlagBadIndex;  // an active cell next to a cell outside the mesh
+            continue;
+          }
+        }
+        if (type == 3) {
+          // sum of the memory of this cell's virtual children on this face
+          const int nsub = DIM == 2 ? a.r : a.r * a.r;
+          for (int j = 0; j < nsub; ++j) {
+            int ch[3];
+            int t = 0;
+            for (int ax = 0; ax < DIM; ++ax) {
+              if (ax == k) {
+                ch[ax] = cc[ax] * a.r + (side ? a.r - 1 : 0);
+              } else {
+                const int aj = DIM == 2 ? j : (t == 0 ? j / a.r : j % a.r);
+                ch[ax] = cc[ax] * a.r + aj;
+                ++t;
+              }
+            }
+            if (DIM == 2) ch[2] = 0;
+            const int64_t chd = dense_index<DIM>(ch, a.nf);
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+              F[side][v] += a.mem_f[((int64_t)(k * 2 + side) * NV + v) * a.ldf + chd];
+          }
+          const double inv = 1.0 / (DIM == 2 ? (double)(a.r * a.r) : (double)(a.r * a.r * a.r));
+#pragma unroll
+          for (int v = 0; v < NV; ++v) F[side][v] *= inv;
+        } else {
+          for (int s = 0; s < n; ++s) {
+            for (int tb = 0; tb < NT; ++tb) {
+              double qm[NV], qp[NV];
+              cell_trace<DIM, M, NV, R>(qme, k, side, tb, s, c, qm);
+              if (type == 0) {
+                cell_trace<DIM, M, NV, R>(qnb, k, 1 - side, tb, s, c, qp);
+              } else if (type == 1) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) qp[v] = qm[v];
+              } else {
+                // coarse predictor at this face point and time node
+                const int tt[2] = {tb % n, tb / n};
+                double wt[4], wax[3][4];
+                int ti = 0;
+#pragma unroll
+                for (int p = 0; p < 4; ++p) wt[p] = p < n ? ac.at_nodes[a.sub][s][p] : 0.0;
+                for (int ax = 0; ax < 3; ++ax) {
+                  for (int p = 0; p < 4; ++p) {
+                    double w = 0.0;
+                    if (p < n && ax < DIM) {
+                      w = ax == k ? ac.at_face[off[ax]][1 - side][p]
+                                  : ac.at_nodes[off[ax]][tt[ti]][p];
+                    }
+                    wax[ax][p] = w;
+                  }
+                  if (ax < DIM && ax != k) ++ti;
+                }
+                eval_predictor<DIM, M, NV, R>(qnb, wt, wax, qp);
+              }
+              double Fpt[NV];
+              if (side)
+                numerical_flux<SYS, DIM>(qm, qp, k, mp, c, Fpt);
+              else
+                numerical_flux<SYS, DIM>(qp, qm, k, mp, c, Fpt);
+              double wtp = c.w[s];
+              {
+                const int tt[2] = {tb % n, tb / n};
+                for (int dd = 0; dd < DIM - 1; ++dd) wtp *= c.w[tt[dd]];
+              }
+#pragma unroll
+              for (int v = 0; v < NV; ++v) F[side][v] += wtp * Fpt[v];
+            }
+          }
+          if (type == 2) {  // the face flux also goes to the coarse cell's memory
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+              a.mem[((int64_t)(k * 2 + (1 - side)) * NV + v) * ld + nb] += F[side][v];
+          }
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) q[v] -= (dt / mp.dx[k]) * (F[1][v] - F[0][v]);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      a.u[v * ld + cell] = q[v];
+      if (q[v] != q[v]) flags |= kFlagNan;
+    }
+    if (!state_physical<SYS, DIM>(q, mp.gamma)) flags |= kFlagNonPhysical;
+  }
+  block_report(0u, flags, hdr);
+}
+
+}  // namespace ader

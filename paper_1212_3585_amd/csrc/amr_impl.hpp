@@ -1,0 +1,130 @@
+// Launchers of the AMR kernels for one (dimension, degree, system, predictor
+// precision).
+#pragma once
+
+#include <type_traits>
+
+#include "amr.hpp"
+#include "predict_mfma.hpp"
+
+namespace ader {
+
+inline unsigned amr_blocks(int64_t work) {
+  int64_t b = (work + kBlock - 1) / kBlock;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+template <int DIM, int M, int SYS, typename R>
+class AmrImpl final : public AmrImplBase {
+  static constexpr int n = M + 1;
+  static constexpr int S = 2 * M + 1;
+  static constexpr int NV = NVars<SYS, DIM>::v;
+
+ public:
+  size_t qh_elem_size() const override { return sizeof(R); }
+  size_t weno_scratch_per_cell() const override {
+    return (size_t)NV * (n * Pow<S, DIM - 1>::v + (DIM == 3 ? n * n * S : 0));
+  }
+  size_t wh_per_cell() const override { return (size_t)NV * Pow<n, DIM>::v; }
+
+  hipError_t cfl(const AmrLevel& lv, double* partial, int nb, hipStream_t st) const override {
+    if (lv.nact == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_amr_cfl<DIM, SYS>), dim3(nb), dim3(kBlock), 0, st, lv.u, lv.act,
+                       lv.nact, lv.mp, partial);
+    return hipGetLastError();
+  }
+
+  hipError_t average(const AmrLevel& c, const AmrLevel& f, int r, hipStream_t st) const override {
+    if (c.nvm == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_amr_average<DIM, NV>), dim3(amr_blocks(c.nvm)), dim3(kBlock), 0, st,
+                       c.u, c.ncells, f.u, f.ncells, c.vm, c.nvm, c.n[0], c.n[1], c.n[2],
+                       f.n[0], f.n[1], f.n[2], r);
+    return hipGetLastError();
+  }
+
+  hipError_t project(const AmrLevel& lv, const AmrLevel& c, const AmrConsts& ac, int sub,
+                     hipStream_t st) const override {
+    if (lv.nvc == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_amr_project<DIM, M, NV, R>), dim3(amr_blocks(lv.nvc)), dim3(kBlock), 0,
+                       st, lv.u, lv.ncells, lv.vc, lv.nvc, lv.n[0], lv.n[1], lv.n[2], c.pos,
+                       c.n[0], c.n[1], c.n[2], static_cast<const R*>(c.qh), ac, sub, lv.hdr);
+    return hipGetLastError();
+  }
+
+  hipError_t predict(const AmrLevel& lv, const double* dt, const DevConsts& c,
+                     hipStream_t st) const override {
+    const int64_t np = lv.nact;
+    if (np == 0) return hipSuccess;
+    unsigned int* flags = &lv.hdr->status;
+    double* pass0 = lv.wa;
+    double* pass1 = DIM == 2 ? lv.wh : lv.wb;
+    hipLaunchKernelGGL((k_amr_weno_x<DIM, M, NV>), dim3(amr_blocks(np * NV * Pow<S, DIM - 1>::v)),
+                       dim3(kBlock), 0, st, lv.u, lv.ncells, lv.act, np, lv.mp, pass0, c);
+    hipLaunchKernelGGL((k_level_weno_pass<DIM, M, NV, 1>),
+                       dim3(amr_blocks(np * NV * n * Pow<S, DIM - 2>::v)), dim3(kBlock), 0, st,
+                       (const double*)nullptr, (int64_t)0, (const int32_t*)nullptr,
+                       (const double*)pass0, pass1, np, c, flags);
+    if constexpr (DIM == 3) {
+      hipLaunchKernelGGL((k_level_weno_pass<DIM, M, NV, 2>), dim3(amr_blocks(np * NV * n * n)),
+                         dim3(kBlock), 0, st, (const double*)nullptr, (int64_t)0,
+                         (const int32_t*)nullptr, (const double*)lv.wb, lv.wh, np, c, flags);
+    }
+    R* qh = static_cast<R*>(lv.qh);
+    if constexpr (DIM == 2 && std::is_same<R, double>::value) {
+      hipLaunchKernelGGL((k_predict_mfma2d<M, SYS, R>),
+                         dim3((unsigned)((np + 4 * (kBlock / 64) - 1) / (4 * (kBlock / 64)))),
+                         dim3(kBlock), 0, st, (const double*)lv.wh, qh, np, dt, lv.mp, c, lv.hdr);
+    } else {
+      constexpr int NS = Pow<n, DIM>::v;
+      hipLaunchKernelGGL((k_predict<DIM, M, SYS, R, R>),
+                         dim3((unsigned)((np + kBlock / NS - 1) / (kBlock / NS))), dim3(kBlock),
+                         0, st, (const double*)lv.wh, qh, np, dt, lv.mp, c, lv.hdr);
+    }
+    return hipGetLastError();
+  }
+
+  hipError_t update(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
+                    const double* dt, int sub, const DevConsts& c, const AmrConsts& ac,
+                    hipStream_t st) const override {
+    if (lv.nact == 0) return hipSuccess;
+    AmrUpdArgs a{};
+    a.u = lv.u;
+    a.st = lv.st;
+    a.pos = lv.pos;
+    a.act = lv.act;
+    a.nact = lv.nact;
+    a.qh = lv.qh;
+    if (coarse) {
+      a.pos_c = coarse->pos;
+      a.qh_c = coarse->qh;
+      for (int k = 0; k < 3; ++k) a.nc[k] = coarse->n[k];
+      a.mem = lv.mem;
+    }
+    if (fine) {
+      a.mem_f = fine->mem;
+      for (int k = 0; k < 3; ++k) a.nf[k] = fine->n[k];
+      a.ldf = fine->ncells;
+    }
+    a.dt = dt;
+    a.sub = sub;
+    a.r = ac.r;
+    hipLaunchKernelGGL((k_amr_update<DIM, M, SYS, R>), dim3(amr_blocks(lv.nact)), dim3(kBlock),
+                       0, st, a, lv.mp, c, ac, lv.hdr);
+    return hipGetLastError();
+  }
+};
+
+template <int DIM, int M>
+const AmrImplBase* pick_amr(int sys, int prec) {
+  static const AmrImpl<DIM, M, 0, double> a;
+  static const AmrImpl<DIM, M, 0, float> b;
+  static const AmrImpl<DIM, M, 1, double> c;
+  static const AmrImpl<DIM, M, 1, float> d;
+  static const AmrImpl<DIM, M, 2, double> e;
+  static const AmrImpl<DIM, M, 2, float> f;
+  if (sys == 0) return prec == 0 ? (const AmrImplBase*)&a : (const AmrImplBase*)&b;
+  if (sys == 1) return prec == 0 ? (const AmrImplBase*)&c : (const AmrImplBase*)&d;
+  return prec == 0 ? (const AmrImplBase*)&e : (const AmrImplBase*)&f;
+}
+
+}  // namespace ader

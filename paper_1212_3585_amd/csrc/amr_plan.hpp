@@ -1,0 +1,100 @@
+// Device-side data of an AMR mesh (Section 3) shared by the driver
+// (amr.cpp) and the templated launchers (amr_impl.hpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace ader {
+
+constexpr int kAmrMaxR = 4;       // refinement factors 2..4
+constexpr int kAmrMaxLevels = 6;  // levels 0..5
+constexpr int8_t kAbsent = -2, kVMother = -1, kActive = 0, kVChild = 1;
+
+// Basis tables of the AMR operators (fp64 copies of AmrTables).
+struct AmrConsts {
+  int r;
+  double sub_avg[kAmrMaxR][4];      // [a][p]
+  double at_sub[kAmrMaxR][4];       // [substep][p]
+  double at_face[kAmrMaxR][2][4];   // [a][side][p]
+  double at_nodes[kAmrMaxR][4][4];  // [a][node][p]
+};
+
+// Device clock of an AMR run: time, end time and the level steps of the
+// current level-0 step (dt[l] = dt[l-1] / r).
+struct AmrClock {
+  double t;
+  double t_end;
+  double dt[kAmrMaxLevels];
+  unsigned long long steps;
+};
+
+// One level of the dense per-level representation.
+struct AmrLevel {
+  int n[3] = {1, 1, 1};  // cells per axis of the level's index space
+  int64_t ncells = 0;    // n[0] n[1] n[2] (= ld of u)
+  double dx[3] = {1, 1, 1};
+  double* u = nullptr;        // [nv][ncells] cell averages
+  int8_t* st = nullptr;       // [ncells] status
+  int32_t* pos = nullptr;     // [ncells] position in the active list, -1 otherwise
+  int32_t* act = nullptr;     // active cells (dense indices, ascending)
+  int64_t nact = 0;
+  int32_t* vc = nullptr;      // virtual children
+  int64_t nvc = 0;
+  int32_t* vm = nullptr;      // virtual mothers
+  int64_t nvm = 0;
+  double* mem = nullptr;      // [dim][2][nv][ncells] fine-coarse flux memory (level >= 1)
+  double* wa = nullptr;       // WENO pass buffers of the active cells
+  double* wb = nullptr;
+  double* wh = nullptr;       // reconstruction w_h of the active cells
+  void* qh = nullptr;         // predictor of the active cells (predictor precision)
+  WsHeader* hdr = nullptr;    // status bits and Picard counters of the level
+  MeshParams mp{};            // the level's mesh (n, dx, ld = ncells)
+};
+
+class AmrImplBase {
+ public:
+  virtual ~AmrImplBase() = default;
+  virtual size_t qh_elem_size() const = 0;
+  // WENO scratch doubles per active cell (two pass buffers) and w_h doubles
+  virtual size_t weno_scratch_per_cell() const = 0;
+  virtual size_t wh_per_cell() const = 0;
+  // block maxima of sum_k speed_k / dx_k over the active cells -> partial[0..nb)
+  virtual hipError_t cfl(const AmrLevel& lv, double* partial, int nb, hipStream_t st) const = 0;
+  // virtual mothers of 'coarse' from their children on 'fine'
+  virtual hipError_t average(const AmrLevel& coarse, const AmrLevel& fine, int r,
+                             hipStream_t st) const = 0;
+  // virtual children of 'lv' from the predictor of 'coarse' at substep 'sub'
+  virtual hipError_t project(const AmrLevel& lv, const AmrLevel& coarse, const AmrConsts& ac,
+                             int sub, hipStream_t st) const = 0;
+  // reconstruction + predictor of the active cells of 'lv' with step *dt
+  virtual hipError_t predict(const AmrLevel& lv, const double* dt, const DevConsts& c,
+                             hipStream_t st) const = 0;
+  // finite-volume update of the active cells of 'lv' (substep 'sub' of the
+  // coarser level's step); coarse / fine may be null at the ends
+  virtual hipError_t update(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
+                            const double* dt, int sub, const DevConsts& c, const AmrConsts& ac,
+                            hipStream_t st) const = 0;
+};
+
+const AmrImplBase* make_amr_impl_2d(int M, int system, int precision);
+const AmrImplBase* make_amr_impl_3d(int M, int system, int precision);
+
+// CFL step of the AMR run (one block): dt0 = min over levels with active
+// cells of r^l cfl / max_l, clipped to t_end - t; dt[l] = dt[l-1] / r;
+// t += dt0.  partial holds kDtMaxBlocks maxima per level, nb[l] of them used.
+struct AmrDtArgs {
+  int nlev;
+  int r;
+  double cfl;
+  int nb[kAmrMaxLevels];
+};
+hipError_t launch_amr_dt(const double* partial, AmrDtArgs a, AmrClock* clock, WsHeader* hdr,
+                         hipStream_t st);
+hipError_t launch_fill(double* p, int64_t n, double value, hipStream_t st);
+
+}  // namespace ader

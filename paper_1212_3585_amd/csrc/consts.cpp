@@ -108,7 +108,47 @@ bool invert(int n, const long double (*a)[kMaxN], long double (*inv)[kMaxN]) {
   return true;
 }
 
+// Lagrange basis psi_l(xi) = prod_{k != l} (xi - x_k) / (x_l - x_k)
+void lagrange(int n, const long double* nodes, Poly* psi) {
+  for (int l = 0; l < n; ++l) {
+    Poly p;
+    p.c[0] = 1;
+    for (int k = 0; k < n; ++k) {
+      if (k == l) continue;
+      Poly f;  // (t - t_k) / (x_l - x_k) with t_k = x_k - 1/2
+      long double den = nodes[l] - nodes[k];
+      f.c[0] = -(nodes[k] - 0.5L) / den;
+      f.c[1] = 1.0L / den;
+      p = mul(p, f);
+    }
+    psi[l] = p;
+  }
+}
+
 }  // namespace
+
+bool build_amr_tables(int M, int r, AmrTables* out) {
+  if (M < 0 || M + 1 > kMaxN || r < 2 || r > kMaxR) return false;
+  AmrTables& t = *out;
+  t = AmrTables();
+  t.M = M;
+  t.r = r;
+  const int n = M + 1;
+  long double x[kMaxN], w[kMaxN];
+  gauss_legendre(n, x, w);
+  if (n == 1) x[0] = 0.5L;
+  Poly psi[kMaxN];
+  lagrange(n, x, psi);
+  for (int a = 0; a < r; ++a)
+    for (int p = 0; p < n; ++p) {
+      t.sub_avg[a][p] = r * integral(psi[p], (long double)a / r, (long double)(a + 1) / r);
+      t.at_sub[a][p] = eval(psi[p], (long double)a / r);
+      for (int side = 0; side < 2; ++side)
+        t.at_face[a][side][p] = eval(psi[p], (long double)(a + side) / r);
+      for (int b = 0; b < n; ++b) t.at_nodes[a][b][p] = eval(psi[p], (a + x[b]) / r);
+    }
+  return true;
+}
 
 bool build_ref_constants(int M, RefConstants* out) {
   if (M < 0 || M + 1 > kMaxN) return false;
@@ -124,21 +164,8 @@ bool build_ref_constants(int M, RefConstants* out) {
     c.weights[0] = 1.0L;
   }
 
-  // Lagrange basis psi_l(xi) = prod_{k != l} (xi - x_k) / (x_l - x_k)
   Poly psi[kMaxN];
-  for (int l = 0; l < n; ++l) {
-    Poly p;
-    p.c[0] = 1;
-    for (int k = 0; k < n; ++k) {
-      if (k == l) continue;
-      Poly f;  // (t - t_k) / (x_l - x_k) with t_k = x_k - 1/2
-      long double den = c.nodes[l] - c.nodes[k];
-      f.c[0] = -(c.nodes[k] - 0.5L) / den;
-      f.c[1] = 1.0L / den;
-      p = mul(p, f);
-    }
-    psi[l] = p;
-  }
+  lagrange(n, c.nodes, psi);
   Poly dpsi[kMaxN];
   for (int l = 0; l < n; ++l) dpsi[l] = deriv(psi[l]);
 

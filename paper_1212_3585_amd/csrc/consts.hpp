@@ -40,6 +40,22 @@ struct RefConstants {
 // Fills 'out' for degree M (0..3). Returns false if a matrix is singular.
 bool build_ref_constants(int M, RefConstants* out);
 
+// Basis tables of the AMR operators for refinement factor r (2..kMaxR),
+// psi_p the nodal basis of degree M on [0, 1], x_b its Gauss-Legendre nodes:
+//   sub_avg[a][p]     = r * int_{a/r}^{(a+1)/r} psi_p   (projection, Sec. 3.1.3)
+//   at_sub[j][p]      = psi_p(j / r)                      (mother-local time of substep j)
+//   at_face[a][s][p]  = psi_p((a + s) / r)                (child face s = 0 / 1)
+//   at_nodes[a][b][p] = psi_p((a + x_b) / r)              (child nodes, substep nodes)
+constexpr int kMaxR = 4;
+struct AmrTables {
+  int M = 0, r = 2;
+  long double sub_avg[kMaxR][kMaxN];
+  long double at_sub[kMaxR][kMaxN];
+  long double at_face[kMaxR][2][kMaxN];
+  long double at_nodes[kMaxR][kMaxN][kMaxN];
+};
+bool build_amr_tables(int M, int r, AmrTables* out);
+
 // WENO constants stated after eq. sigmas.
 constexpr double kLambdaCentral = 1.0e5;
 constexpr double kLambdaOneSided = 1.0;

@@ -1,0 +1,159 @@
+"""AMR with local time stepping (ader_amr_*) against the oracle's AMR
+(oracle/amr.py): the same mesh from the same initial data (bit-exact status
+arrays), level averages of the active cells within 1e-11 pooled relative L1
+after level-0 steps, conservation, graph replay equal to direct launches,
+and the fp32-predictor form's stated error."""
+import numpy as np
+import pytest
+
+from oracle import Euler, Problem as OProblem
+from oracle.amr import Hierarchy, amr_step
+from paper_1212_3585_amd import workloads as wl
+
+from gpu_helpers import rel_l1, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _coarsen(U, r):
+    nv, *n = U.shape
+    sh = [nv]
+    for k in n:
+        sh += [k // r, r]
+    return U.reshape(sh).mean(axis=tuple(range(2, 2 + 2 * len(n), 2)))
+
+
+def _levels_from_fine(Uf, r, L):
+    Us = [Uf]
+    for _ in range(L):
+        Us.insert(0, _coarsen(Us[0], r))
+    return Us
+
+
+def _make(ader, dim, M, n0, r, L, Us, bc="periodic", flags=None, lo=0.0, hi=1.0,
+          precision=0, use_graph=True, indicator_var=0, chi_ref=0.2, cfl=0.9):
+    tol = 1e-14 if precision == 0 else 1e-6
+    bcs = [bc] * dim
+    op = OProblem(dim, M, Euler(dim), (n0,) * dim, (lo,) * dim, (hi,) * dim, bcs, cfl=cfl)
+    gp = ader.Problem(dim=dim, M=M, n=(n0,) * dim + (1,) * (3 - dim), lo=(lo,) * 3,
+                      hi=(hi,) * 3, bc=tuple(ader.BC_PERIODIC if bc == "periodic"
+                                             else ader.BC_TRANSMISSIVE for _ in range(3)),
+                      precision=precision, picard_tol=tol, cfl=cfl)
+    H = Hierarchy(op, r, L, Us, flags=flags, indicator_var=indicator_var, chi_ref=chi_ref)
+    A = ader.Amr(gp, r=r, max_level=L, indicator_var=indicator_var, chi_ref=chi_ref,
+                 use_graph=use_graph)
+    for l in range(L + 1):
+        A.set_level(l, Us[l])
+    if flags is not None:
+        for l in range(L):
+            A.set_flags(l, flags[l])
+    A.build()
+    return H, A
+
+
+def _compare(H, A, tol=1e-11):
+    num = den = 0.0
+    for l in range(H.L + 1):
+        U, st = A.level(l)
+        assert np.array_equal(st, H.status[l])
+        act = st == 0
+        num += np.abs(U[:, act] - H.U[l][:, act]).sum()
+        den += np.abs(H.U[l][:, act]).sum()
+    err = num / den
+    assert err <= tol, err
+    return err
+
+
+def _patch_flags(n0, r):
+    F0 = np.zeros((n0, n0), bool)
+    F0[2:4, 2:4] = True
+    F1 = np.zeros((n0 * r, n0 * r), bool)
+    F1[7:9, 7:9] = True
+    return [F0, F1]
+
+
+def test_amr_patches_two_levels_parity(ader):
+    say("AMR 2D 6^2 r=3 L=2 M=2, refined patches: 2 level-0 steps vs oracle")
+    n0, r = 6, 3
+    Us = _levels_from_fine(wl.perturbed_smooth_euler((n0 * 9, n0 * 9), 5), r, 2)
+    H, A = _make(ader, 2, 2, n0, r, 2, Us, flags=_patch_flags(n0, r))
+    for c_gpu, c_or in zip([A.counts(l) for l in range(3)], H.counts()):
+        assert c_gpu == c_or
+    for _ in range(2):
+        amr_step(H, 0.0, 1.0)
+        A.step(1.0)
+    t, steps, _ = A.clock()
+    assert steps == 2
+    _compare(H, A)
+    assert A.stats()["flags"] == 0
+
+
+def test_amr_indicator_mesh_explosion(ader):
+    say("AMR explosion 16^2 r=3 L=2 M=2 transmissive CFL 0.5, indicator on E: 2 steps")
+    n0, r = 16, 3
+    Us = [wl.explosion_2d(n0 * r ** l, seed=2) for l in range(3)]
+    H, A = _make(ader, 2, 2, n0, r, 2, Us, bc="transmissive", lo=-1.0, hi=1.0,
+                 indicator_var=3, cfl=0.5)
+    assert H.counts()[2]["active"] > 0 and H.counts()[0]["active"] > 0
+    for _ in range(2):
+        amr_step(H, 0.0, 1.0)
+        A.step(1.0)
+    _compare(H, A)
+
+
+@pytest.mark.parametrize("M", [1, 3])
+def test_amr_degrees(ader, M):
+    say(f"AMR 2D 6^2 r=3 L=1 M={M}: 2 level-0 steps vs oracle")
+    n0, r = 6, 3
+    Us = _levels_from_fine(wl.perturbed_smooth_euler((n0 * r, n0 * r), 7 + M), r, 1)
+    F0 = np.zeros((n0, n0), bool)
+    F0[1:3, 2:5] = True
+    H, A = _make(ader, 2, M, n0, r, 1, Us, flags=[F0])
+    for _ in range(2):
+        amr_step(H, 0.0, 1.0)
+        A.step(1.0)
+    _compare(H, A)
+
+
+def test_amr_3d_parity(ader):
+    say("AMR 3D 4^3 r=2 L=1 M=2: 1 level-0 step vs oracle")
+    n0, r = 4, 2
+    Us = _levels_from_fine(wl.perturbed_smooth_euler((n0 * r,) * 3, 8), r, 1)
+    F0 = np.zeros((n0,) * 3, bool)
+    F0[1, 1, 1] = True
+    H, A = _make(ader, 3, 2, n0, r, 1, Us, flags=[F0])
+    amr_step(H, 0.0, 1.0)
+    A.step(1.0)
+    _compare(H, A)
+
+
+def test_amr_conservation_and_graph(ader):
+    say("AMR conservation over 3 steps; graph replay equals direct launches")
+    n0, r = 6, 3
+    Us = _levels_from_fine(wl.perturbed_smooth_euler((n0 * 9, n0 * 9), 11), r, 2)
+    res = []
+    for use_graph in (True, False):
+        H, A = _make(ader, 2, 2, n0, r, 2, Us, flags=_patch_flags(n0, r), use_graph=use_graph)
+        tot0 = H.total()
+        for _ in range(3):
+            A.step(1.0)
+        lv = [A.level(l) for l in range(3)]
+        tot = 0.0
+        for l, (U, st) in enumerate(lv):
+            tot = tot + np.prod(H.dx(l)) * U[:, st == 0].sum(axis=1)
+        assert np.all(np.abs(tot - tot0) <= 1e-12 * np.abs(tot0).max())
+        res.append(lv)
+    for (Ua, _), (Ub, _) in zip(*res):
+        assert np.array_equal(np.nan_to_num(Ua, nan=7.0), np.nan_to_num(Ub, nan=7.0))
+
+
+def test_amr_mixed_precision_error(ader):
+    say("AMR fp32 predictor, 2 levels: error vs the fp64 oracle")
+    n0, r = 6, 3
+    Us = _levels_from_fine(wl.perturbed_smooth_euler((n0 * 9, n0 * 9), 12), r, 2)
+    H, A = _make(ader, 2, 2, n0, r, 2, Us, flags=_patch_flags(n0, r), precision=1)
+    for _ in range(2):
+        amr_step(H, 0.0, 1.0)
+        A.step(1.0)
+    err = _compare(H, A, tol=1e-5)
+    print(f"fp32-predictor AMR relative L1 vs fp64 oracle: {err:.3e}")
