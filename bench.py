@@ -187,6 +187,62 @@ def serve(ader, reqs, arrivals, hbm_bytes):
             "peak_bytes": st["peak_bytes_in_use"], "rounds": st["rounds"]}
 
 
+def amr_leg(ader, label, dim, n0, r, L, M, ic, precision, steps, cfl=0.5):
+    """One AMR configuration: mesh built by the Loehner indicator on the
+    energy (the density noise does not enter it), one-layer flag buffer,
+    local time stepping, one recorded graph per level-0 step.  Rate =
+    active-cell substeps per second over 'steps' level-0 steps."""
+    tol = 1e-14 if precision == ader.PREC_FP64 else 1e-6
+    prob = ader.Problem(dim=dim, M=M, n=(n0,) * dim + (1,) * (3 - dim), lo=(-1.0,) * 3,
+                        hi=(1.0,) * 3, bc=(ader.BC_TRANSMISSIVE,) * 3, cfl=cfl,
+                        precision=precision, picard_tol=tol)
+    A = ader.Amr(prob, r=r, max_level=L, indicator_var=dim + 1, chi_ref=0.2, eps=0.01,
+                 buffer=1, use_graph=True)
+    for l in range(L + 1):
+        A.set_level(l, ic(n0 * r ** l, l))
+    t0 = time.perf_counter()
+    A.build()
+    build_s = time.perf_counter() - t0
+    counts = [A.counts(l) for l in range(L + 1)]
+    A.step(1e9)                      # warm-up, records the graph
+    A.clock()
+    cu0 = A.stats()["cell_updates"]
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        A.step(1e9)
+    t_sim, nsteps, dt0 = A.clock()
+    el = time.perf_counter() - t0
+    st = A.stats()
+    cu = st["cell_updates"] - cu0
+    A.close()
+    return {"workload": label, "precision": "fp64" if precision == ader.PREC_FP64 else
+            "fp32 predictor / fp64", "levels": counts, "mesh_build_s": build_s,
+            "level0_steps": steps, "cell_updates": cu, "seconds": el,
+            "cell_updates_per_s": cu / el, "ms_per_level0_step": el / steps * 1e3,
+            "t_reached": t_sim, "status_flags": st["flags"]}
+
+
+def amr_legs(ader, wl):
+    """The paper-shaped AMR workloads: 2D explosion (level 0 100^2, r = 3,
+    two levels, M = 2, fp32 predictor and fp64) and 3D blast (level 0 64^3,
+    r = 3, one level, M = 2, fp64 and fp32 predictor), transmissive, CFL 0.5."""
+    out = []
+    expl = lambda n, l: wl.explosion_2d(n, seed=2)
+    blast = lambda n, l: wl.blast_3d(n, seed=3, nq=4 if l == 0 else 2)
+    for prec in (ader.PREC_FP32_PREDICTOR, ader.PREC_FP64):
+        log(f"bench: AMR 2D explosion, precision {prec}")
+        out.append(amr_leg(ader, "2D Euler explosion (rho, p) = (1, 1) inside r = 0.5, "
+                           "(0.125, 0.1) outside, 1% density noise (seed 2), [-1,1]^2, "
+                           "level 0 100^2, r = 3, 2 levels, M = 2",
+                           2, 100, 3, 2, 2, expl, prec, steps=10))
+    for prec in (ader.PREC_FP64, ader.PREC_FP32_PREDICTOR):
+        log(f"bench: AMR 3D blast, precision {prec}")
+        out.append(amr_leg(ader, "3D Euler blast p = 1 inside r = 0.3, 0.1 outside, rho = 1 "
+                           "with 1% noise (seed 3), [-1,1]^3, level 0 64^3, r = 3, 1 level, "
+                           "M = 2", 3, 64, 3, 1, 2, blast, prec, steps=2))
+    return out
+
+
 def serving_leg(ader, wl, count, hbm_bytes=16 << 30, seed=4):
     """Closed loop (all requests at t = 0) for the maximum rate, then Poisson
     arrivals (seed 5) at 0.5 and 0.9 of it: p50 / p99 latency and solves/s."""
@@ -275,6 +331,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of the serving leg (0 skips it)")
+    ap.add_argument("--no-amr", action="store_true", help="skip the AMR legs")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run the launches that the HBM counters calibrate")
     args = ap.parse_args()
@@ -350,6 +407,7 @@ def main():
     serving = None
     if args.serve_requests > 0:
         serving = serving_leg(ader, wl, args.serve_requests)
+    amr = None if args.no_amr else amr_legs(ader, wl)
 
     line = {
         "metric": "cell-updates/s (FP32-predictor vs FP64) at stated L1 err; "
@@ -388,6 +446,7 @@ def main():
                      "avg_launch_ms": avg_s * 1e3},
         "cpu_baseline": cpu,
         "serving": serving,
+        "amr": amr,
     }
     print(json.dumps(line), flush=True)
 
