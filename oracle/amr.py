@@ -15,7 +15,7 @@ dense array over its whole index space, with a status per cell:
 The mother of level-l cell i is i // r on level l-1; the children of a cell
 are the r^d cells i*r + a, 0 <= a < r (consecutive blocks).
 
-Refinement (built once from the initial data).  A cell of level l < L is
+Refinement (built from the initial data, then changed by regrid()).  A cell of level l < L is
 flagged when the Loehner indicator (eq. indicator) of its level's initial
 averages exceeds chi_ref, and so are its Voronoi neighbours up to 'buffer'
 layers (the paper names no buffer; without one, a single unflagged cell on a
@@ -153,14 +153,52 @@ def _children(F: np.ndarray, r: int) -> np.ndarray:
     return out
 
 
+def _close_flags(F, bcs, r: int, L: int):
+    """Rules 4 and 5 of Section 3.1 on refinement flags F[0..L-1]: the mother
+    of every cell in the Voronoi neighbourhood of a flagged level-l cell is
+    flagged on level l-1 (so Voronoi neighbours differ by at most one level
+    and a refined cell's Voronoi neighbours exist on the finer level), and
+    flags nest (a flagged cell has a flagged mother)."""
+    F = [np.asarray(f, dtype=bool).copy() for f in F]
+    for l in range(L - 1, 0, -1):
+        F[l - 1] |= _mothers(_dilate(F[l], bcs), r)
+    for l in range(1, L):
+        F[l] &= _children(F[l - 1], r)
+    return F
+
+
+def _status_from_flags(F, shape, bcs, r: int, L: int):
+    """Status arrays of all levels from closed flags: children of flagged
+    cells are active (virtual mothers if flagged themselves); children of the
+    unflagged Voronoi neighbours of flagged cells are virtual children;
+    every other cell of levels >= 1 is absent."""
+    st = [np.full(shape[0], ACTIVE, dtype=np.int8)]
+    if L > 0:
+        st[0][F[0]] = VMOTHER
+    for l in range(1, L + 1):
+        s = np.full(shape[l], ABSENT, dtype=np.int8)
+        near = _dilate(F[l - 1], bcs) & ~F[l - 1]
+        assert np.all(st[l - 1][near] == ACTIVE)
+        s[_children(near, r)] = VCHILD
+        kids = _children(F[l - 1], r)
+        s[kids] = ACTIVE
+        if l < L:
+            s[kids & F[l]] = VMOTHER
+        st.append(s)
+    return st
+
+
 class Hierarchy:
-    """Dense per-level state and status arrays of a static AMR mesh."""
+    """Dense per-level state and status arrays of an AMR mesh."""
 
     def __init__(self, prob: Problem, r: int, L: int, U_levels, chi_ref: float = 0.2,
-                 eps: float = 0.01, indicator_var: int = 0, flags=None, buffer: int = 1):
+                 eps: float = 0.01, indicator_var: int = 0, flags=None, buffer: int = 1,
+                 chi_rec: float | None = None):
         if r < max(prob.M, 2):
             raise ValueError("the refinement factor must satisfy r >= M (and r >= 2)")
         self.prob, self.r, self.L, self.d = prob, r, L, prob.dim
+        self.chi_ref, self.eps, self.indicator_var, self.buffer = chi_ref, eps, indicator_var, buffer
+        self.chi_rec = chi_ref if chi_rec is None else chi_rec
         d = self.d
         self.bcs = list(prob.bc[:d])
         self.shape = [tuple(prob.n[k] * r ** l for k in range(d)) for l in range(L + 1)]
@@ -169,25 +207,9 @@ class Hierarchy:
                      for l in range(L)]
             for _ in range(buffer):          # buffer layers around indicator flags
                 flags = [_dilate(f, self.bcs) for f in flags]
-        F = [np.asarray(f, dtype=bool).copy() for f in flags]
-        for l in range(L - 1, 0, -1):
-            F[l - 1] |= _mothers(_dilate(F[l], self.bcs), r)
-        for l in range(1, L):
-            F[l] &= _children(F[l - 1], r)
+        F = _close_flags(flags, self.bcs, r, L)
         self.flags = F
-        st = [np.full(self.shape[0], ACTIVE, dtype=np.int8)]
-        if L > 0:
-            st[0][F[0]] = VMOTHER
-        for l in range(1, L + 1):
-            s = np.full(self.shape[l], ABSENT, dtype=np.int8)
-            near = _dilate(F[l - 1], self.bcs) & ~F[l - 1]
-            assert np.all(st[l - 1][near] == ACTIVE)
-            s[_children(near, r)] = VCHILD
-            kids = _children(F[l - 1], r)
-            s[kids] = ACTIVE
-            if l < L:
-                s[kids & F[l]] = VMOTHER
-            st.append(s)
+        st = _status_from_flags(F, self.shape, self.bcs, r, L)
         self.status = st
         self.U = []
         for l in range(L + 1):
@@ -418,6 +440,90 @@ def update_level(H: Hierarchy, l: int, dt: float):
         out -= (dt / H.dx(l)[k]) * (Fs[1] - Fs[0])
     H.U[l][(slice(None),) + tuple(cells.T)] = out
     H.cell_updates += len(cells)
+
+
+def children_from_mothers(H: Hierarchy, l: int, target: np.ndarray):
+    """Averages of the level-l cells in the mask 'target' from their mothers'
+    reconstruction (Section 2.2 on level l-1, at the current averages): the
+    average of w_h over the child's sub-cell (the projection of Section 3.1.3
+    applied to w_h).  The mean of the r^d sub-cell averages is the mother's
+    average, so refinement is conservative."""
+    r, d, M = H.r, H.d, H.prob.M
+    cells = np.argwhere(target)
+    if len(cells) == 0:
+        return
+    moth, inv = np.unique(cells // r, axis=0, return_inverse=True)
+    inv = inv.reshape(-1)
+    idx = tuple(bc_index(moth[:, k][:, None] + np.arange(-M, M + 1)[None, :],
+                         H.shape[l - 1][k], H.bcs[k]) for k in range(d))
+    for offs in np.ndindex(*([2 * M + 1] * d)):        # every mother's stencil lies in the mesh
+        pidx = tuple(idx[k][:, offs[k]] for k in range(d))
+        assert np.all(H.status[l - 1][pidx] != ABSENT), "a mother's stencil leaves the mesh"
+    w = reconstruct(H.U[l - 1], moth, M, H.bcs)          # [v, Cm, px, py(, pz)]
+    P = subcell_average_matrix(M, r)
+    val = w[:, inv]                                       # [v, C, px, py(, pz)]
+    offs = cells % r
+    for k in range(d - 1, -1, -1):                        # contract pz, then py, then px
+        val = np.einsum("vc...p,cp->vc...", val, P[offs[:, k]])
+    H.U[l][(slice(None),) + tuple(cells.T)] = val
+
+
+def refinement_flags(H: Hierarchy):
+    """Raw flags of levels 0..L-1 at a regrid (Section 3.1.1): an active cell
+    is refined when chi > chi_ref; a refined cell (virtual mother) stays
+    refined unless chi < chi_rec.  Virtual children are never flagged by the
+    indicator (rule 2: a virtual child is activated first)."""
+    out = []
+    for l in range(H.L):
+        with np.errstate(invalid="ignore"):
+            chi = lohner(H.U[l][H.indicator_var], H.bcs, H.eps)
+        st = H.status[l]
+        out.append(((st == ACTIVE) & (chi > H.chi_ref)) | ((st == VMOTHER) & (chi >= H.chi_rec)))
+    return out
+
+
+def regrid(H: Hierarchy, flags=None):
+    """Refinement and recoarsening at a common time of all levels (after a
+    level-0 step, virtual mothers averaged):
+      1. virtual children take the sub-cell averages of their mothers'
+         reconstruction, coarse to fine, so every cell holds a value at this
+         time;
+      2. raw flags (refinement_flags, or the caller's), widened by 'buffer'
+         Voronoi layers when they come from the indicator, closed by rules 4
+         and 5 (flags nest, which keeps a cell with grandchildren refined:
+         rule 7);
+      3. the new status of every cell (recoarsened cells are active again with
+         the average of their children, eq. average; their children become
+         virtual or are removed);
+      4. cells that did not exist take the sub-cell averages of their
+         mothers' reconstruction, coarse to fine (a new cell's mother may be
+         new itself).
+    Returns True when the mesh changed."""
+    L, r = H.L, H.r
+    if L == 0:
+        return False
+    average_down(H, 0)
+    for l in range(1, L + 1):
+        children_from_mothers(H, l, H.status[l] == VCHILD)
+    if flags is None:
+        F = refinement_flags(H)
+        for _ in range(H.buffer):
+            F = [_dilate(f, H.bcs) for f in F]
+    else:
+        F = [np.asarray(f, dtype=bool) for f in flags]
+    F = _close_flags(F, H.bcs, r, L)
+    old = H.status
+    new = _status_from_flags(F, H.shape, H.bcs, r, L)
+    changed = any(not np.array_equal(a, b) for a, b in zip(old, new))
+    H.status, H.flags = new, F
+    H._check_patches()
+    for l in range(1, L + 1):
+        children_from_mothers(H, l, (new[l] != ABSENT) & (old[l] == ABSENT))
+    for l in range(L + 1):
+        H.U[l][:, new[l] == ABSENT] = np.nan
+    H.q = [None] * (L + 1)
+    H.pos = [None] * (L + 1)
+    return changed
 
 
 def cfl_dt0(H: Hierarchy, t: float, t_end: float) -> float:
