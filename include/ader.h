@@ -317,7 +317,21 @@ ader_status ader_server_stats_get(ader_server server, ader_server_stats* stats);
  * most one level and a refined cell's Voronoi neighbours exist on the finer
  * level; children of flagged cells are active, children of their active
  * Voronoi neighbours are virtual.  EINVAL if an active cell's (2M+1)^d
- * stencil would leave the mesh.  The mesh is static afterwards.
+ * stencil would leave the mesh.
+ *
+ * ader_amr_regrid refines and recoarsens between steps (Section 3.1, rules
+ * 1-7; thresholds of Section 3.1.1).  All levels are at one time after a
+ * step.  Virtual mothers are averaged, then virtual children take the
+ * average of their mother's reconstruction (Section 2.2) over their
+ * sub-cell, coarse to fine.  The indicator then flags active cells with
+ * chi > chi_ref and keeps virtual mothers with chi >= chi_rec.  Flags set by
+ * ader_amr_set_flags after the build replace the indicator for one regrid.
+ * Buffer layers, closure and status follow the build.  Cells that did not
+ * exist take the sub-cell averages of their mother's reconstruction, coarse
+ * to fine.  Recoarsened cells keep the average of their children (eq.
+ * average), so a regrid is conservative.  Removed cells become NaN.
+ * Synchronous; *changed (may be NULL) is 1 when the mesh changed.  A
+ * recorded step graph is recorded again at the next ader_amr_step.
  *
  * ader_amr_step: one level-0 step, Delta t_0 = min over levels of
  * r^l CFL / max over active cells of sum_k speed_k / dx_(l,k), clipped to
@@ -340,6 +354,8 @@ typedef struct {
   int max_level;      /* finest level L */
   int indicator_var;  /* conserved variable fed to the indicator */
   double chi_ref;     /* refine where chi > chi_ref */
+  double chi_rec;     /* regrid: a refined cell is recoarsened where chi < chi_rec
+                         (chi_rec <= chi_ref; equal values: no hysteresis) */
   double eps;         /* indicator filter (0.01 in the paper) */
   int buffer;         /* Voronoi layers added around indicator flags (0..4) */
   int use_graph;      /* replay one recorded step per ader_amr_step */
@@ -352,9 +368,11 @@ ader_status ader_amr_destroy(ader_amr amr);
 ader_status ader_amr_level_cells(ader_amr amr, int level, int n[3]);
 /* Initial averages of a level's whole index space (host, [nvar][cells]). */
 ader_status ader_amr_set_level(ader_amr amr, int level, const double* u);
-/* Refinement flags of a level < max_level (host, [cells], nonzero = refine). */
+/* Refinement flags of a level < max_level (host, [cells], nonzero = refine),
+ * taken as given by the next ader_amr_build or ader_amr_regrid. */
 ader_status ader_amr_set_flags(ader_amr amr, int level, const uint8_t* flags);
 ader_status ader_amr_build(ader_amr amr);
+ader_status ader_amr_regrid(ader_amr amr, int* changed);
 ader_status ader_amr_step(ader_amr amr, double t_end, void* stream);
 ader_status ader_amr_clock(ader_amr amr, double* t, int64_t* steps, double* dt0);
 /* Level averages (host [nvar][cells]; absent cells NaN) and status (host

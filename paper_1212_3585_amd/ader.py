@@ -33,7 +33,7 @@ EXPORTS = [
     "ader_server_submit", "ader_server_progress", "ader_server_request",
     "ader_server_stats_get",
     "ader_amr_create", "ader_amr_destroy", "ader_amr_level_cells", "ader_amr_set_level",
-    "ader_amr_set_flags", "ader_amr_build", "ader_amr_step", "ader_amr_clock",
+    "ader_amr_set_flags", "ader_amr_build", "ader_amr_regrid", "ader_amr_step", "ader_amr_clock",
     "ader_amr_get_level", "ader_amr_counts", "ader_amr_stats",
     "ader_status_string", "ader_last_error",
 ]
@@ -91,7 +91,8 @@ class CServerStats(ctypes.Structure):
 class CAmrConfig(ctypes.Structure):
     _fields_ = [("r", ctypes.c_int), ("max_level", ctypes.c_int),
                 ("indicator_var", ctypes.c_int), ("chi_ref", ctypes.c_double),
-                ("eps", ctypes.c_double), ("buffer", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("chi_rec", ctypes.c_double), ("eps", ctypes.c_double), ("buffer", ctypes.c_int),
+                ("use_graph", ctypes.c_int)]
 
 
 _lib = None
@@ -140,6 +141,7 @@ def load_library():
         "ader_amr_set_level": [vp, ctypes.c_int, vp],
         "ader_amr_set_flags": [vp, ctypes.c_int, vp],
         "ader_amr_build": [vp],
+        "ader_amr_regrid": [vp, ctypes.POINTER(ctypes.c_int)],
         "ader_amr_step": [vp, dbl, vp],
         "ader_amr_clock": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl)],
         "ader_amr_get_level": [vp, ctypes.c_int, vp, vp],
@@ -482,11 +484,13 @@ class Amr:
     arrays [nvar, nx, ny(, nz)] over each level's whole index space."""
 
     def __init__(self, problem: Problem, r=3, max_level=1, indicator_var=0, chi_ref=0.2,
-                 eps=0.01, buffer=1, use_graph=True):
+                 eps=0.01, buffer=1, use_graph=True, chi_rec=None):
         self.lib = load_library()
         self.problem = problem
         self.L = max_level
-        cfg = CAmrConfig(r, max_level, indicator_var, chi_ref, eps, buffer, int(bool(use_graph)))
+        chi_rec = chi_ref if chi_rec is None else chi_rec
+        cfg = CAmrConfig(r, max_level, indicator_var, chi_ref, chi_rec, eps, buffer,
+                         int(bool(use_graph)))
         h = ctypes.c_void_p()
         _check(self.lib.ader_amr_create(ctypes.byref(problem.to_c()), ctypes.byref(cfg),
                                         ctypes.byref(h)), "ader_amr_create")
@@ -518,6 +522,12 @@ class Amr:
     def build(self):
         _check(self.lib.ader_amr_build(self._h), "ader_amr_build")
 
+    def regrid(self):
+        """Refine and recoarsen at the current time; True when the mesh changed."""
+        ch = ctypes.c_int()
+        _check(self.lib.ader_amr_regrid(self._h, ctypes.byref(ch)), "ader_amr_regrid")
+        return bool(ch.value)
+
     def step(self, t_end, stream=None):
         _check(self.lib.ader_amr_step(self._h, float(t_end), _stream(stream)), "ader_amr_step")
 
@@ -528,12 +538,15 @@ class Amr:
                                        ctypes.byref(dt0)), "ader_amr_clock")
         return t.value, steps.value, dt0.value
 
-    def run(self, t_end, max_steps=10 ** 9):
-        """Level-0 steps until t_end (reads the clock after each step)."""
+    def run(self, t_end, max_steps=10 ** 9, regrid_every=0):
+        """Level-0 steps until t_end (reads the clock after each step); with
+        regrid_every = k > 0 a regrid follows every k-th step."""
         t, steps, _ = self.clock()
         while t < t_end and steps < max_steps:
             self.step(t_end)
             t, steps, _ = self.clock()
+            if regrid_every > 0 and steps % regrid_every == 0:
+                self.regrid()
         return t, steps
 
     def level(self, level):

@@ -16,8 +16,19 @@
 //   4. every active cell's (2M+1)^d stencil must lie in the mesh (r >= M).
 // The indicator is evaluated in plain double arithmetic, term by term, so the
 // integer refinement decisions are reproducible.
+//
+// Regrid (ader_amr_regrid), at a common time of all levels:
+//   1. virtual mothers averaged; virtual children take the sub-cell averages
+//      of their mothers' reconstruction, coarse to fine (device);
+//   2. flags on the host from the indicator variable: an active cell is
+//      refined when chi > chi_ref, a virtual mother stays refined unless
+//      chi < chi_rec; buffer layers, closure and status as in the build;
+//   3. new level lists and scratch; cells that did not exist take the
+//      sub-cell averages of their mothers' reconstruction, coarse to fine
+//      (device); removed cells are set to NaN.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -42,6 +53,7 @@ struct ader_amr_s {
   std::vector<std::vector<uint8_t>> h_flags;
   std::vector<std::vector<int8_t>> h_status;
   std::vector<void*> dev_allocs;
+  std::vector<std::vector<void*>> lvl_bufs;  // per-level lists and scratch (replaced by a regrid)
   double* partial = nullptr;
   ader::AmrClock* clock = nullptr;
   ader::AmrClock* h_clock = nullptr;  // pinned staging
@@ -49,7 +61,7 @@ struct ader_amr_s {
   hipGraphExec_t exec = nullptr;
   bool built = false;
   double t_end_set = -1.0;
-  uint64_t cell_updates = 0, updates_per_step = 0;
+  uint64_t cell_updates = 0, updates_per_step = 0, regrids = 0;
   ader::AmrDtArgs dtargs{};
 };
 
@@ -177,6 +189,77 @@ std::vector<uint8_t> children(const Grid& coarse, const Grid& fine, const std::v
   return out;
 }
 
+using Flags = std::vector<std::vector<uint8_t>>;
+using Status = std::vector<std::vector<int8_t>>;
+
+// Rules 4 and 5: the mother of every cell in the Voronoi neighbourhood of a
+// flagged level-l cell is flagged on level l-1; flags nest.
+void close_flags(const std::vector<Grid>& g, Flags& F, const int* bc, int r, int L) {
+  for (int l = L - 1; l >= 1; --l) {
+    std::vector<uint8_t> m = mothers(g[l], g[l - 1], dilate(g[l], F[l], bc), r);
+    for (size_t i = 0; i < m.size(); ++i) F[l - 1][i] |= m[i];
+  }
+  for (int l = 1; l < L; ++l) {
+    std::vector<uint8_t> c = children(g[l - 1], g[l], F[l - 1], r);
+    for (size_t i = 0; i < c.size(); ++i) F[l][i] &= c[i];
+  }
+}
+
+// Status of every level from closed flags.
+Status status_from_flags(const std::vector<Grid>& g, const Flags& F, const int* bc, int r,
+                         int L) {
+  Status S(L + 1);
+  S[0].assign(g[0].cells(), ader::kActive);
+  if (L > 0)
+    for (int64_t i = 0; i < g[0].cells(); ++i)
+      if (F[0][i]) S[0][i] = ader::kVMother;
+  for (int l = 1; l <= L; ++l) {
+    std::vector<uint8_t> near = dilate(g[l - 1], F[l - 1], bc);
+    for (size_t i = 0; i < near.size(); ++i) near[i] = near[i] && !F[l - 1][i];
+    std::vector<uint8_t> vch = children(g[l - 1], g[l], near, r);
+    std::vector<uint8_t> kids = children(g[l - 1], g[l], F[l - 1], r);
+    std::vector<int8_t>& s = S[l];
+    s.assign(g[l].cells(), ader::kAbsent);
+    for (int64_t i = 0; i < g[l].cells(); ++i) {
+      if (vch[i]) s[i] = ader::kVChild;
+      if (kids[i]) s[i] = (l < L && F[l][i]) ? ader::kVMother : ader::kActive;
+    }
+  }
+  return S;
+}
+
+// Every active cell's (2M+1)^d stencil lies in the mesh.
+bool stencils_in_mesh(const std::vector<Grid>& g, const Status& S, const int* bc, int M) {
+  for (size_t l = 0; l < S.size(); ++l) {
+    const std::vector<int8_t>& s = S[l];
+    const int d = g[l].d;
+    for (int64_t i = 0; i < g[l].cells(); ++i) {
+      if (s[i] != ader::kActive) continue;
+      int c[3];
+      g[l].coords(i, c);
+      const int spanz = d > 2 ? M : 0;
+      for (int oz = -spanz; oz <= spanz; ++oz)
+        for (int oy = -M; oy <= M; ++oy)
+          for (int ox = -M; ox <= M; ++ox) {
+            const int o[3] = {ox, oy, oz};
+            int cc[3] = {0, 0, 0};
+            for (int k = 0; k < d; ++k) cc[k] = map_bc(c[k] + o[k], g[l].n[k], bc[k]);
+            if (s[g[l].idx(cc)] == ader::kAbsent) return false;
+          }
+    }
+  }
+  return true;
+}
+
+std::vector<Grid> level_grids(const ader_amr_s* a) {
+  std::vector<Grid> g(a->L + 1);
+  for (int l = 0; l <= a->L; ++l) {
+    g[l].d = a->d;
+    for (int k = 0; k < 3; ++k) g[l].n[k] = a->lv[l].n[k];
+  }
+  return g;
+}
+
 template <typename T>
 ader_status upload(ader_amr a, T** dst, const void* src, size_t bytes) {
   void* p = nullptr;
@@ -189,6 +272,115 @@ ader_status upload(ader_amr a, T** dst, const void* src, size_t bytes) {
   }
   *dst = static_cast<T*>(p);
   return ADER_OK;
+}
+
+// Device buffer owned by level l's list set (freed when the lists change).
+template <typename T>
+ader_status upload_lvl(ader_amr a, int l, T** dst, const void* src, size_t bytes) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes > 0 ? bytes : 256);
+  if (e != hipSuccess) return hip_status(e, "AMR level lists (allocation)");
+  a->lvl_bufs[l].push_back(p);
+  if (src && bytes) {
+    e = hipMemcpy(p, src, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_status(e, "AMR level lists (upload)");
+  }
+  *dst = static_cast<T*>(p);
+  return ADER_OK;
+}
+
+// Lists, positions and scratch of level l from a->h_status[l]; the dense
+// status and position arrays are rewritten in place.
+ader_status set_level_lists(ader_amr a, int l) {
+  ader::AmrLevel& v = a->lv[l];
+  const int64_t N = v.ncells;
+  const int M = a->M, d = a->d;
+  const std::vector<int8_t>& s = a->h_status[l];
+  std::vector<int32_t> act, vc, vm, pos(N, -1);
+  for (int64_t i = 0; i < N; ++i) {
+    if (s[i] == ader::kActive) {
+      pos[i] = (int32_t)act.size();
+      act.push_back((int32_t)i);
+    } else if (s[i] == ader::kVChild) {
+      vc.push_back((int32_t)i);
+    } else if (s[i] == ader::kVMother) {
+      vm.push_back((int32_t)i);
+    }
+  }
+  hipError_t e = hipDeviceSynchronize();
+  for (void* p : a->lvl_bufs[l])
+    if (e == hipSuccess) e = hipFree(p);
+  a->lvl_bufs[l].clear();
+  if (e == hipSuccess) e = hipMemcpy(v.st, s.data(), N, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(v.pos, pos.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_status(e, "AMR level lists");
+  v.nact = (int64_t)act.size();
+  v.nvc = (int64_t)vc.size();
+  v.nvm = (int64_t)vm.size();
+  ader_status st = ADER_OK;
+  if (!st) st = upload_lvl(a, l, &v.act, act.data(), sizeof(int32_t) * act.size());
+  if (!st) st = upload_lvl(a, l, &v.vc, vc.data(), sizeof(int32_t) * vc.size());
+  if (!st) st = upload_lvl(a, l, &v.vm, vm.data(), sizeof(int32_t) * vm.size());
+  const size_t na = (size_t)v.nact;
+  if (!st)
+    st = upload_lvl(a, l, &v.wa, nullptr, sizeof(double) * a->impl->weno_scratch_per_cell() * na);
+  v.wb = v.wa ? v.wa + (size_t)a->nv * (M + 1) * ipow(2 * M + 1, d - 1) * na : nullptr;
+  if (!st) st = upload_lvl(a, l, &v.wh, nullptr, sizeof(double) * a->impl->wh_per_cell() * na);
+  if (!st)
+    st = upload_lvl(a, l, &v.qh, nullptr,
+                    a->impl->qh_elem_size() * a->nv * ipow(M + 1, d + 1) * na);
+  if (st) return st;
+  a->dtargs.nb[l] = v.nact == 0 ? 0
+                    : (int)std::min<int64_t>((v.nact + ader::kBlock - 1) / ader::kBlock,
+                                             ader::kDtMaxBlocks);
+  a->updates_per_step = 0;
+  for (int k = 0; k <= a->L; ++k)
+    a->updates_per_step += (uint64_t)a->lv[k].nact * (uint64_t)ipow(a->r, k);
+  return ADER_OK;
+}
+
+// Level-l cells 'targets' (dense indices) from the reconstruction of their
+// mothers on level l-1 (synchronous; temporaries freed before returning).
+ader_status children_pass(ader_amr a, int l, const std::vector<int32_t>& targets) {
+  if (targets.empty()) return ADER_OK;
+  const std::vector<Grid> g = level_grids(a);
+  std::vector<int32_t> moth(targets.size());
+  for (size_t i = 0; i < targets.size(); ++i) {
+    int c[3];
+    g[l].coords(targets[i], c);
+    for (int k = 0; k < a->d; ++k) c[k] /= a->r;
+    moth[i] = (int32_t)g[l - 1].idx(c);
+  }
+  std::vector<int32_t> uniq(moth);
+  std::sort(uniq.begin(), uniq.end());
+  uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+  std::vector<int32_t> slot(targets.size());
+  for (size_t i = 0; i < targets.size(); ++i)
+    slot[i] = (int32_t)(std::lower_bound(uniq.begin(), uniq.end(), moth[i]) - uniq.begin());
+  const size_t nm = uniq.size(), nt = targets.size();
+  const size_t wa_n = a->impl->weno_scratch_per_cell() * nm, wh_n = a->impl->wh_per_cell() * nm;
+  void* buf[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  const size_t bytes[5] = {sizeof(int32_t) * nm, sizeof(int32_t) * nt, sizeof(int32_t) * nt,
+                           sizeof(double) * wa_n, sizeof(double) * wh_n};
+  const void* src[5] = {uniq.data(), targets.data(), slot.data(), nullptr, nullptr};
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 5 && e == hipSuccess; ++i) {
+    e = hipMalloc(&buf[i], bytes[i]);
+    if (e == hipSuccess && src[i]) e = hipMemcpy(buf[i], src[i], bytes[i], hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) {
+    double* wa = static_cast<double*>(buf[3]);
+    double* wb = wa + (size_t)a->nv * (a->M + 1) * ipow(2 * a->M + 1, a->d - 1) * nm;
+    e = a->impl->children(a->lv[l - 1], static_cast<const int32_t*>(buf[0]), (int64_t)nm, wa, wb,
+                          static_cast<double*>(buf[4]), a->lv[l],
+                          static_cast<const int32_t*>(buf[1]), static_cast<const int32_t*>(buf[2]),
+                          (int64_t)nt, a->dc, a->ac, a->stream);
+  }
+  const hipError_t es = hipStreamSynchronize(a->stream);
+  if (e == hipSuccess) e = es;
+  for (void* p : buf)
+    if (p) (void)hipFree(p);
+  return hip_status(e, "ader_amr_regrid");
 }
 
 ader_status record_advance(ader_amr a, int l, int sub, hipStream_t st) {
@@ -244,6 +436,8 @@ ader_status ader_amr_create(const ader_problem* prob, const ader_amr_config* cfg
     return fail(ADER_EINVAL, "indicator_var out of range");
   if (!std::isfinite(cfg->chi_ref) || !std::isfinite(cfg->eps) || cfg->eps < 0.0)
     return fail(ADER_EINVAL, "chi_ref and eps must be finite, eps >= 0");
+  if (!std::isfinite(cfg->chi_rec) || cfg->chi_rec > cfg->chi_ref)
+    return fail(ADER_EINVAL, "chi_rec must be finite and at most chi_ref");
   if (cfg->buffer < 0 || cfg->buffer > 4) return fail(ADER_EINVAL, "buffer must be in 0..4");
   // every level's cell count and the indices of the finest level must fit
   int64_t fine = ncells * ipow(cfg->r, cfg->max_level * prob->dim);
@@ -296,6 +490,8 @@ ader_status ader_amr_destroy(ader_amr a) {
   if (a->stream) (void)hipStreamSynchronize(a->stream);
   if (a->exec) (void)hipGraphExecDestroy(a->exec);
   for (void* p : a->dev_allocs) (void)hipFree(p);
+  for (auto& v : a->lvl_bufs)
+    for (void* p : v) (void)hipFree(p);
   if (a->h_clock) (void)hipHostFree(a->h_clock);
   if (a->stream) (void)hipStreamDestroy(a->stream);
   delete a;
@@ -318,7 +514,6 @@ ader_status ader_amr_set_level(ader_amr a, int level, const double* u) {
 
 ader_status ader_amr_set_flags(ader_amr a, int level, const uint8_t* flags) {
   if (!a || !flags || level < 0 || level >= a->L) return fail(ADER_EINVAL, "bad level or pointer");
-  if (a->built) return fail(ADER_EINVAL, "the mesh is already built");
   const int64_t N = a->lv[level].ncells;
   a->h_flags[level].assign(flags, flags + N);
   for (auto& x : a->h_flags[level]) x = x ? 1 : 0;
@@ -350,108 +545,41 @@ ader_status ader_amr_build(ader_amr a) {
       for (int b = 0; b < a->cfg.buffer; ++b) F[l] = dilate(g[l], F[l], bc);
     }
   }
-  // 2. closure and nesting
-  for (int l = L - 1; l >= 1; --l) {
-    std::vector<uint8_t> m = mothers(g[l], g[l - 1], dilate(g[l], F[l], bc), r);
-    for (size_t i = 0; i < m.size(); ++i) F[l - 1][i] |= m[i];
-  }
-  for (int l = 1; l < L; ++l) {
-    std::vector<uint8_t> c = children(g[l - 1], g[l], F[l - 1], r);
-    for (size_t i = 0; i < c.size(); ++i) F[l][i] &= c[i];
-  }
-  // 3. status
-  a->h_status.assign(L + 1, {});
-  a->h_status[0].assign(g[0].cells(), ader::kActive);
-  if (L > 0)
-    for (int64_t i = 0; i < g[0].cells(); ++i)
-      if (F[0][i]) a->h_status[0][i] = ader::kVMother;
-  for (int l = 1; l <= L; ++l) {
-    std::vector<uint8_t> near = dilate(g[l - 1], F[l - 1], bc);
-    for (size_t i = 0; i < near.size(); ++i) near[i] = near[i] && !F[l - 1][i];
-    std::vector<uint8_t> vch = children(g[l - 1], g[l], near, r);
-    std::vector<uint8_t> kids = children(g[l - 1], g[l], F[l - 1], r);
-    std::vector<int8_t>& s = a->h_status[l];
-    s.assign(g[l].cells(), ader::kAbsent);
-    for (int64_t i = 0; i < g[l].cells(); ++i) {
-      if (vch[i]) s[i] = ader::kVChild;
-      if (kids[i]) s[i] = (l < L && F[l][i]) ? ader::kVMother : ader::kActive;
-    }
-  }
-  // 4. every active stencil lies in the mesh
-  const int M = a->M;
-  for (int l = 0; l <= L; ++l) {
-    const std::vector<int8_t>& s = a->h_status[l];
-    for (int64_t i = 0; i < g[l].cells(); ++i) {
-      if (s[i] != ader::kActive) continue;
-      int c[3];
-      g[l].coords(i, c);
-      const int spanz = d > 2 ? M : 0;
-      for (int oz = -spanz; oz <= spanz; ++oz)
-        for (int oy = -M; oy <= M; ++oy)
-          for (int ox = -M; ox <= M; ++ox) {
-            const int o[3] = {ox, oy, oz};
-            int cc[3] = {0, 0, 0};
-            for (int k = 0; k < d; ++k) cc[k] = map_bc(c[k] + o[k], g[l].n[k], bc[k]);
-            if (s[g[l].idx(cc)] == ader::kAbsent)
-              return fail(ADER_EINVAL, "an active cell's stencil leaves the mesh");
-          }
-    }
-  }
+  // 2. closure and nesting, 3. status, 4. every active stencil lies in the mesh
+  close_flags(g, F, bc, r, L);
+  a->h_status = status_from_flags(g, F, bc, r, L);
+  if (!stencils_in_mesh(g, a->h_status, bc, a->M))
+    return fail(ADER_EINVAL, "an active cell's stencil leaves the mesh");
+  for (auto& f : a->h_flags) f.clear();
   // 5. device data
   hipError_t e = hipStreamCreateWithFlags(&a->stream, hipStreamNonBlocking);
   if (e != hipSuccess) return hip_status(e, "ader_amr_build");
   const double dx0[3] = {(a->prob.hi[0] - a->prob.lo[0]) / a->prob.n[0],
                          (a->prob.hi[1] - a->prob.lo[1]) / a->prob.n[1],
                          d > 2 ? (a->prob.hi[2] - a->prob.lo[2]) / a->prob.n[2] : 1.0};
-  a->updates_per_step = 0;
+  a->lvl_bufs.assign(L + 1, {});
   for (int l = 0; l <= L; ++l) {
     ader::AmrLevel& v = a->lv[l];
     const int64_t N = v.ncells;
     const std::vector<int8_t>& s = a->h_status[l];
-    std::vector<int32_t> act, vc, vm, pos(N, -1);
-    for (int64_t i = 0; i < N; ++i) {
-      if (s[i] == ader::kActive) {
-        pos[i] = (int32_t)act.size();
-        act.push_back((int32_t)i);
-      } else if (s[i] == ader::kVChild) {
-        vc.push_back((int32_t)i);
-      } else if (s[i] == ader::kVMother) {
-        vm.push_back((int32_t)i);
-      }
-    }
-    v.nact = (int64_t)act.size();
-    v.nvc = (int64_t)vc.size();
-    v.nvm = (int64_t)vm.size();
-    a->updates_per_step += (uint64_t)v.nact * (uint64_t)ipow(r, l);
     std::vector<double> u0(a->h_init[l]);
     for (int64_t i = 0; i < N; ++i)
       if (s[i] == ader::kAbsent)
         for (int q = 0; q < nv; ++q) u0[(size_t)q * N + i] = std::nan("");
     ader_status st = ADER_OK;
     if (!st) st = upload(a, &v.u, u0.data(), sizeof(double) * nv * N);
-    if (!st) st = upload(a, &v.st, s.data(), N);
-    if (!st) st = upload(a, &v.pos, pos.data(), sizeof(int32_t) * N);
-    if (!st) st = upload(a, &v.act, act.data(), sizeof(int32_t) * act.size());
-    if (!st) st = upload(a, &v.vc, vc.data(), sizeof(int32_t) * vc.size());
-    if (!st) st = upload(a, &v.vm, vm.data(), sizeof(int32_t) * vm.size());
+    if (!st) st = upload(a, &v.st, nullptr, N);
+    if (!st) st = upload(a, &v.pos, nullptr, sizeof(int32_t) * N);
     if (!st && l > 0) st = upload(a, &v.mem, nullptr, sizeof(double) * d * 2 * nv * N);
-    const size_t na = (size_t)v.nact;
-    if (!st) st = upload(a, &v.wa, nullptr, sizeof(double) * a->impl->weno_scratch_per_cell() * na);
-    v.wb = v.wa ? v.wa + (size_t)nv * (M + 1) * ipow(2 * M + 1, d - 1) * na : nullptr;
-    if (!st) st = upload(a, &v.wh, nullptr, sizeof(double) * a->impl->wh_per_cell() * na);
-    if (!st)
-      st = upload(a, &v.qh, nullptr, a->impl->qh_elem_size() * nv * ipow(M + 1, d + 1) * na);
     std::vector<char> zero(ader::kHeaderBytes, 0);
     if (!st) st = upload(a, &v.hdr, zero.data(), ader::kHeaderBytes);
+    if (!st) st = set_level_lists(a, l);
     if (st) return st;
     ader_problem pl = a->prob;
     for (int k = 0; k < d; ++k) pl.n[k] = v.n[k];
     ader::fill_mesh_params(pl, N, &v.mp);
     for (int k = 0; k < d; ++k) v.dx[k] = v.mp.dx[k] = dx0[k] / (double)ipow(r, l);
     v.mp.ld = N;
-    a->dtargs.nb[l] = v.nact == 0 ? 0
-                      : (int)std::min<int64_t>((v.nact + ader::kBlock - 1) / ader::kBlock,
-                                               ader::kDtMaxBlocks);
   }
   a->dtargs.nlev = L + 1;
   a->dtargs.r = r;
@@ -505,6 +633,89 @@ ader_status ader_amr_step(ader_amr a, double t_end, void* stream) {
     if (ader_status rs = record_step(a, st)) return rs;
   }
   a->cell_updates += a->updates_per_step;
+  return ADER_OK;
+}
+
+ader_status ader_amr_regrid(ader_amr a, int* changed) {
+  if (changed) *changed = 0;
+  if (!a || !a->built) return fail(ADER_EINVAL, "mesh not built");
+  const int r = a->r, L = a->L;
+  if (L == 0) return ADER_OK;
+  const int* bc = a->prob.bc;
+  const std::vector<Grid> g = level_grids(a);
+  hipError_t e = hipDeviceSynchronize();
+  // 1. virtual mothers, then virtual children from their mothers, coarse to fine
+  for (int lev = L - 1; lev >= 0 && e == hipSuccess; --lev)
+    e = a->impl->average(a->lv[lev], a->lv[lev + 1], r, a->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
+  if (e != hipSuccess) return hip_status(e, "ader_amr_regrid");
+  for (int l = 1; l <= L; ++l) {
+    std::vector<int32_t> t;
+    const std::vector<int8_t>& s = a->h_status[l];
+    for (int64_t i = 0; i < (int64_t)s.size(); ++i)
+      if (s[i] == ader::kVChild) t.push_back((int32_t)i);
+    if (ader_status st = children_pass(a, l, t)) return st;
+  }
+  // 2. flags: refine active cells above chi_ref, keep virtual mothers down to chi_rec
+  Flags F(L);
+  for (int l = 0; l < L; ++l) {
+    if (!a->h_flags[l].empty()) {
+      F[l] = a->h_flags[l];
+      continue;
+    }
+    const int64_t N = g[l].cells();
+    std::vector<double> Phi(N);
+    e = hipMemcpy(Phi.data(), a->lv[l].u + (size_t)a->cfg.indicator_var * N, sizeof(double) * N,
+                  hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_status(e, "ader_amr_regrid");
+    const std::vector<double> chi = lohner(g[l], Phi.data(), bc, a->cfg.eps);
+    const std::vector<int8_t>& s = a->h_status[l];
+    F[l].assign(N, 0);
+    for (int64_t i = 0; i < N; ++i)
+      F[l][i] = (s[i] == ader::kActive && chi[i] > a->cfg.chi_ref) ||
+                (s[i] == ader::kVMother && chi[i] >= a->cfg.chi_rec);
+    for (int b = 0; b < a->cfg.buffer; ++b) F[l] = dilate(g[l], F[l], bc);
+  }
+  for (auto& f : a->h_flags) f.clear();
+  close_flags(g, F, bc, r, L);
+  Status S = status_from_flags(g, F, bc, r, L);
+  if (!stencils_in_mesh(g, S, bc, a->M))
+    return fail(ADER_EINVAL, "an active cell's stencil would leave the mesh");
+  if (S == a->h_status) return ADER_OK;
+  // 3. new lists; new cells from their mothers, coarse to fine; removed cells NaN
+  Status old = std::move(a->h_status);
+  a->h_status = std::move(S);
+  for (int l = 0; l <= L; ++l)
+    if (ader_status st = set_level_lists(a, l)) return st;
+  for (int l = 1; l <= L; ++l) {
+    std::vector<int32_t> born, gone;
+    const std::vector<int8_t>& s = a->h_status[l];
+    for (int64_t i = 0; i < (int64_t)s.size(); ++i) {
+      if (s[i] != ader::kAbsent && old[l][i] == ader::kAbsent) born.push_back((int32_t)i);
+      if (s[i] == ader::kAbsent && old[l][i] != ader::kAbsent) gone.push_back((int32_t)i);
+    }
+    if (ader_status st = children_pass(a, l, born)) return st;
+    if (!gone.empty()) {
+      int32_t* dl = nullptr;
+      e = hipMalloc(&dl, sizeof(int32_t) * gone.size());
+      if (e == hipSuccess)
+        e = hipMemcpy(dl, gone.data(), sizeof(int32_t) * gone.size(), hipMemcpyHostToDevice);
+      if (e == hipSuccess)
+        e = ader::launch_fill_list(a->lv[l].u, a->lv[l].ncells, a->nv, dl,
+                                   (int64_t)gone.size(), std::nan(""), a->stream);
+      const hipError_t es = hipStreamSynchronize(a->stream);
+      if (e == hipSuccess) e = es;
+      if (dl) (void)hipFree(dl);
+      if (e != hipSuccess) return hip_status(e, "ader_amr_regrid");
+    }
+  }
+  // the recorded step holds the old lists: record again at the next step
+  if (a->exec) {
+    (void)hipGraphExecDestroy(a->exec);
+    a->exec = nullptr;
+  }
+  a->regrids += 1;
+  if (changed) *changed = 1;
   return ADER_OK;
 }
 

@@ -13,6 +13,9 @@
 //   k_amr_weno_x    first WENO pass of the active cells, stencil indices from
 //                   the dense grid; later passes and the predictor are the
 //                   level-list kernels (level.hpp, predictor kernels)
+//   k_amr_subavg    a regrid's new (and virtual) children: the average of
+//                   the mother's reconstruction w_h over the child's sub-cell
+//   k_fill_list     one value into listed cells of every variable
 //   k_amr_update    finite-volume update of the active cells: same-level
 //                   faces as on a uniform mesh; a face to a virtual child
 //                   (coarser neighbour) takes the coarse predictor at this
@@ -104,6 +107,53 @@ __global__ void k_amr_dt(const double* __restrict__ partial, AmrDtArgs a, AmrClo
   for (int l = 1; l < a.nlev; ++l) clock->dt[l] = clock->dt[l - 1] / a.r;
   clock->t = t + dt;
   clock->steps = clock->steps + 1;
+}
+
+template <int TAG>
+__global__ void __launch_bounds__(kBlock)
+k_fill_list(double* __restrict__ u, int64_t ld, int nv, const int32_t* __restrict__ list,
+            int64_t n, double value) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n * nv) return;
+  u[(t / n) * ld + list[t % n]] = value;
+}
+
+// Children from their mothers' reconstruction at a regrid: target i of the
+// fine level (dense index targets[i]) takes, for every variable,
+//   sum_p  prod_k sub_avg[a_k][p_k]  w_h[slot][v][p],   a_k = c_k mod r,
+// with w_h of mother slot tslot[i] in the layout of the WENO passes
+// ([slot][v][px + n py + n^2 pz]).  Contracted along x, then y, then z.
+template <int DIM, int M, int NV>
+__global__ void __launch_bounds__(kBlock)
+k_amr_subavg(double* __restrict__ u, int64_t ld, const int32_t* __restrict__ targets,
+             const int32_t* __restrict__ tslot, int64_t nt, int n0, int n1, int n2,
+             const double* __restrict__ wh, AmrConsts ac) {
+  constexpr int n = M + 1;
+  constexpr int NS = Pow<n, DIM>::v;
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= nt * NV) return;
+  const int v = (int)(t % NV);
+  const int64_t i = t / NV;
+  const int nn[3] = {n0, n1, n2};
+  int cc[3];
+  dense_coords<DIM>(targets[i], nn, cc);
+  const int r = ac.r;
+  const double* w = wh + ((int64_t)tslot[i] * NV + v) * NS;
+  double acc_z = 0.0;
+#pragma unroll
+  for (int pz = 0; pz < (DIM > 2 ? n : 1); ++pz) {
+    double acc_y = 0.0;
+#pragma unroll
+    for (int py = 0; py < (DIM > 1 ? n : 1); ++py) {
+      double acc_x = 0.0;
+#pragma unroll
+      for (int px = 0; px < n; ++px)
+        acc_x += ac.sub_avg[cc[0] % r][px] * w[px + n * (py + n * pz)];
+      acc_y += DIM > 1 ? ac.sub_avg[cc[1] % r][py] * acc_x : acc_x;
+    }
+    acc_z += DIM > 2 ? ac.sub_avg[cc[2] % r][pz] * acc_y : acc_y;
+  }
+  u[(int64_t)v * ld + targets[i]] = acc_z;
 }
 
 template <int TAG>

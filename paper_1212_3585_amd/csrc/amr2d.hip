@@ -27,4 +27,13 @@ hipError_t launch_fill(double* p, int64_t n, double value, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_fill_list(double* u, int64_t ld, int nv, const int32_t* list, int64_t n,
+                            double value, hipStream_t st) {
+  if (n <= 0 || nv <= 0) return hipSuccess;
+  const int64_t b = (n * nv + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_fill_list<0>, dim3((unsigned)b), dim3(kBlock), 0, st, u, ld, nv, list, n,
+                     value);
+  return hipGetLastError();
+}
+
 }  // namespace ader

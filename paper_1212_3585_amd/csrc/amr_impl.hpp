@@ -83,6 +83,30 @@ class AmrImpl final : public AmrImplBase {
     return hipGetLastError();
   }
 
+  hipError_t children(const AmrLevel& cl, const int32_t* moth, int64_t nm, double* wa,
+                      double* wb, double* wh, const AmrLevel& fl, const int32_t* targets,
+                      const int32_t* tslot, int64_t nt, const DevConsts& c, const AmrConsts& ac,
+                      hipStream_t st) const override {
+    if (nm == 0 || nt == 0) return hipSuccess;
+    unsigned int* flags = &cl.hdr->status;
+    double* pass1 = DIM == 2 ? wh : wb;
+    hipLaunchKernelGGL((k_amr_weno_x<DIM, M, NV>), dim3(amr_blocks(nm * NV * Pow<S, DIM - 1>::v)),
+                       dim3(kBlock), 0, st, cl.u, cl.ncells, moth, nm, cl.mp, wa, c);
+    hipLaunchKernelGGL((k_level_weno_pass<DIM, M, NV, 1>),
+                       dim3(amr_blocks(nm * NV * n * Pow<S, DIM - 2>::v)), dim3(kBlock), 0, st,
+                       (const double*)nullptr, (int64_t)0, (const int32_t*)nullptr,
+                       (const double*)wa, pass1, nm, c, flags);
+    if constexpr (DIM == 3) {
+      hipLaunchKernelGGL((k_level_weno_pass<DIM, M, NV, 2>), dim3(amr_blocks(nm * NV * n * n)),
+                         dim3(kBlock), 0, st, (const double*)nullptr, (int64_t)0,
+                         (const int32_t*)nullptr, (const double*)wb, wh, nm, c, flags);
+    }
+    hipLaunchKernelGGL((k_amr_subavg<DIM, M, NV>), dim3(amr_blocks(nt * NV)), dim3(kBlock), 0, st,
+                       fl.u, fl.ncells, targets, tslot, nt, fl.n[0], fl.n[1], fl.n[2],
+                       (const double*)wh, ac);
+    return hipGetLastError();
+  }
+
   hipError_t update(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
                     const double* dt, int sub, const DevConsts& c, const AmrConsts& ac,
                     hipStream_t st) const override {

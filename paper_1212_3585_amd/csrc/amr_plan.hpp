@@ -79,6 +79,13 @@ class AmrImplBase {
   virtual hipError_t update(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
                             const double* dt, int sub, const DevConsts& c, const AmrConsts& ac,
                             hipStream_t st) const = 0;
+  // regrid: reconstruction of the listed cells 'moth' (nm of them) of
+  // 'coarse' into wh (scratch wa, wb as for predict), then targets[i] of
+  // 'fine' = sub-cell average of w_h of slot tslot[i]
+  virtual hipError_t children(const AmrLevel& coarse, const int32_t* moth, int64_t nm,
+                              double* wa, double* wb, double* wh, const AmrLevel& fine,
+                              const int32_t* targets, const int32_t* tslot, int64_t nt,
+                              const DevConsts& c, const AmrConsts& ac, hipStream_t st) const = 0;
 };
 
 const AmrImplBase* make_amr_impl_2d(int M, int system, int precision);
@@ -96,5 +103,8 @@ struct AmrDtArgs {
 hipError_t launch_amr_dt(const double* partial, AmrDtArgs a, AmrClock* clock, WsHeader* hdr,
                          hipStream_t st);
 hipError_t launch_fill(double* p, int64_t n, double value, hipStream_t st);
+// u[v * ld + list[i]] = value for every variable v < nv and i < n
+hipError_t launch_fill_list(double* u, int64_t ld, int nv, const int32_t* list, int64_t n,
+                            double value, hipStream_t st);
 
 }  // namespace ader

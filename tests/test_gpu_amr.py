@@ -31,7 +31,7 @@ def _levels_from_fine(Uf, r, L):
 
 
 def _make(ader, dim, M, n0, r, L, Us, bc="periodic", flags=None, lo=0.0, hi=1.0,
-          precision=0, use_graph=True, indicator_var=0, chi_ref=0.2, cfl=0.9):
+          precision=0, use_graph=True, indicator_var=0, chi_ref=0.2, cfl=0.9, chi_rec=None):
     tol = 1e-14 if precision == 0 else 1e-6
     bcs = [bc] * dim
     op = OProblem(dim, M, Euler(dim), (n0,) * dim, (lo,) * dim, (hi,) * dim, bcs, cfl=cfl)
@@ -39,9 +39,10 @@ def _make(ader, dim, M, n0, r, L, Us, bc="periodic", flags=None, lo=0.0, hi=1.0,
                       hi=(hi,) * 3, bc=tuple(ader.BC_PERIODIC if bc == "periodic"
                                              else ader.BC_TRANSMISSIVE for _ in range(3)),
                       precision=precision, picard_tol=tol, cfl=cfl)
-    H = Hierarchy(op, r, L, Us, flags=flags, indicator_var=indicator_var, chi_ref=chi_ref)
+    H = Hierarchy(op, r, L, Us, flags=flags, indicator_var=indicator_var, chi_ref=chi_ref,
+                  chi_rec=chi_rec)
     A = ader.Amr(gp, r=r, max_level=L, indicator_var=indicator_var, chi_ref=chi_ref,
-                 use_graph=use_graph)
+                 use_graph=use_graph, chi_rec=chi_rec)
     for l in range(L + 1):
         A.set_level(l, Us[l])
     if flags is not None:

@@ -1,0 +1,169 @@
+"""Dynamic refinement and recoarsening on the device (ader_amr_regrid)
+against the oracle's regrid (oracle/amr.py): bit-exact status arrays, the
+averages of every existing cell within 1e-11 pooled relative L1, steps after
+a regrid, conservation across regrids, 3D, and a recorded step graph that is
+recorded again after the mesh changes."""
+import copy
+
+import numpy as np
+import pytest
+
+from oracle.amr import (ACTIVE, ABSENT, VCHILD, VMOTHER, amr_step, average_down,
+                        children_from_mothers, lohner, regrid)
+from paper_1212_3585_amd import workloads as wl
+
+from gpu_helpers import say
+from test_gpu_amr import _levels_from_fine, _make, _patch_flags
+
+pytestmark = pytest.mark.gpu
+
+
+def _compare_all(H, A, tol=1e-11):
+    """Status bit-exact; averages of all non-absent cells (active, virtual
+    children, virtual mothers) within tol pooled relative L1."""
+    num = den = 0.0
+    for l in range(H.L + 1):
+        U, st = A.level(l)
+        assert np.array_equal(st, H.status[l]), f"level {l} status differs"
+        ex = st != ABSENT
+        assert np.isnan(U[:, ~ex]).all()
+        num += np.abs(U[:, ex] - H.U[l][:, ex]).sum()
+        den += np.abs(H.U[l][:, ex]).sum()
+    err = num / den
+    assert err <= tol, err
+    return err
+
+
+def _indicator_margin(H):
+    """Smallest relative distance of an indicator value to the threshold that
+    decides it (the decisions are only comparable across rounding when this
+    is far above the rounding level)."""
+    G = copy.deepcopy(H)
+    average_down(G, 0)
+    for l in range(1, G.L + 1):
+        children_from_mothers(G, l, G.status[l] == VCHILD)
+    m = np.inf
+    for l in range(G.L):
+        with np.errstate(invalid="ignore"):
+            chi = lohner(G.U[l][G.indicator_var], G.bcs, G.eps)
+        a, v = G.status[l] == ACTIVE, G.status[l] == VMOTHER
+        if a.any():
+            m = min(m, np.min(np.abs(chi[a] - G.chi_ref)) / G.chi_ref)
+        if v.any():
+            m = min(m, np.min(np.abs(chi[v] - G.chi_rec)) / G.chi_rec)
+    return m
+
+
+def test_regrid_given_flags_parity(ader):
+    say("AMR regrid with given flags: 2D 6^2 r=3 L=2 M=2, grow and shrink, steps after")
+    n0, r = 6, 3
+    Us = _levels_from_fine(wl.perturbed_smooth_euler((n0 * 9, n0 * 9), 5), r, 2)
+    H, A = _make(ader, 2, 2, n0, r, 2, Us, flags=_patch_flags(n0, r))
+    amr_step(H, 0.0, 1.0)
+    A.step(1.0)
+    G0 = np.zeros((n0, n0), bool)
+    G0[1:4, 2:5] = True                   # grows level 1 ...
+    G1 = np.zeros((n0 * r, n0 * r), bool)
+    G1[10:12, 7:9] = True                 # ... and moves the level-2 patch
+    for l, f in enumerate((G0, G1)):
+        A.set_flags(l, f)
+    assert regrid(H, flags=[G0, G1])
+    assert A.regrid()
+    _compare_all(H, A)
+    for _ in range(2):
+        amr_step(H, 0.0, 1.0)
+        A.step(1.0)
+    _compare_all(H, A)
+    S0 = np.zeros((n0, n0), bool)
+    S0[2:4, 3:5] = True                   # shrinks level 1, drops level 2
+    S1 = np.zeros((n0 * r, n0 * r), bool)
+    for l, f in enumerate((S0, S1)):
+        A.set_flags(l, f)
+    assert regrid(H, flags=[S0, S1])
+    assert A.regrid()
+    _compare_all(H, A)
+    amr_step(H, 0.0, 1.0)
+    A.step(1.0)
+    _compare_all(H, A)
+    assert A.stats()["flags"] == 0
+
+
+def test_regrid_indicator_explosion(ader):
+    say("AMR regrid by indicator: explosion 16^2 r=3 L=2 M=2, chi 0.2 / 0.1, 3 steps")
+    n0, r = 16, 3
+    Us = [wl.explosion_2d(n0 * r ** l, seed=2) for l in range(3)]
+    H, A = _make(ader, 2, 2, n0, r, 2, Us, bc="transmissive", lo=-1.0, hi=1.0,
+                 indicator_var=3, cfl=0.5, chi_rec=0.1)
+    changed = 0
+    for _ in range(3):
+        amr_step(H, 0.0, 1.0)
+        A.step(1.0)
+        assert _indicator_margin(H) > 1e-8
+        ch = regrid(H)
+        assert A.regrid() == ch
+        changed += ch
+        _compare_all(H, A)
+    assert changed >= 1
+
+
+def test_regrid_conserves_on_the_device(ader):
+    say("AMR regrid conservation: explosion 8^2 r=3 L=2 periodic, 3 steps + regrids")
+    n0, r = 8, 3
+    Us = [wl.explosion_2d(n0 * r ** l, seed=2) for l in range(3)]
+    H, A = _make(ader, 2, 2, n0, r, 2, Us, lo=-1.0, hi=1.0, indicator_var=3, cfl=0.5,
+                 chi_rec=0.1)
+
+    def total():
+        tot = 0.0
+        for l in range(3):
+            U, st = A.level(l)
+            tot = tot + np.prod(H.dx(l)) * U[:, st == 0].sum(axis=1)
+        return tot
+    tot0 = total()
+    for _ in range(3):
+        A.step(1.0)
+        before = total()
+        A.regrid()
+        np.testing.assert_allclose(total(), before, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(total(), tot0, rtol=1e-12, atol=1e-13)
+
+
+def test_regrid_3d_parity(ader):
+    say("AMR regrid 3D 4^3 r=2 L=1 M=2 with given flags, one step after")
+    n0, r = 4, 2
+    Us = _levels_from_fine(wl.perturbed_smooth_euler((n0 * r,) * 3, 8), r, 1)
+    F0 = np.zeros((n0,) * 3, bool)
+    F0[1, 1, 1] = True
+    H, A = _make(ader, 3, 2, n0, r, 1, Us, flags=[F0])
+    amr_step(H, 0.0, 1.0)
+    A.step(1.0)
+    G0 = np.zeros((n0,) * 3, bool)
+    G0[1:3, 1, 2] = True
+    A.set_flags(0, G0)
+    assert regrid(H, flags=[G0])
+    assert A.regrid()
+    _compare_all(H, A)
+    amr_step(H, 0.0, 1.0)
+    A.step(1.0)
+    _compare_all(H, A)
+
+
+def test_regrid_graph_recorded_again(ader):
+    say("AMR regrid: graph replay after a regrid equals direct launches")
+    n0, r = 6, 3
+    Us = _levels_from_fine(wl.perturbed_smooth_euler((n0 * 9, n0 * 9), 11), r, 2)
+    out = []
+    for use_graph in (True, False):
+        H, A = _make(ader, 2, 2, n0, r, 2, Us, flags=_patch_flags(n0, r), use_graph=use_graph)
+        A.step(1.0)
+        G0 = np.zeros((n0, n0), bool)
+        G0[3:5, 1:3] = True
+        A.set_flags(0, G0)
+        A.set_flags(1, np.zeros((n0 * r, n0 * r), bool))
+        assert A.regrid()
+        for _ in range(2):
+            A.step(1.0)
+        out.append([A.level(l) for l in range(3)])
+    for (Ua, sa), (Ub, sb) in zip(*out):
+        assert np.array_equal(sa, sb)
+        assert np.array_equal(np.nan_to_num(Ua, nan=7.0), np.nan_to_num(Ub, nan=7.0))
