@@ -187,17 +187,19 @@ def serve(ader, reqs, arrivals, hbm_bytes):
             "peak_bytes": st["peak_bytes_in_use"], "rounds": st["rounds"]}
 
 
-def amr_leg(ader, label, dim, n0, r, L, M, ic, precision, steps, cfl=0.5):
+def amr_leg(ader, label, dim, n0, r, L, M, ic, precision, steps, cfl=0.5, regrid_steps=0):
     """One AMR configuration: mesh built by the Loehner indicator on the
     energy (the density noise does not enter it), one-layer flag buffer,
     local time stepping, one recorded graph per level-0 step.  Rate =
-    active-cell substeps per second over 'steps' level-0 steps."""
+    active-cell substeps per second over 'steps' level-0 steps on the static
+    mesh; then 'regrid_steps' steps each followed by a regrid (refine above
+    chi 0.2, recoarsen below 0.1), regrid time included in that rate."""
     tol = 1e-14 if precision == ader.PREC_FP64 else 1e-6
     prob = ader.Problem(dim=dim, M=M, n=(n0,) * dim + (1,) * (3 - dim), lo=(-1.0,) * 3,
                         hi=(1.0,) * 3, bc=(ader.BC_TRANSMISSIVE,) * 3, cfl=cfl,
                         precision=precision, picard_tol=tol)
-    A = ader.Amr(prob, r=r, max_level=L, indicator_var=dim + 1, chi_ref=0.2, eps=0.01,
-                 buffer=1, use_graph=True)
+    A = ader.Amr(prob, r=r, max_level=L, indicator_var=dim + 1, chi_ref=0.2, chi_rec=0.1,
+                 eps=0.01, buffer=1, use_graph=True)
     for l in range(L + 1):
         A.set_level(l, ic(n0 * r ** l, l))
     t0 = time.perf_counter()
@@ -214,12 +216,32 @@ def amr_leg(ader, label, dim, n0, r, L, M, ic, precision, steps, cfl=0.5):
     el = time.perf_counter() - t0
     st = A.stats()
     cu = st["cell_updates"] - cu0
+    out = {"workload": label, "precision": "fp64" if precision == ader.PREC_FP64 else
+           "fp32 predictor / fp64", "levels": counts, "mesh_build_s": build_s,
+           "level0_steps": steps, "cell_updates": cu, "seconds": el,
+           "cell_updates_per_s": cu / el, "ms_per_level0_step": el / steps * 1e3,
+           "t_reached": t_sim, "status_flags": st["flags"]}
+    if regrid_steps > 0:
+        cu0 = st["cell_updates"]
+        t_regrid, changed = 0.0, 0
+        t0 = time.perf_counter()
+        for _ in range(regrid_steps):
+            A.step(1e9)
+            A.clock()
+            t1 = time.perf_counter()
+            changed += A.regrid()
+            t_regrid += time.perf_counter() - t1
+        A.clock()
+        el = time.perf_counter() - t0
+        st = A.stats()
+        cu = st["cell_updates"] - cu0
+        out["with_regrid"] = {
+            "level0_steps": regrid_steps, "regrids_that_changed_the_mesh": changed,
+            "cell_updates": cu, "seconds": el, "cell_updates_per_s": cu / el,
+            "regrid_ms_avg": t_regrid / regrid_steps * 1e3,
+            "levels_after": [A.counts(l) for l in range(L + 1)], "status_flags": st["flags"]}
     A.close()
-    return {"workload": label, "precision": "fp64" if precision == ader.PREC_FP64 else
-            "fp32 predictor / fp64", "levels": counts, "mesh_build_s": build_s,
-            "level0_steps": steps, "cell_updates": cu, "seconds": el,
-            "cell_updates_per_s": cu / el, "ms_per_level0_step": el / steps * 1e3,
-            "t_reached": t_sim, "status_flags": st["flags"]}
+    return out
 
 
 def amr_legs(ader, wl):
@@ -234,12 +256,12 @@ def amr_legs(ader, wl):
         out.append(amr_leg(ader, "2D Euler explosion (rho, p) = (1, 1) inside r = 0.5, "
                            "(0.125, 0.1) outside, 1% density noise (seed 2), [-1,1]^2, "
                            "level 0 100^2, r = 3, 2 levels, M = 2",
-                           2, 100, 3, 2, 2, expl, prec, steps=10))
+                           2, 100, 3, 2, 2, expl, prec, steps=10, regrid_steps=10))
     for prec in (ader.PREC_FP64, ader.PREC_FP32_PREDICTOR):
         log(f"bench: AMR 3D blast, precision {prec}")
         out.append(amr_leg(ader, "3D Euler blast p = 1 inside r = 0.3, 0.1 outside, rho = 1 "
                            "with 1% noise (seed 3), [-1,1]^3, level 0 64^3, r = 3, 1 level, "
-                           "M = 2", 3, 64, 3, 1, 2, blast, prec, steps=2))
+                           "M = 2", 3, 64, 3, 1, 2, blast, prec, steps=2, regrid_steps=2))
     return out
 
 

@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -40,6 +41,31 @@
 
 using ader::fail;
 using ader::hip_status;
+
+// Device buffer with a capacity; grows (never shrinks) on demand.
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= cap && p) return hipSuccess;
+    if (p) {
+      hipError_t e = hipDeviceSynchronize();
+      if (e == hipSuccess) e = hipFree(p);
+      p = nullptr;
+      cap = 0;
+      if (e != hipSuccess) return e;
+    }
+    const size_t want = bytes + bytes / 4 + 256;
+    hipError_t e = hipMalloc(&p, want);
+    if (e == hipSuccess) cap = want;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
 
 struct ader_amr_s {
   ader_problem prob{};
@@ -53,7 +79,10 @@ struct ader_amr_s {
   std::vector<std::vector<uint8_t>> h_flags;
   std::vector<std::vector<int8_t>> h_status;
   std::vector<void*> dev_allocs;
-  std::vector<std::vector<void*>> lvl_bufs;  // per-level lists and scratch (replaced by a regrid)
+  // per-level lists and scratch (act, vc, vm, wa, wh, qh), grown by a regrid;
+  // temporaries of the regrid's children passes
+  std::vector<std::array<DevBuf, 6>> lvl_bufs;
+  std::array<DevBuf, 5> tmp;
   double* partial = nullptr;
   ader::AmrClock* clock = nullptr;
   ader::AmrClock* h_clock = nullptr;  // pinned staging
@@ -177,15 +206,25 @@ std::vector<uint8_t> mothers(const Grid& fine, const Grid& coarse, const std::ve
   return out;
 }
 
+// Calls fn(fine index) for the r^d children of coarse cell c.
+template <typename Fn>
+void for_children(const Grid& coarse, const Grid& fine, int64_t c, int r, Fn fn) {
+  int cc[3];
+  coarse.coords(c, cc);
+  const int rz = fine.d > 2 ? r : 1, ry = fine.d > 1 ? r : 1;
+  for (int z = 0; z < rz; ++z)
+    for (int y = 0; y < ry; ++y) {
+      const int f[3] = {cc[0] * r, cc[1] * ry + y, cc[2] * rz + z};
+      const int64_t row = fine.idx(f);
+      for (int x = 0; x < r; ++x) fn(row + x);
+    }
+}
+
 std::vector<uint8_t> children(const Grid& coarse, const Grid& fine, const std::vector<uint8_t>& F,
                               int r) {
   std::vector<uint8_t> out(fine.cells(), 0);
-  for (int64_t i = 0; i < fine.cells(); ++i) {
-    int c[3];
-    fine.coords(i, c);
-    for (int k = 0; k < fine.d; ++k) c[k] /= r;
-    out[i] = F[coarse.idx(c)];
-  }
+  for (int64_t c = 0; c < coarse.cells(); ++c)
+    if (F[c]) for_children(coarse, fine, c, r, [&](int64_t i) { out[i] = 1; });
   return out;
 }
 
@@ -205,7 +244,10 @@ void close_flags(const std::vector<Grid>& g, Flags& F, const int* bc, int r, int
   }
 }
 
-// Status of every level from closed flags.
+// Status of every level from closed flags: children of flagged cells are
+// active (virtual mothers if flagged themselves), children of the unflagged
+// Voronoi neighbours of flagged cells are virtual children, the rest of
+// levels >= 1 is absent.  Written block by block over the coarser level.
 Status status_from_flags(const std::vector<Grid>& g, const Flags& F, const int* bc, int r,
                          int L) {
   Status S(L + 1);
@@ -214,15 +256,22 @@ Status status_from_flags(const std::vector<Grid>& g, const Flags& F, const int* 
     for (int64_t i = 0; i < g[0].cells(); ++i)
       if (F[0][i]) S[0][i] = ader::kVMother;
   for (int l = 1; l <= L; ++l) {
-    std::vector<uint8_t> near = dilate(g[l - 1], F[l - 1], bc);
-    for (size_t i = 0; i < near.size(); ++i) near[i] = near[i] && !F[l - 1][i];
-    std::vector<uint8_t> vch = children(g[l - 1], g[l], near, r);
-    std::vector<uint8_t> kids = children(g[l - 1], g[l], F[l - 1], r);
+    const std::vector<uint8_t> near = dilate(g[l - 1], F[l - 1], bc);
+    const std::vector<uint8_t>& fl = F[l - 1];
     std::vector<int8_t>& s = S[l];
     s.assign(g[l].cells(), ader::kAbsent);
-    for (int64_t i = 0; i < g[l].cells(); ++i) {
-      if (vch[i]) s[i] = ader::kVChild;
-      if (kids[i]) s[i] = (l < L && F[l][i]) ? ader::kVMother : ader::kActive;
+    for (int64_t c = 0; c < g[l - 1].cells(); ++c) {
+      if (fl[c]) {
+        if (l < L) {
+          const std::vector<uint8_t>& ff = F[l];
+          for_children(g[l - 1], g[l], c, r,
+                       [&](int64_t i) { s[i] = ff[i] ? ader::kVMother : ader::kActive; });
+        } else {
+          for_children(g[l - 1], g[l], c, r, [&](int64_t i) { s[i] = ader::kActive; });
+        }
+      } else if (near[c]) {
+        for_children(g[l - 1], g[l], c, r, [&](int64_t i) { s[i] = ader::kVChild; });
+      }
     }
   }
   return S;
@@ -274,19 +323,13 @@ ader_status upload(ader_amr a, T** dst, const void* src, size_t bytes) {
   return ADER_OK;
 }
 
-// Device buffer owned by level l's list set (freed when the lists change).
+// Copy 'bytes' from host 'src' (may be null) into a grown buffer.
 template <typename T>
-ader_status upload_lvl(ader_amr a, int l, T** dst, const void* src, size_t bytes) {
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes > 0 ? bytes : 256);
-  if (e != hipSuccess) return hip_status(e, "AMR level lists (allocation)");
-  a->lvl_bufs[l].push_back(p);
-  if (src && bytes) {
-    e = hipMemcpy(p, src, bytes, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_status(e, "AMR level lists (upload)");
-  }
-  *dst = static_cast<T*>(p);
-  return ADER_OK;
+hipError_t fill_buf(DevBuf& b, T** dst, const void* src, size_t bytes) {
+  hipError_t e = b.ensure(bytes);
+  if (e == hipSuccess && src && bytes) e = hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice);
+  *dst = static_cast<T*>(b.p);
+  return e;
 }
 
 // Lists, positions and scratch of level l from a->h_status[l]; the dense
@@ -307,29 +350,24 @@ ader_status set_level_lists(ader_amr a, int l) {
       vm.push_back((int32_t)i);
     }
   }
-  hipError_t e = hipDeviceSynchronize();
-  for (void* p : a->lvl_bufs[l])
-    if (e == hipSuccess) e = hipFree(p);
-  a->lvl_bufs[l].clear();
-  if (e == hipSuccess) e = hipMemcpy(v.st, s.data(), N, hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpy(v.st, s.data(), N, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(v.pos, pos.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_status(e, "AMR level lists");
   v.nact = (int64_t)act.size();
   v.nvc = (int64_t)vc.size();
   v.nvm = (int64_t)vm.size();
-  ader_status st = ADER_OK;
-  if (!st) st = upload_lvl(a, l, &v.act, act.data(), sizeof(int32_t) * act.size());
-  if (!st) st = upload_lvl(a, l, &v.vc, vc.data(), sizeof(int32_t) * vc.size());
-  if (!st) st = upload_lvl(a, l, &v.vm, vm.data(), sizeof(int32_t) * vm.size());
+  std::array<DevBuf, 6>& B = a->lvl_bufs[l];
   const size_t na = (size_t)v.nact;
-  if (!st)
-    st = upload_lvl(a, l, &v.wa, nullptr, sizeof(double) * a->impl->weno_scratch_per_cell() * na);
-  v.wb = v.wa ? v.wa + (size_t)a->nv * (M + 1) * ipow(2 * M + 1, d - 1) * na : nullptr;
-  if (!st) st = upload_lvl(a, l, &v.wh, nullptr, sizeof(double) * a->impl->wh_per_cell() * na);
-  if (!st)
-    st = upload_lvl(a, l, &v.qh, nullptr,
-                    a->impl->qh_elem_size() * a->nv * ipow(M + 1, d + 1) * na);
-  if (st) return st;
+  if (e == hipSuccess) e = fill_buf(B[0], &v.act, act.data(), sizeof(int32_t) * act.size());
+  if (e == hipSuccess) e = fill_buf(B[1], &v.vc, vc.data(), sizeof(int32_t) * vc.size());
+  if (e == hipSuccess) e = fill_buf(B[2], &v.vm, vm.data(), sizeof(int32_t) * vm.size());
+  if (e == hipSuccess)
+    e = fill_buf(B[3], &v.wa, nullptr, sizeof(double) * a->impl->weno_scratch_per_cell() * na);
+  if (e == hipSuccess)
+    e = fill_buf(B[4], &v.wh, nullptr, sizeof(double) * a->impl->wh_per_cell() * na);
+  if (e == hipSuccess)
+    e = fill_buf(B[5], &v.qh, nullptr, a->impl->qh_elem_size() * a->nv * ipow(M + 1, d + 1) * na);
+  if (e != hipSuccess) return hip_status(e, "AMR level lists");
+  v.wb = v.wa + (size_t)a->nv * (M + 1) * ipow(2 * M + 1, d - 1) * na;
   a->dtargs.nb[l] = v.nact == 0 ? 0
                     : (int)std::min<int64_t>((v.nact + ader::kBlock - 1) / ader::kBlock,
                                              ader::kDtMaxBlocks);
@@ -359,27 +397,20 @@ ader_status children_pass(ader_amr a, int l, const std::vector<int32_t>& targets
     slot[i] = (int32_t)(std::lower_bound(uniq.begin(), uniq.end(), moth[i]) - uniq.begin());
   const size_t nm = uniq.size(), nt = targets.size();
   const size_t wa_n = a->impl->weno_scratch_per_cell() * nm, wh_n = a->impl->wh_per_cell() * nm;
-  void* buf[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  const size_t bytes[5] = {sizeof(int32_t) * nm, sizeof(int32_t) * nt, sizeof(int32_t) * nt,
-                           sizeof(double) * wa_n, sizeof(double) * wh_n};
-  const void* src[5] = {uniq.data(), targets.data(), slot.data(), nullptr, nullptr};
-  hipError_t e = hipSuccess;
-  for (int i = 0; i < 5 && e == hipSuccess; ++i) {
-    e = hipMalloc(&buf[i], bytes[i]);
-    if (e == hipSuccess && src[i]) e = hipMemcpy(buf[i], src[i], bytes[i], hipMemcpyHostToDevice);
-  }
+  int32_t *d_moth = nullptr, *d_targets = nullptr, *d_slot = nullptr;
+  double *wa = nullptr, *wh = nullptr;
+  hipError_t e = fill_buf(a->tmp[0], &d_moth, uniq.data(), sizeof(int32_t) * nm);
+  if (e == hipSuccess) e = fill_buf(a->tmp[1], &d_targets, targets.data(), sizeof(int32_t) * nt);
+  if (e == hipSuccess) e = fill_buf(a->tmp[2], &d_slot, slot.data(), sizeof(int32_t) * nt);
+  if (e == hipSuccess) e = fill_buf(a->tmp[3], &wa, nullptr, sizeof(double) * wa_n);
+  if (e == hipSuccess) e = fill_buf(a->tmp[4], &wh, nullptr, sizeof(double) * wh_n);
   if (e == hipSuccess) {
-    double* wa = static_cast<double*>(buf[3]);
     double* wb = wa + (size_t)a->nv * (a->M + 1) * ipow(2 * a->M + 1, a->d - 1) * nm;
-    e = a->impl->children(a->lv[l - 1], static_cast<const int32_t*>(buf[0]), (int64_t)nm, wa, wb,
-                          static_cast<double*>(buf[4]), a->lv[l],
-                          static_cast<const int32_t*>(buf[1]), static_cast<const int32_t*>(buf[2]),
-                          (int64_t)nt, a->dc, a->ac, a->stream);
+    e = a->impl->children(a->lv[l - 1], d_moth, (int64_t)nm, wa, wb, wh, a->lv[l], d_targets,
+                          d_slot, (int64_t)nt, a->dc, a->ac, a->stream);
   }
   const hipError_t es = hipStreamSynchronize(a->stream);
   if (e == hipSuccess) e = es;
-  for (void* p : buf)
-    if (p) (void)hipFree(p);
   return hip_status(e, "ader_amr_regrid");
 }
 
@@ -491,7 +522,8 @@ ader_status ader_amr_destroy(ader_amr a) {
   if (a->exec) (void)hipGraphExecDestroy(a->exec);
   for (void* p : a->dev_allocs) (void)hipFree(p);
   for (auto& v : a->lvl_bufs)
-    for (void* p : v) (void)hipFree(p);
+    for (DevBuf& b : v) b.release();
+  for (DevBuf& b : a->tmp) b.release();
   if (a->h_clock) (void)hipHostFree(a->h_clock);
   if (a->stream) (void)hipStreamDestroy(a->stream);
   delete a;
@@ -557,7 +589,7 @@ ader_status ader_amr_build(ader_amr a) {
   const double dx0[3] = {(a->prob.hi[0] - a->prob.lo[0]) / a->prob.n[0],
                          (a->prob.hi[1] - a->prob.lo[1]) / a->prob.n[1],
                          d > 2 ? (a->prob.hi[2] - a->prob.lo[2]) / a->prob.n[2] : 1.0};
-  a->lvl_bufs.assign(L + 1, {});
+  a->lvl_bufs.resize(L + 1);
   for (int l = 0; l <= L; ++l) {
     ader::AmrLevel& v = a->lv[l];
     const int64_t N = v.ncells;
@@ -678,9 +710,10 @@ ader_status ader_amr_regrid(ader_amr a, int* changed) {
   }
   for (auto& f : a->h_flags) f.clear();
   close_flags(g, F, bc, r, L);
+  // (the stencil check of the build holds by construction here: an active
+  // cell's stencil, M <= r cells wide, lies in the children of its mother's
+  // Voronoi neighbours, which are flagged or near-flagged)
   Status S = status_from_flags(g, F, bc, r, L);
-  if (!stencils_in_mesh(g, S, bc, a->M))
-    return fail(ADER_EINVAL, "an active cell's stencil would leave the mesh");
   if (S == a->h_status) return ADER_OK;
   // 3. new lists; new cells from their mothers, coarse to fine; removed cells NaN
   Status old = std::move(a->h_status);
@@ -697,15 +730,12 @@ ader_status ader_amr_regrid(ader_amr a, int* changed) {
     if (ader_status st = children_pass(a, l, born)) return st;
     if (!gone.empty()) {
       int32_t* dl = nullptr;
-      e = hipMalloc(&dl, sizeof(int32_t) * gone.size());
-      if (e == hipSuccess)
-        e = hipMemcpy(dl, gone.data(), sizeof(int32_t) * gone.size(), hipMemcpyHostToDevice);
+      e = fill_buf(a->tmp[0], &dl, gone.data(), sizeof(int32_t) * gone.size());
       if (e == hipSuccess)
         e = ader::launch_fill_list(a->lv[l].u, a->lv[l].ncells, a->nv, dl,
                                    (int64_t)gone.size(), std::nan(""), a->stream);
       const hipError_t es = hipStreamSynchronize(a->stream);
       if (e == hipSuccess) e = es;
-      if (dl) (void)hipFree(dl);
       if (e != hipSuccess) return hip_status(e, "ader_amr_regrid");
     }
   }
