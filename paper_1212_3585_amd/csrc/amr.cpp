@@ -79,9 +79,9 @@ struct ader_amr_s {
   std::vector<std::vector<uint8_t>> h_flags;
   std::vector<std::vector<int8_t>> h_status;
   std::vector<void*> dev_allocs;
-  // per-level lists and scratch (act, vc, vm, wa, wh, qh), grown by a regrid;
+  // per-level lists and scratch (act, vc, vm, wa, wh, qh, fbuf), grown by a regrid;
   // temporaries of the regrid's children passes
-  std::vector<std::array<DevBuf, 6>> lvl_bufs;
+  std::vector<std::array<DevBuf, 7>> lvl_bufs;
   std::array<DevBuf, 5> tmp;
   double* partial = nullptr;
   ader::AmrClock* clock = nullptr;
@@ -355,7 +355,7 @@ ader_status set_level_lists(ader_amr a, int l) {
   v.nact = (int64_t)act.size();
   v.nvc = (int64_t)vc.size();
   v.nvm = (int64_t)vm.size();
-  std::array<DevBuf, 6>& B = a->lvl_bufs[l];
+  std::array<DevBuf, 7>& B = a->lvl_bufs[l];
   const size_t na = (size_t)v.nact;
   if (e == hipSuccess) e = fill_buf(B[0], &v.act, act.data(), sizeof(int32_t) * act.size());
   if (e == hipSuccess) e = fill_buf(B[1], &v.vc, vc.data(), sizeof(int32_t) * vc.size());
@@ -366,6 +366,8 @@ ader_status set_level_lists(ader_amr a, int l) {
     e = fill_buf(B[4], &v.wh, nullptr, sizeof(double) * a->impl->wh_per_cell() * na);
   if (e == hipSuccess)
     e = fill_buf(B[5], &v.qh, nullptr, a->impl->qh_elem_size() * a->nv * ipow(M + 1, d + 1) * na);
+  if (e == hipSuccess)
+    e = fill_buf(B[6], &v.fbuf, nullptr, sizeof(double) * a->impl->fbuf_per_cell() * na);
   if (e != hipSuccess) return hip_status(e, "AMR level lists");
   v.wb = v.wa + (size_t)a->nv * (M + 1) * ipow(2 * M + 1, d - 1) * na;
   a->dtargs.nb[l] = v.nact == 0 ? 0
@@ -423,8 +425,9 @@ ader_status record_advance(ader_amr a, int l, int sub, hipStream_t st) {
   if (e == hipSuccess) e = im->predict(a->lv[l], &a->clock->dt[l], a->dc, st);
   if (e != hipSuccess) return hip_status(e, "ader_amr_step");
   if (l < a->L) {
+    // the finer level's memory is read at its virtual children only
     const ader::AmrLevel& f = a->lv[l + 1];
-    e = ader::launch_fill(f.mem, (int64_t)a->d * 2 * a->nv * f.ncells, 0.0, st);
+    e = ader::launch_fill_list(f.mem, f.ncells, a->d * 2 * a->nv, f.vc, f.nvc, 0.0, st);
     if (e != hipSuccess) return hip_status(e, "ader_amr_step");
     for (int s = 0; s < a->r; ++s)
       if (ader_status stt = record_advance(a, l + 1, s, st)) return stt;

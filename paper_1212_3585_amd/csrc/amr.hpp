@@ -15,14 +15,19 @@
 //                   level-list kernels (level.hpp, predictor kernels)
 //   k_amr_subavg    a regrid's new (and virtual) children: the average of
 //                   the mother's reconstruction w_h over the child's sub-cell
-//   k_fill_list     one value into listed cells of every variable
-//   k_amr_update    finite-volume update of the active cells: same-level
+//   k_fill_list     one value into listed cells of every variable (the
+//                   memory of the virtual children before a level's substeps)
+//   k_amr_flux      face fluxes of the active cells, one group of lanes per
+//                   (cell, axis), one lane per space-time point of the face;
+//                   each face once (a cell's high faces, and its low faces
+//                   not shared with an active cell of the level): same-level
 //                   faces as on a uniform mesh; a face to a virtual child
 //                   (coarser neighbour) takes the coarse predictor at this
 //                   face's Gauss points and this substep's time nodes and
 //                   stores the flux in the virtual child's memory; a face to
 //                   a virtual mother (finer neighbour) averages the memory of
 //                   this cell's virtual children on that face (eq. memory.sum)
+//   k_amr_apply     conservative update of the active cells from those fluxes
 #pragma once
 
 #include "amr_plan.hpp"
@@ -154,13 +159,6 @@ k_amr_subavg(double* __restrict__ u, int64_t ld, const int32_t* __restrict__ tar
     acc_z += DIM > 2 ? ac.sub_avg[cc[2] % r][pz] * acc_y : acc_y;
   }
   u[(int64_t)v * ld + targets[i]] = acc_z;
-}
-
-template <int TAG>
-__global__ void k_fill(double* __restrict__ p, int64_t n, double value) {
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kBlock)
-    p[i] = value;
 }
 
 template <int DIM, int NV>
@@ -307,13 +305,183 @@ struct AmrUpdArgs {
   int r;
 };
 
+// Shape of the face-flux kernel: a group of G lanes per (cell, axis k); lane
+// g < NPT of a group owns space-time point (s = g / NT, tb = g % NT) of the
+// face.  CPB cells per block.
+template <int DIM, int M>
+struct AmrFluxShape {
+  static constexpr int n = M + 1;
+  static constexpr int NT = Pow<n, DIM - 1>::v;  // transverse nodes of a face
+  static constexpr int NPT = n * NT;              // space-time points of a face
+  static constexpr int G = NPT <= 4 ? 4 : (NPT <= 8 ? 8 : (NPT <= 16 ? 16 : (NPT <= 32 ? 32 : 64)));
+  static constexpr int LPC = DIM * G;             // lanes per cell
+  static constexpr int CPB = LPC >= 256 ? 1 : 256 / LPC;
+  static constexpr int BLOCK = CPB * LPC;
+};
+
+// Kind of the face of active cell cc on (axis k, side): 0 an active cell of
+// the same level (its list position in *pn), 1 outflow through a
+// transmissive boundary, 2 a virtual child (the coarse mother's list
+// position in *pn, the child's offsets in off), 3 a virtual mother (finer
+// neighbour), -1 no flux (an index outside the lists: flagged).
+template <int DIM>
+__device__ __forceinline__ int amr_face_kind(const AmrUpdArgs& a, const MeshParams& mp,
+                                             const int (&cc)[3], int k, int side, int64_t* nb,
+                                             int32_t* pn, int (&off)[3]) {
+  const int raw = cc[k] + (side ? 1 : -1);
+  if ((raw < 0 || raw >= mp.n[k]) && mp.bc[k] != 0) return 1;
+  int nbc[3] = {cc[0], cc[1], cc[2]};
+  nbc[k] = bc_map(raw, mp.n[k], mp.bc[k]);
+  *nb = dense_index<DIM>(nbc, mp.n);
+  const int8_t s = a.st[*nb];
+  if (s == kActive) {
+    *pn = a.pos[*nb];
+    return *pn >= 0 ? 0 : -1;
+  }
+  if (s == kVChild && a.pos_c) {
+    int m[3];
+    for (int ax = 0; ax < 3; ++ax) {
+      m[ax] = nbc[ax] / a.r;
+      off[ax] = nbc[ax] % a.r;
+    }
+    *pn = a.pos_c[dense_index<DIM>(m, a.nc)];
+    return *pn >= 0 ? 2 : -1;
+  }
+  if (s == kVMother && a.mem_f) return 3;
+  return -1;
+}
+
+// Face fluxes of the active cells: each cell computes its high face on every
+// axis, and its low face where the low neighbour is not an active cell of
+// the same level (that face is the neighbour's high face), so every face is
+// evaluated once.  Face-averaged fluxes go to
+// fbuf[(i * 2 DIM + 2 k + side) * NV + v].  A face to a virtual child also
+// adds its flux to the child's memory.
 template <int DIM, int M, int SYS, typename R>
-__global__ void __launch_bounds__(kBlock)
-k_amr_update(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, WsHeader* hdr) {
+__global__ void __launch_bounds__((AmrFluxShape<DIM, M>::BLOCK))
+k_amr_flux(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, double* __restrict__ fbuf,
+           WsHeader* hdr) {
+  using Sh = AmrFluxShape<DIM, M>;
   constexpr int n = M + 1;
   constexpr int NV = NVars<SYS, DIM>::v;
   constexpr int NST = Pow<n, DIM + 1>::v;
-  constexpr int NT = Pow<n, DIM - 1>::v;  // transverse nodes of a face
+  constexpr int NT = Sh::NT;
+  constexpr int G = Sh::G;
+  constexpr int FS = 2 * DIM;
+  const int tid = threadIdx.x;
+  const int cs = tid / Sh::LPC;
+  const int k = (tid % Sh::LPC) / G;
+  const int g = tid % G;
+  const int64_t i = (int64_t)blockIdx.x * Sh::CPB + cs;
+  const bool valid = i < a.nact;
+  unsigned int flags = 0;
+  int cc[3] = {0, 0, 0};
+  if (valid) dense_coords<DIM>(a.act[i], mp.n, cc);
+  const R* qme = static_cast<const R*>(a.qh) + (valid ? i : 0) * NV * NST;
+  for (int side = 1; side >= 0; --side) {
+    int64_t nb = 0;
+    int32_t pn = -1;
+    int off[3] = {0, 0, 0};
+    const int type = valid ? amr_face_kind<DIM>(a, mp, cc, k, side, &nb, &pn, off) : -2;
+    if (side == 0 && (type == 0 || type == -2)) continue;  // uniform in the group
+    if (type == -1) flags |= kFlagBadIndex;
+    double F[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = 0.0;
+    if (type == 3) {
+      // this lane's share of the memory of the cell's virtual children on the face
+      const int nsub = DIM == 2 ? a.r : a.r * a.r;
+      for (int j = g; j < nsub; j += G) {
+        int ch[3] = {0, 0, 0};
+        int t = 0;
+        for (int ax = 0; ax < DIM; ++ax) {
+          if (ax == k) {
+            ch[ax] = cc[ax] * a.r + (side ? a.r - 1 : 0);
+          } else {
+            const int aj = DIM == 2 ? j : (t == 0 ? j / a.r : j % a.r);
+            ch[ax] = cc[ax] * a.r + aj;
+            ++t;
+          }
+        }
+        const int64_t chd = dense_index<DIM>(ch, a.nf);
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          F[v] += a.mem_f[((int64_t)(k * 2 + side) * NV + v) * a.ldf + chd];
+      }
+    } else if (type >= 0 && g < Sh::NPT) {
+      const int s = g / NT, tb = g % NT;
+      double qm[NV], qp[NV];
+      cell_trace<DIM, M, NV, R>(qme, k, side, tb, s, c, qm);
+      if (type == 0) {
+        cell_trace<DIM, M, NV, R>(static_cast<const R*>(a.qh) + (int64_t)pn * NV * NST, k,
+                                  1 - side, tb, s, c, qp);
+      } else if (type == 1) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) qp[v] = qm[v];
+      } else {
+        // coarse predictor at this face point and time node
+        const int tt[2] = {tb % n, tb / n};
+        double wt[4], wax[3][4];
+        int ti = 0;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) wt[p] = p < n ? ac.at_nodes[a.sub][s][p] : 0.0;
+        for (int ax = 0; ax < 3; ++ax) {
+          for (int p = 0; p < 4; ++p) {
+            double w = 0.0;
+            if (p < n && ax < DIM)
+              w = ax == k ? ac.at_face[off[ax]][1 - side][p] : ac.at_nodes[off[ax]][tt[ti]][p];
+            wax[ax][p] = w;
+          }
+          if (ax < DIM && ax != k) ++ti;
+        }
+        eval_predictor<DIM, M, NV, R>(static_cast<const R*>(a.qh_c) + (int64_t)pn * NV * NST, wt,
+                                      wax, qp);
+      }
+      double Fpt[NV];
+      if (side)
+        numerical_flux<SYS, DIM>(qm, qp, k, mp, c, Fpt);
+      else
+        numerical_flux<SYS, DIM>(qp, qm, k, mp, c, Fpt);
+      double wtp = c.w[s];
+      {
+        const int tt[2] = {tb % n, tb / n};
+        for (int dd = 0; dd < DIM - 1; ++dd) wtp *= c.w[tt[dd]];
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) F[v] = wtp * Fpt[v];
+    }
+    // group sum by a fixed butterfly (the group takes one path: no divergence)
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) F[v] += __shfl_xor(F[v], o, 64);
+    if (g == 0 && type >= 0) {
+      if (type == 3) {
+        const double inv = 1.0 / (DIM == 2 ? (double)(a.r * a.r) : (double)(a.r * a.r * a.r));
+#pragma unroll
+        for (int v = 0; v < NV; ++v) F[v] *= inv;
+      }
+      double* fo = fbuf + (i * FS + 2 * k + side) * NV;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) fo[v] = F[v];
+      if (type == 2) {  // the face flux also goes to the coarse cell's memory
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          a.mem[((int64_t)(k * 2 + (1 - side)) * NV + v) * mp.ld + nb] += F[v];
+      }
+    }
+  }
+  block_report(0u, flags, hdr);
+}
+
+// Conservative update of the active cells (eq. finite_vol) from the face
+// fluxes of k_amr_flux: the low face on axis k is the low neighbour's high
+// face when that neighbour is an active cell of the same level.
+template <int DIM, int SYS>
+__global__ void __launch_bounds__(kBlock)
+k_amr_apply(AmrUpdArgs a, MeshParams mp, const double* __restrict__ fbuf, WsHeader* hdr) {
+  constexpr int NV = NVars<SYS, DIM>::v;
+  constexpr int FS = 2 * DIM;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   unsigned int flags = 0;
   if (i < a.nact) {
@@ -321,133 +489,23 @@ k_amr_update(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, WsHeader* h
     const int64_t cell = a.act[i];
     int cc[3];
     dense_coords<DIM>(cell, mp.n, cc);
-    const R* qme = static_cast<const R*>(a.qh) + i * NV * NST;
     const double dt = *a.dt;
     double q[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) q[v] = a.u[v * ld + cell];
+#pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      double F[2][NV];
-      for (int side = 0; side < 2; ++side) {
+      int64_t nb = 0;
+      int32_t pn = -1;
+      int off[3];
+      const int type = amr_face_kind<DIM>(a, mp, cc, k, 0, &nb, &pn, off);
+      const double* fhi = fbuf + (i * FS + 2 * k + 1) * NV;
+      const double* flo = type == 0 ? fbuf + ((int64_t)pn * FS + 2 * k + 1) * NV
+                                    : fbuf + (i * FS + 2 * k) * NV;
+      if (type == -1) flags |= kFlagBadIndex;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) F[side][v] = 0.0;
-        const int raw = cc[k] + (side ? 1 : -1);
-        const bool outside = raw < 0 || raw >= mp.n[k];
-        int nbc[3] = {cc[0], cc[1], cc[2]};
-        nbc[k] = bc_map(raw, mp.n[k], mp.bc[k]);
-        const int64_t nb = dense_index<DIM>(nbc, mp.n);
-        int type;  // 0 same level, 1 outflow, 2 coarser (virtual child), 3 finer (virtual mother)
-        const R* qnb = nullptr;
-        int off[3] = {0, 0, 0};
-        if (outside && mp.bc[k] != 0) {
-          type = 1;
-        } else {
-          const int8_t s = a.st[nb];
-          if (s == kActive) {
-            type = 0;
-            const int32_t pn = a.pos[nb];
-            if (pn < 0) {
-              flags |= kFlagBadIndex;
-              continue;
-            }
-            qnb = static_cast<const R*>(a.qh) + (int64_t)pn * NV * NST;
-          } else if (s == kVChild && a.pos_c) {
-            type = 2;
-            int m[3];
-            for (int ax = 0; ax < 3; ++ax) {
-              m[ax] = nbc[ax] / a.r;
-              off[ax] = nbc[ax] % a.r;
-            }
-            const int32_t pm = a.pos_c[dense_index<DIM>(m, a.nc)];
-            if (pm < 0) {
-              flags |= kFlagBadIndex;
-              continue;
-            }
-            qnb = static_cast<const R*>(a.qh_c) + (int64_t)pm * NV * NST;
-          } else if (s == kVMother && a.mem_f) {
-            type = 3;
-          } else {
-            flags |= kFlagBadIndex;  // an active cell next to a cell outside the mesh
-            continue;
-          }
-        }
-        if (type == 3) {
-          // sum of the memory of this cell's virtual children on this face
-          const int nsub = DIM == 2 ? a.r : a.r * a.r;
-          for (int j = 0; j < nsub; ++j) {
-            int ch[3];
-            int t = 0;
-            for (int ax = 0; ax < DIM; ++ax) {
-              if (ax == k) {
-                ch[ax] = cc[ax] * a.r + (side ? a.r - 1 : 0);
-              } else {
-                const int aj = DIM == 2 ? j : (t == 0 ? j / a.r : j % a.r);
-                ch[ax] = cc[ax] * a.r + aj;
-                ++t;
-              }
-            }
-            if (DIM == 2) ch[2] = 0;
-            const int64_t chd = dense_index<DIM>(ch, a.nf);
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-              F[side][v] += a.mem_f[((int64_t)(k * 2 + side) * NV + v) * a.ldf + chd];
-          }
-          const double inv = 1.0 / (DIM == 2 ? (double)(a.r * a.r) : (double)(a.r * a.r * a.r));
-#pragma unroll
-          for (int v = 0; v < NV; ++v) F[side][v] *= inv;
-        } else {
-          for (int s = 0; s < n; ++s) {
-            for (int tb = 0; tb < NT; ++tb) {
-              double qm[NV], qp[NV];
-              cell_trace<DIM, M, NV, R>(qme, k, side, tb, s, c, qm);
-              if (type == 0) {
-                cell_trace<DIM, M, NV, R>(qnb, k, 1 - side, tb, s, c, qp);
-              } else if (type == 1) {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) qp[v] = qm[v];
-              } else {
-                // coarse predictor at this face point and time node
-                const int tt[2] = {tb % n, tb / n};
-                double wt[4], wax[3][4];
-                int ti = 0;
-#pragma unroll
-                for (int p = 0; p < 4; ++p) wt[p] = p < n ? ac.at_nodes[a.sub][s][p] : 0.0;
-                for (int ax = 0; ax < 3; ++ax) {
-                  for (int p = 0; p < 4; ++p) {
-                    double w = 0.0;
-                    if (p < n && ax < DIM) {
-                      w = ax == k ? ac.at_face[off[ax]][1 - side][p]
-                                  : ac.at_nodes[off[ax]][tt[ti]][p];
-                    }
-                    wax[ax][p] = w;
-                  }
-                  if (ax < DIM && ax != k) ++ti;
-                }
-                eval_predictor<DIM, M, NV, R>(qnb, wt, wax, qp);
-              }
-              double Fpt[NV];
-              if (side)
-                numerical_flux<SYS, DIM>(qm, qp, k, mp, c, Fpt);
-              else
-                numerical_flux<SYS, DIM>(qp, qm, k, mp, c, Fpt);
-              double wtp = c.w[s];
-              {
-                const int tt[2] = {tb % n, tb / n};
-                for (int dd = 0; dd < DIM - 1; ++dd) wtp *= c.w[tt[dd]];
-              }
-#pragma unroll
-              for (int v = 0; v < NV; ++v) F[side][v] += wtp * Fpt[v];
-            }
-          }
-          if (type == 2) {  // the face flux also goes to the coarse cell's memory
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-              a.mem[((int64_t)(k * 2 + (1 - side)) * NV + v) * ld + nb] += F[side][v];
-          }
-        }
-      }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) q[v] -= (dt / mp.dx[k]) * (F[1][v] - F[0][v]);
+      for (int v = 0; v < NV; ++v)
+        q[v] -= (dt / mp.dx[k]) * (fhi[v] - (type == -1 ? 0.0 : flo[v]));
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {

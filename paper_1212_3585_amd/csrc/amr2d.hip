@@ -19,14 +19,6 @@ hipError_t launch_amr_dt(const double* partial, AmrDtArgs a, AmrClock* clock, Ws
   return hipGetLastError();
 }
 
-hipError_t launch_fill(double* p, int64_t n, double value, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  int64_t b = (n + kBlock - 1) / kBlock;
-  if (b > 4096) b = 4096;
-  hipLaunchKernelGGL(k_fill<0>, dim3((unsigned)b), dim3(kBlock), 0, st, p, n, value);
-  return hipGetLastError();
-}
-
 hipError_t launch_fill_list(double* u, int64_t ld, int nv, const int32_t* list, int64_t n,
                             double value, hipStream_t st) {
   if (n <= 0 || nv <= 0) return hipSuccess;

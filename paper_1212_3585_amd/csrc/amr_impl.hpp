@@ -26,6 +26,7 @@ class AmrImpl final : public AmrImplBase {
     return (size_t)NV * (n * Pow<S, DIM - 1>::v + (DIM == 3 ? n * n * S : 0));
   }
   size_t wh_per_cell() const override { return (size_t)NV * Pow<n, DIM>::v; }
+  size_t fbuf_per_cell() const override { return (size_t)2 * DIM * NV; }
 
   hipError_t cfl(const AmrLevel& lv, double* partial, int nb, hipStream_t st) const override {
     if (lv.nact == 0) return hipSuccess;
@@ -132,8 +133,12 @@ class AmrImpl final : public AmrImplBase {
     a.dt = dt;
     a.sub = sub;
     a.r = ac.r;
-    hipLaunchKernelGGL((k_amr_update<DIM, M, SYS, R>), dim3(amr_blocks(lv.nact)), dim3(kBlock),
-                       0, st, a, lv.mp, c, ac, lv.hdr);
+    using Sh = AmrFluxShape<DIM, M>;
+    const unsigned nb = (unsigned)((lv.nact + Sh::CPB - 1) / Sh::CPB);
+    hipLaunchKernelGGL((k_amr_flux<DIM, M, SYS, R>), dim3(nb), dim3(Sh::BLOCK), 0, st, a, lv.mp,
+                       c, ac, lv.fbuf, lv.hdr);
+    hipLaunchKernelGGL((k_amr_apply<DIM, SYS>), dim3(amr_blocks(lv.nact)), dim3(kBlock), 0, st,
+                       a, lv.mp, (const double*)lv.fbuf, lv.hdr);
     return hipGetLastError();
   }
 };

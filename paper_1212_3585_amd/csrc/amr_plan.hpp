@@ -52,6 +52,7 @@ struct AmrLevel {
   double* wb = nullptr;
   double* wh = nullptr;       // reconstruction w_h of the active cells
   void* qh = nullptr;         // predictor of the active cells (predictor precision)
+  double* fbuf = nullptr;     // face fluxes of the active cells [cell][2 dim][nv]
   WsHeader* hdr = nullptr;    // status bits and Picard counters of the level
   MeshParams mp{};            // the level's mesh (n, dx, ld = ncells)
 };
@@ -63,6 +64,8 @@ class AmrImplBase {
   // WENO scratch doubles per active cell (two pass buffers) and w_h doubles
   virtual size_t weno_scratch_per_cell() const = 0;
   virtual size_t wh_per_cell() const = 0;
+  // face-flux doubles per active cell
+  virtual size_t fbuf_per_cell() const = 0;
   // block maxima of sum_k speed_k / dx_k over the active cells -> partial[0..nb)
   virtual hipError_t cfl(const AmrLevel& lv, double* partial, int nb, hipStream_t st) const = 0;
   // virtual mothers of 'coarse' from their children on 'fine'
@@ -102,7 +105,6 @@ struct AmrDtArgs {
 };
 hipError_t launch_amr_dt(const double* partial, AmrDtArgs a, AmrClock* clock, WsHeader* hdr,
                          hipStream_t st);
-hipError_t launch_fill(double* p, int64_t n, double value, hipStream_t st);
 // u[v * ld + list[i]] = value for every variable v < nv and i < n
 hipError_t launch_fill_list(double* u, int64_t ld, int nv, const int32_t* list, int64_t n,
                             double value, hipStream_t st);
