@@ -71,16 +71,25 @@ def cell_kernel_flops(dim, M, nv, picard_sweeps_total, ncells):
     return weno + picard + traces
 
 
+# the sources the uniform 2D cell and face kernels are compiled from (their
+# launcher, kernels, constants and the header they include)
+CELL_KERNEL_SOURCES = ("impl2d.hip", "impl.hpp", "plan.hpp", "fused2d.hpp", "level.hpp",
+                       "predict_mfma.hpp", "kernels.hpp", "consts.hpp", "consts.cpp",
+                       "cell2d_launch.hpp", "cell2d_rows.hpp", "cell2d_rows2.hip",
+                       "cell2d_rows4.hip", "cell2d_rows8.hip", "cell2d_rows16.hip")
+
+
 def device_source_hash():
-    """sha256 of the HIP sources: a traffic figure measured on other kernels
-    than the ones built now is not reported."""
+    """sha256 of the sources of the measured kernels: a traffic figure taken
+    on other kernels than the ones built now is not reported."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1212_3585_amd", "csrc")
     h = hashlib.sha256()
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hpp", ".hip", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in CELL_KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    with open(os.path.join(ROOT, "include", "ader.h"), "rb") as f:
+        h.update(b"ader.h\0" + f.read())
     return h.hexdigest()
 
 
@@ -114,6 +123,7 @@ def traffic_probe():
                                      picard_tol=tol))
         b = torch.empty_like(u0)
         s.compute_dt(u0)
+        s.tune(u0, reps=2)
         s.step(u0, b)
     src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
@@ -312,6 +322,9 @@ def time_form(ader, wl, torch, precision, tol, steps, warmup, u0):
                         lo=(0, 0, 0), hi=(1, 1, 1), bc=(0, 0, 0), cfl=0.9,
                         precision=precision, picard_tol=tol, picard_max=64)
     s = ader.Solver(prob)
+    # tile height of the cell kernel: timed on this state, fastest kept
+    s.compute_dt(u0)
+    rows, tune_ms = s.tune(u0, reps=5)
     s.profile_begin()
     a = u0.clone()
     b = torch.empty_like(a)
@@ -332,7 +345,8 @@ def time_form(ader, wl, torch, precision, tol, steps, warmup, u0):
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return {"ms": e0.elapsed_time(e1), "wall_s": wall, "solver": s}
+    return {"ms": e0.elapsed_time(e1), "wall_s": wall, "solver": s, "tile_rows": rows,
+            "tune_ms": tune_ms}
 
 
 def finish_form(r):
@@ -459,9 +473,16 @@ def main():
                   "status_flags": r32["flags"],
                   "picard_iterations_per_cell": r32["iters"] / p32l / ncells,
                   "cell_kernel_tflops": ach32,
-                  "cell_kernel_frac_of_fp32_peak": ach32 / FP32_PEAK_TFLOPS},
+                  "cell_kernel_frac_of_fp32_peak": ach32 / FP32_PEAK_TFLOPS,
+                  "tile_rows": r32["tile_rows"],
+                  "autotune_ms_per_launch": r32["tune_ms"]},
+        "autotune": {"what": "tile height of the fused cell kernel (4 x rows cells), "
+                             "timed on the initial state, fastest kept",
+                     "fp64_tile_rows": r64["tile_rows"],
+                     "fp64_ms_per_launch": r64["tune_ms"]},
         "roofline": {"bound": "alu",
-                     "kernel": "k_cell2d<3,1,8,double> (WENO + Picard predictor + traces)",
+                     "kernel": f"k_cell2d<3,1,{r64['tile_rows']},double> "
+                               "(WENO + Picard predictor + traces)",
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": recorded_traffic(),
                      "flops_per_launch": flops_launch,

@@ -160,6 +160,24 @@ ader_status ader_debug_predict(ader_plan plan, const double* w_h,
                                int64_t ncells, double* q_h,
                                const double* dt_dev, void* ws, void* stream);
 
+/* Autotuning of the fused 2D cell kernel (2D plans; EUNSUPPORTED for 3D).
+ * The cell kernel works on tiles of 4 x rows cells, one wavefront per tile
+ * row; rows is 2, 4, 8 or 16 (at most 8 for GLM-MHD, whose kernel needs more
+ * registers).  Results do not depend on the height: every wavefront holds one
+ * tile row whatever the height, so the arithmetic per cell is the same.
+ *   ader_tune       times one untimed and 'reps' (1..1000) timed launches of
+ *                   the cell kernel per candidate height on the caller's
+ *                   state u (read only) with *dt_dev, on 'stream'.  It keeps
+ *                   the fastest height in the plan, writes it to *rows (may be
+ *                   NULL), and writes the mean ms of each of the four heights
+ *                   to ms_out[4] (may be NULL; -1 for a height that is not a
+ *                   candidate).  The workspace's traces are overwritten and
+ *                   its status bits and counters cleared.  Synchronous.
+ *   ader_set_tile_rows  forces a height (0 = the default, 8). */
+ader_status ader_tune(ader_plan plan, const double* u, int64_t ld, const double* dt_dev,
+                      void* ws, void* stream, int reps, int* rows, double* ms_out);
+ader_status ader_set_tile_rows(ader_plan plan, int rows);
+
 /* One step over the cell lists of one refinement level (or any subset of a
  * uniform mesh).  On a cell-by-cell AMR mesh the predictor is element-local
  * and identical to the uniform one; the reconstruction of every cell reads a

@@ -27,7 +27,8 @@ EXPORTS = [
     "ader_plan_create", "ader_plan_destroy", "ader_plan_nvar",
     "ader_workspace_bytes", "ader_clear_status", "ader_compute_dt", "ader_step",
     "ader_debug_reconstruct", "ader_debug_predict", "ader_read_status",
-    "ader_debug_constants", "ader_profile_begin", "ader_profile_end",
+    "ader_debug_constants", "ader_profile_begin", "ader_profile_end", "ader_tune",
+    "ader_set_tile_rows",
     "ader_level_workspace_bytes", "ader_step_level",
     "ader_server_create", "ader_server_destroy", "ader_server_footprint",
     "ader_server_submit", "ader_server_progress", "ader_server_request",
@@ -122,6 +123,8 @@ def load_library():
                              ctypes.POINTER(ctypes.c_uint64), vp],
         "ader_debug_constants": [vp, vp, vp, vp, vp],
         "ader_profile_begin": [vp],
+        "ader_tune": [vp, vp, i64, vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), vp],
+        "ader_set_tile_rows": [vp, ctypes.c_int],
         "ader_profile_end": [vp, vp, vp],
         "ader_level_workspace_bytes": [vp, i64, ctypes.POINTER(ctypes.c_size_t)],
         "ader_step_level": [vp, ctypes.POINTER(CLevelView), vp, vp, i64, vp, vp, vp],
@@ -320,6 +323,20 @@ class Solver:
             "ader_debug_constants")
         return {"nodes": arrs[0], "weights": arrs[1], "dmat": arrs[2].reshape(n, n),
                 "time_inv_w": arrs[3].reshape(n, n)}
+
+    def tune(self, u, dt=None, reps=5, stream=None):
+        """Pick the fused 2D cell kernel's tile height on this state; returns
+        (rows, {rows: mean ms per launch})."""
+        dt = self.dt if dt is None else dt
+        rows = ctypes.c_int()
+        ms = np.zeros(4)
+        _check(self.lib.ader_tune(self._plan, _ptr(u), u.shape[1], _ptr(dt), _ptr(self.ws),
+                                  _stream(stream), int(reps), ctypes.byref(rows),
+                                  ms.ctypes.data_as(ctypes.c_void_p)), "ader_tune")
+        return rows.value, {r: float(m) for r, m in zip((2, 4, 8, 16), ms) if m >= 0}
+
+    def set_tile_rows(self, rows):
+        _check(self.lib.ader_set_tile_rows(self._plan, int(rows)), "ader_set_tile_rows")
 
     def profile_begin(self):
         _check(self.lib.ader_profile_begin(self._plan), "ader_profile_begin")

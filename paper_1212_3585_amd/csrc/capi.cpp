@@ -8,6 +8,7 @@
 #include <string>
 
 #include "plan.hpp"
+#include "cell2d_launch.hpp"
 
 struct ader_plan_s {
   ader::PlanData data;
@@ -369,6 +370,65 @@ ader_status ader_debug_constants(ader_plan plan, double* nodes, double* weights,
       time_inv_w[a * n + b] = (double)r.time_inv_w[a][b];
     }
   }
+  return ADER_OK;
+}
+
+ader_status ader_set_tile_rows(ader_plan plan, int rows) {
+  if (!plan) return fail(ADER_EINVAL, "null argument");
+  if (plan->data.dim != 2) return fail(ADER_EUNSUPPORTED, "tile heights apply to 2D plans");
+  if (rows == 0) rows = ader::kCellRowsDefault;
+  bool known = false;
+  for (int r : ader::kCellRowChoices) known = known || r == rows;
+  const int top = ader::max_cell_rows(plan->data.prob.system, plan->data.prob.precision);
+  if (!known || rows > top)
+    return fail(ADER_EINVAL, "tile rows must be 2, 4, 8 or 16, at most " + std::to_string(top) +
+                                 " for this system and precision");
+  plan->data.cell_rows = rows;
+  return ADER_OK;
+}
+
+ader_status ader_tune(ader_plan plan, const double* u, int64_t ld, const double* dt_dev,
+                      void* ws, void* stream, int reps, int* rows, double* ms_out) {
+  if (!plan || !dt_dev) return fail(ADER_EINVAL, "null argument");
+  if (plan->data.dim != 2) return fail(ADER_EUNSUPPORTED, "tile heights apply to 2D plans");
+  if (reps < 1 || reps > 1000) return fail(ADER_EINVAL, "reps must be in 1..1000");
+  if (ader_status s = check_state(plan, u, ld)) return s;
+  if (ader_status s = check_ws(plan, ws)) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const int top = ader::max_cell_rows(plan->data.prob.system, plan->data.prob.precision);
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipError_t e = hipEventCreate(&ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+  int best = plan->data.cell_rows;
+  float best_ms = 0.0f;
+  for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+    const int r = ader::kCellRowChoices[i];
+    if (ms_out) ms_out[i] = -1.0;
+    if (r > top) continue;
+    // one untimed launch, then 'reps' timed launches of this height
+    e = plan->impl->cell2d(plan->data, u, ld, dt_dev, (char*)ws, r, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+    for (int k = 0; k < reps && e == hipSuccess; ++k)
+      e = plan->impl->cell2d(plan->data, u, ld, dt_dev, (char*)ws, r, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+    if (e != hipSuccess) break;
+    ms /= (float)reps;
+    if (ms_out) ms_out[i] = ms;
+    if (best_ms == 0.0f || ms < best_ms) {
+      best_ms = ms;
+      best = r;
+    }
+  }
+  if (e == hipSuccess) e = plan->impl->clear_status((char*)ws, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (e != hipSuccess) return hip_status(e, "ader_tune");
+  plan->data.cell_rows = best;
+  if (rows) *rows = best;
   return ADER_OK;
 }
 

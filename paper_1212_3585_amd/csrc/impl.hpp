@@ -4,6 +4,7 @@
 #include <type_traits>
 
 #include "plan.hpp"
+#include "cell2d_launch.hpp"
 #include "fused2d.hpp"
 #include "level.hpp"
 #include "predict_mfma.hpp"
@@ -169,17 +170,33 @@ struct Impl final : ImplBase {
   }
 
   // 2D: cell kernel (WENO + predictor + traces) and face kernel
+  hipError_t cell2d(const PlanData& p, const double* u_in, int64_t ld, const double* dt,
+                    char* ws, int rows, hipStream_t st) const override {
+    if constexpr (DIM != 2) {
+      return hipErrorInvalidConfiguration;
+    } else {
+      Cell2dArgs a;
+      a.u = u_in;
+      a.ld = ld;
+      a.traces = ws + p.off_tr;
+      a.dt = dt;
+      a.mp = params(p, ld);
+      a.n0 = p.mp.n[0];
+      a.n1 = p.mp.n[1];
+      return launch_cell2d(rows, M, SYS, std::is_same<R, double>::value ? 0 : 1, a, p.dc,
+                           reinterpret_cast<WsHeader*>(ws), st);
+    }
+  }
+
   hipError_t step_fused2d(const PlanData& p, const double* u_in, double* u_out, int64_t ld,
                           const double* dt, char* ws, hipStream_t st) const {
-    constexpr int TY = 8;  // tile rows = wavefronts per block
     const MeshParams mp = params(p, ld);
     WsHeader* hdr = reinterpret_cast<WsHeader*>(ws);
     R* tr = reinterpret_cast<R*>(ws + p.off_tr);
     {
       StageTimer timer(&p.prof, ADER_STAGE_PREDICT, st);
-      dim3 grid((p.mp.n[0] + kCellTX - 1) / kCellTX, (p.mp.n[1] + TY - 1) / TY);
-      hipLaunchKernelGGL((k_cell2d<M, SYS, TY, R>), grid, dim3(64 * TY), 0, st, u_in, ld, tr,
-                         dt, mp, p.dc, hdr);
+      hipError_t e = cell2d(p, u_in, ld, dt, ws, p.cell_rows, st);
+      if (e != hipSuccess) return e;
     }
     {
       StageTimer timer(&p.prof, ADER_STAGE_FLUX, st);

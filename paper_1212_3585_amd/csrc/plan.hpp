@@ -66,6 +66,7 @@ struct PlanData {
   size_t off_dtp = 0;  // per-block partial maxima of the time-step reduction
   size_t off_tr = 0;   // face traces of the fused 2D path
   size_t ws_bytes = 0;
+  int cell_rows = 8;   // tile height of the fused 2D cell kernel (ader_tune)
   mutable Profiler prof;
 };
 
@@ -106,6 +107,9 @@ struct ImplBase {
                                    hipStream_t st) const = 0;
   virtual hipError_t step(const PlanData& p, const double* u_in, double* u_out, int64_t ld,
                           const double* dt, char* ws, hipStream_t st) const = 0;
+  // the fused 2D cell kernel alone with tile height 'rows' (2D plans)
+  virtual hipError_t cell2d(const PlanData& p, const double* u_in, int64_t ld, const double* dt,
+                            char* ws, int rows, hipStream_t st) const = 0;
   virtual LevelLayout level_layout(const PlanData& p, int64_t npred) const = 0;
   virtual hipError_t step_level(const PlanData& p, const LevelArgs& L, const double* u_in,
                                 double* u_out, int64_t ld, const double* dt, char* ws,

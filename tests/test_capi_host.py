@@ -221,3 +221,27 @@ def test_flux_selector_validation(ader_mod):
     mhd = ader_mod.Problem(dim=2, M=2, system=ader_mod.SYS_MHD_GLM, gamma=5 / 3, n=(8, 8, 1),
                            flux=ader_mod.FLUX_OSHER)
     assert lib.ader_plan_create(ctypes.byref(mhd.to_c()), ctypes.byref(h)) == ader_mod.EUNSUPPORTED
+
+
+def test_tile_rows_validation(ader_mod):
+    lib = ader_mod.load_library()
+    for kw, good, bad in [
+        (dict(dim=2, M=3, n=(32, 32, 1)), (0, 2, 4, 8, 16), (1, 3, 32)),
+        (dict(dim=2, M=2, n=(32, 32, 1), system=ader_mod.SYS_MHD_GLM), (2, 4, 8), (16,)),
+        (dict(dim=2, M=2, n=(32, 32, 1), system=ader_mod.SYS_MHD_GLM, precision=1),
+         (2, 4, 8), (16,)),
+    ]:
+        st, plan = _create(ader_mod, **kw)
+        assert st == 0
+        for r in good:
+            assert lib.ader_set_tile_rows(plan, r) == 0, (kw, r)
+        for r in bad:
+            assert lib.ader_set_tile_rows(plan, r) == -1, (kw, r)
+        # reps out of range is refused before any launch
+        assert lib.ader_tune(plan, None, 0, None, None, None, 0, None, None) == -1
+        lib.ader_plan_destroy(plan)
+    st, plan3 = _create(ader_mod, dim=3, M=2, n=(8, 8, 8))
+    assert st == 0
+    assert lib.ader_set_tile_rows(plan3, 8) == -2
+    lib.ader_plan_destroy(plan3)
+    assert lib.ader_set_tile_rows(None, 8) == -1
