@@ -370,9 +370,16 @@ def main():
     ap.add_argument("--no-amr", action="store_true", help="skip the AMR legs")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run the launches that the HBM counters calibrate")
+    ap.add_argument("--amr-only", action="store_true",
+                    help="only the AMR legs (for profiling them); prints {\"amr\": [...]}")
     args = ap.parse_args()
     if args.traffic_probe:
         traffic_probe()
+        return
+    if args.amr_only:
+        from paper_1212_3585_amd import ader, workloads as wl
+        ader.require_gpu()
+        print(json.dumps({"amr": amr_legs(ader, wl)}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus must be 1",
