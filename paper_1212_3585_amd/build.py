@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libaderweno.so")
 SOURCES = ["consts.cpp", "capi.cpp", "server.cpp", "amr.cpp", "impl2d.hip", "impl3d.hip",
            "batch2d.hip", "amr2d.hip", "amr3d.hip", "cell2d_rows2.hip", "cell2d_rows4.hip",
-           "cell2d_rows8.hip", "cell2d_rows16.hip"]
+           "cell2d_rows8.hip", "cell2d_rows16.hip", "amr_regrid.hip"]
 ARCH = "gfx950"
 
 

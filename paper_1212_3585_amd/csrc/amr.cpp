@@ -77,12 +77,27 @@ struct ader_amr_s {
   std::vector<ader::AmrLevel> lv;
   std::vector<std::vector<double>> h_init;
   std::vector<std::vector<uint8_t>> h_flags;
-  std::vector<std::vector<int8_t>> h_status;
+  std::vector<std::vector<int8_t>> h_status;  // during the build only
   std::vector<void*> dev_allocs;
-  // per-level lists and scratch (act, vc, vm, wa, wh, qh, fbuf), grown by a regrid;
-  // temporaries of the regrid's children passes
-  std::vector<std::array<DevBuf, 7>> lvl_bufs;
-  std::array<DevBuf, 5> tmp;
+  // per-level scratch of the active cells (wa, wh, qh, fbuf), grown on demand
+  std::vector<std::array<DevBuf, 4>> lvl_bufs;
+  // per-level dense regrid arrays: flags, dilation scratch, previous status,
+  // mother slots (list capacity = the level's cells)
+  struct RegridLevel {
+    uint8_t* F = nullptr;
+    uint8_t* T = nullptr;
+    int8_t* old = nullptr;
+    int32_t* slot = nullptr;
+    int32_t* list = nullptr;   // second list (new cells)
+    int32_t* tslot = nullptr;  // their mother slots
+  };
+  std::vector<RegridLevel> rg;
+  // temporaries of the regrid's reconstruction of mothers (wa, wh)
+  std::array<DevBuf, 2> tmp;
+  void* sel_temp = nullptr;   // stream-compaction scratch
+  size_t sel_bytes = 0;
+  int* d_count = nullptr;     // device counters of the compactions
+  unsigned int* d_changed = nullptr;
   double* partial = nullptr;
   ader::AmrClock* clock = nullptr;
   ader::AmrClock* h_clock = nullptr;  // pinned staging
@@ -300,15 +315,6 @@ bool stencils_in_mesh(const std::vector<Grid>& g, const Status& S, const int* bc
   return true;
 }
 
-std::vector<Grid> level_grids(const ader_amr_s* a) {
-  std::vector<Grid> g(a->L + 1);
-  for (int l = 0; l <= a->L; ++l) {
-    g[l].d = a->d;
-    for (int k = 0; k < 3; ++k) g[l].n[k] = a->lv[l].n[k];
-  }
-  return g;
-}
-
 template <typename T>
 ader_status upload(ader_amr a, T** dst, const void* src, size_t bytes) {
   void* p = nullptr;
@@ -332,42 +338,51 @@ hipError_t fill_buf(DevBuf& b, T** dst, const void* src, size_t bytes) {
   return e;
 }
 
-// Lists, positions and scratch of level l from a->h_status[l]; the dense
-// status and position arrays are rewritten in place.
+ader::RgGrid rg_grid(const ader_amr_s* a, int l) {
+  ader::RgGrid g;
+  g.dim = a->d;
+  for (int k = 0; k < 3; ++k) {
+    g.n[k] = a->lv[l].n[k];
+    g.bc[k] = k < a->d ? a->prob.bc[k] : ADER_BC_PERIODIC;
+  }
+  g.N = a->lv[l].ncells;
+  return g;
+}
+
+// Number selected by a compaction (synchronous read of the device counter).
+hipError_t select_count(ader_amr a, int mode, const int8_t* st, const int8_t* old, int64_t N,
+                        int32_t* out, int64_t* count) {
+  size_t bytes = a->sel_bytes;
+  hipError_t e = ader::rg_select(mode, st, old, N, out, a->d_count, a->sel_temp, &bytes,
+                                 a->stream);
+  int c = 0;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&c, a->d_count, sizeof(int), hipMemcpyDeviceToHost, a->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
+  *count = c;
+  return e;
+}
+
+// Lists, positions and scratch of level l from its device status.
 ader_status set_level_lists(ader_amr a, int l) {
   ader::AmrLevel& v = a->lv[l];
   const int64_t N = v.ncells;
   const int M = a->M, d = a->d;
-  const std::vector<int8_t>& s = a->h_status[l];
-  std::vector<int32_t> act, vc, vm, pos(N, -1);
-  for (int64_t i = 0; i < N; ++i) {
-    if (s[i] == ader::kActive) {
-      pos[i] = (int32_t)act.size();
-      act.push_back((int32_t)i);
-    } else if (s[i] == ader::kVChild) {
-      vc.push_back((int32_t)i);
-    } else if (s[i] == ader::kVMother) {
-      vm.push_back((int32_t)i);
-    }
-  }
-  hipError_t e = hipMemcpy(v.st, s.data(), N, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(v.pos, pos.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice);
-  v.nact = (int64_t)act.size();
-  v.nvc = (int64_t)vc.size();
-  v.nvm = (int64_t)vm.size();
-  std::array<DevBuf, 7>& B = a->lvl_bufs[l];
+  hipError_t e = select_count(a, ader::kSelActive, v.st, nullptr, N, v.act, &v.nact);
+  if (e == hipSuccess) e = select_count(a, ader::kSelVChild, v.st, nullptr, N, v.vc, &v.nvc);
+  if (e == hipSuccess) e = select_count(a, ader::kSelVMother, v.st, nullptr, N, v.vm, &v.nvm);
+  if (e == hipSuccess) e = ader::rg_positions(v.pos, N, v.act, v.nact, a->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
+  std::array<DevBuf, 4>& B = a->lvl_bufs[l];
   const size_t na = (size_t)v.nact;
-  if (e == hipSuccess) e = fill_buf(B[0], &v.act, act.data(), sizeof(int32_t) * act.size());
-  if (e == hipSuccess) e = fill_buf(B[1], &v.vc, vc.data(), sizeof(int32_t) * vc.size());
-  if (e == hipSuccess) e = fill_buf(B[2], &v.vm, vm.data(), sizeof(int32_t) * vm.size());
   if (e == hipSuccess)
-    e = fill_buf(B[3], &v.wa, nullptr, sizeof(double) * a->impl->weno_scratch_per_cell() * na);
+    e = fill_buf(B[0], &v.wa, nullptr, sizeof(double) * a->impl->weno_scratch_per_cell() * na);
   if (e == hipSuccess)
-    e = fill_buf(B[4], &v.wh, nullptr, sizeof(double) * a->impl->wh_per_cell() * na);
+    e = fill_buf(B[1], &v.wh, nullptr, sizeof(double) * a->impl->wh_per_cell() * na);
   if (e == hipSuccess)
-    e = fill_buf(B[5], &v.qh, nullptr, a->impl->qh_elem_size() * a->nv * ipow(M + 1, d + 1) * na);
+    e = fill_buf(B[2], &v.qh, nullptr, a->impl->qh_elem_size() * a->nv * ipow(M + 1, d + 1) * na);
   if (e == hipSuccess)
-    e = fill_buf(B[6], &v.fbuf, nullptr, sizeof(double) * a->impl->fbuf_per_cell() * na);
+    e = fill_buf(B[3], &v.fbuf, nullptr, sizeof(double) * a->impl->fbuf_per_cell() * na);
   if (e != hipSuccess) return hip_status(e, "AMR level lists");
   v.wb = v.wa + (size_t)a->nv * (M + 1) * ipow(2 * M + 1, d - 1) * na;
   a->dtargs.nb[l] = v.nact == 0 ? 0
@@ -379,41 +394,19 @@ ader_status set_level_lists(ader_amr a, int l) {
   return ADER_OK;
 }
 
-// Level-l cells 'targets' (dense indices) from the reconstruction of their
-// mothers on level l-1 (synchronous; temporaries freed before returning).
-ader_status children_pass(ader_amr a, int l, const std::vector<int32_t>& targets) {
-  if (targets.empty()) return ADER_OK;
-  const std::vector<Grid> g = level_grids(a);
-  std::vector<int32_t> moth(targets.size());
-  for (size_t i = 0; i < targets.size(); ++i) {
-    int c[3];
-    g[l].coords(targets[i], c);
-    for (int k = 0; k < a->d; ++k) c[k] /= a->r;
-    moth[i] = (int32_t)g[l - 1].idx(c);
-  }
-  std::vector<int32_t> uniq(moth);
-  std::sort(uniq.begin(), uniq.end());
-  uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
-  std::vector<int32_t> slot(targets.size());
-  for (size_t i = 0; i < targets.size(); ++i)
-    slot[i] = (int32_t)(std::lower_bound(uniq.begin(), uniq.end(), moth[i]) - uniq.begin());
-  const size_t nm = uniq.size(), nt = targets.size();
-  const size_t wa_n = a->impl->weno_scratch_per_cell() * nm, wh_n = a->impl->wh_per_cell() * nm;
-  int32_t *d_moth = nullptr, *d_targets = nullptr, *d_slot = nullptr;
-  double *wa = nullptr, *wh = nullptr;
-  hipError_t e = fill_buf(a->tmp[0], &d_moth, uniq.data(), sizeof(int32_t) * nm);
-  if (e == hipSuccess) e = fill_buf(a->tmp[1], &d_targets, targets.data(), sizeof(int32_t) * nt);
-  if (e == hipSuccess) e = fill_buf(a->tmp[2], &d_slot, slot.data(), sizeof(int32_t) * nt);
-  if (e == hipSuccess) e = fill_buf(a->tmp[3], &wa, nullptr, sizeof(double) * wa_n);
-  if (e == hipSuccess) e = fill_buf(a->tmp[4], &wh, nullptr, sizeof(double) * wh_n);
-  if (e == hipSuccess) {
-    double* wb = wa + (size_t)a->nv * (a->M + 1) * ipow(2 * a->M + 1, a->d - 1) * nm;
-    e = a->impl->children(a->lv[l - 1], d_moth, (int64_t)nm, wa, wb, wh, a->lv[l], d_targets,
-                          d_slot, (int64_t)nt, a->dc, a->ac, a->stream);
-  }
-  const hipError_t es = hipStreamSynchronize(a->stream);
-  if (e == hipSuccess) e = es;
-  return hip_status(e, "ader_amr_regrid");
+// Level-l cells 'targets' (device list, nt of them) from the reconstruction of
+// their mothers on level l-1, listed in 'moth' (nm cells, the slot of each
+// level-(l-1) cell in slot_c); wa, wb, wh hold the mothers' scratch.
+hipError_t children_from(ader_amr a, int l, const int32_t* moth, int64_t nm, const int32_t* slot_c,
+                         double* wa, double* wb, double* wh, const int32_t* targets, int64_t nt) {
+  if (nt == 0 || nm == 0) return hipSuccess;
+  int32_t* tslot = a->rg[l].tslot;
+  hipError_t e = ader::rg_slots(rg_grid(a, l), rg_grid(a, l - 1), a->r, targets, nt, slot_c,
+                                tslot, a->stream);
+  if (e == hipSuccess)
+    e = a->impl->children(a->lv[l - 1], moth, nm, wa, wb, wh, a->lv[l], targets, tslot, nt,
+                          a->dc, a->ac, a->stream);
+  return e;
 }
 
 ader_status record_advance(ader_amr a, int l, int sub, hipStream_t st) {
@@ -593,6 +586,20 @@ ader_status ader_amr_build(ader_amr a) {
                          (a->prob.hi[1] - a->prob.lo[1]) / a->prob.n[1],
                          d > 2 ? (a->prob.hi[2] - a->prob.lo[2]) / a->prob.n[2] : 1.0};
   a->lvl_bufs.resize(L + 1);
+  a->rg.assign(L + 1, {});
+  {
+    // compaction scratch for the largest level, device counters
+    int64_t nmax = 0;
+    for (int l = 0; l <= L; ++l) nmax = std::max<int64_t>(nmax, a->lv[l].ncells);
+    size_t bytes = 0;
+    e = ader::rg_select(ader::kSelActive, nullptr, nullptr, nmax, nullptr, nullptr, nullptr,
+                        &bytes, a->stream);
+    if (e != hipSuccess) return hip_status(e, "ader_amr_build (compaction scratch)");
+    a->sel_bytes = bytes;
+    if (ader_status st = upload(a, &a->sel_temp, nullptr, bytes)) return st;
+    if (ader_status st = upload(a, &a->d_count, nullptr, sizeof(int) * 4)) return st;
+    if (ader_status st = upload(a, &a->d_changed, nullptr, sizeof(unsigned int))) return st;
+  }
   for (int l = 0; l <= L; ++l) {
     ader::AmrLevel& v = a->lv[l];
     const int64_t N = v.ncells;
@@ -603,12 +610,21 @@ ader_status ader_amr_build(ader_amr a) {
         for (int q = 0; q < nv; ++q) u0[(size_t)q * N + i] = std::nan("");
     ader_status st = ADER_OK;
     if (!st) st = upload(a, &v.u, u0.data(), sizeof(double) * nv * N);
-    if (!st) st = upload(a, &v.st, nullptr, N);
+    if (!st) st = upload(a, &v.st, s.data(), N);
     if (!st) st = upload(a, &v.pos, nullptr, sizeof(int32_t) * N);
+    if (!st) st = upload(a, &v.act, nullptr, sizeof(int32_t) * N);
+    if (!st) st = upload(a, &v.vc, nullptr, sizeof(int32_t) * N);
+    if (!st) st = upload(a, &v.vm, nullptr, sizeof(int32_t) * N);
     if (!st && l > 0) st = upload(a, &v.mem, nullptr, sizeof(double) * d * 2 * nv * N);
     std::vector<char> zero(ader::kHeaderBytes, 0);
     if (!st) st = upload(a, &v.hdr, zero.data(), ader::kHeaderBytes);
-    if (!st) st = set_level_lists(a, l);
+    auto& R = a->rg[l];
+    if (!st && l < L) st = upload(a, &R.F, nullptr, N);
+    if (!st) st = upload(a, &R.T, nullptr, N);
+    if (!st) st = upload(a, &R.old, nullptr, N);
+    if (!st && l < L) st = upload(a, &R.slot, nullptr, sizeof(int32_t) * N);
+    if (!st) st = upload(a, &R.list, nullptr, sizeof(int32_t) * N);
+    if (!st) st = upload(a, &R.tslot, nullptr, sizeof(int32_t) * N);
     if (st) return st;
     ader_problem pl = a->prob;
     for (int k = 0; k < d; ++k) pl.n[k] = v.n[k];
@@ -616,6 +632,10 @@ ader_status ader_amr_build(ader_amr a) {
     for (int k = 0; k < d; ++k) v.dx[k] = v.mp.dx[k] = dx0[k] / (double)ipow(r, l);
     v.mp.ld = N;
   }
+  for (int l = 0; l <= L; ++l)
+    if (ader_status st = set_level_lists(a, l)) return st;
+  a->h_status.clear();
+  a->h_status.shrink_to_fit();
   a->dtargs.nlev = L + 1;
   a->dtargs.r = r;
   a->dtargs.cfl = a->prob.cfl;
@@ -676,72 +696,91 @@ ader_status ader_amr_regrid(ader_amr a, int* changed) {
   if (!a || !a->built) return fail(ADER_EINVAL, "mesh not built");
   const int r = a->r, L = a->L;
   if (L == 0) return ADER_OK;
-  const int* bc = a->prob.bc;
-  const std::vector<Grid> g = level_grids(a);
+  hipStream_t st = a->stream;
+  std::vector<ader::RgGrid> g(L + 1);
+  for (int l = 0; l <= L; ++l) g[l] = rg_grid(a, l);
   hipError_t e = hipDeviceSynchronize();
-  // 1. virtual mothers, then virtual children from their mothers, coarse to fine
+  // 1. virtual mothers, then virtual children from their mothers (the level's
+  //    reconstruction of its active cells), coarse to fine
   for (int lev = L - 1; lev >= 0 && e == hipSuccess; --lev)
-    e = a->impl->average(a->lv[lev], a->lv[lev + 1], r, a->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
-  if (e != hipSuccess) return hip_status(e, "ader_amr_regrid");
-  for (int l = 1; l <= L; ++l) {
-    std::vector<int32_t> t;
-    const std::vector<int8_t>& s = a->h_status[l];
-    for (int64_t i = 0; i < (int64_t)s.size(); ++i)
-      if (s[i] == ader::kVChild) t.push_back((int32_t)i);
-    if (ader_status st = children_pass(a, l, t)) return st;
+    e = a->impl->average(a->lv[lev], a->lv[lev + 1], r, st);
+  for (int l = 1; l <= L && e == hipSuccess; ++l) {
+    const ader::AmrLevel& c = a->lv[l - 1];
+    e = children_from(a, l, c.act, c.nact, c.pos, c.wa, c.wb, c.wh, a->lv[l].vc, a->lv[l].nvc);
   }
-  // 2. flags: refine active cells above chi_ref, keep virtual mothers down to chi_rec
-  Flags F(L);
-  for (int l = 0; l < L; ++l) {
+  // 2. flags: refine active cells above chi_ref, keep virtual mothers down to
+  //    chi_rec (or the caller's flags), buffer layers
+  for (int l = 0; l < L && e == hipSuccess; ++l) {
+    auto& R = a->rg[l];
+    const int64_t N = g[l].N;
     if (!a->h_flags[l].empty()) {
-      F[l] = a->h_flags[l];
+      e = hipMemcpyAsync(R.F, a->h_flags[l].data(), N, hipMemcpyHostToDevice, st);
       continue;
     }
-    const int64_t N = g[l].cells();
-    std::vector<double> Phi(N);
-    e = hipMemcpy(Phi.data(), a->lv[l].u + (size_t)a->cfg.indicator_var * N, sizeof(double) * N,
-                  hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_status(e, "ader_amr_regrid");
-    const std::vector<double> chi = lohner(g[l], Phi.data(), bc, a->cfg.eps);
-    const std::vector<int8_t>& s = a->h_status[l];
-    F[l].assign(N, 0);
-    for (int64_t i = 0; i < N; ++i)
-      F[l][i] = (s[i] == ader::kActive && chi[i] > a->cfg.chi_ref) ||
-                (s[i] == ader::kVMother && chi[i] >= a->cfg.chi_rec);
-    for (int b = 0; b < a->cfg.buffer; ++b) F[l] = dilate(g[l], F[l], bc);
+    e = ader::rg_lohner(g[l], a->lv[l].u + (size_t)a->cfg.indicator_var * N, a->lv[l].st,
+                        a->cfg.eps, a->cfg.chi_ref, a->cfg.chi_rec, R.F, st);
+    for (int b = 0; b < a->cfg.buffer && e == hipSuccess; ++b) {
+      e = ader::rg_dilate(g[l], R.F, R.T, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(R.F, R.T, N, hipMemcpyDeviceToDevice, st);
+    }
   }
+  //    closure (rules 4, 5) and nesting
+  for (int l = L - 1; l >= 1 && e == hipSuccess; --l) {
+    e = ader::rg_dilate(g[l], a->rg[l].F, a->rg[l].T, st);
+    if (e == hipSuccess) e = ader::rg_mothers_or(g[l], g[l - 1], r, a->rg[l].T, a->rg[l - 1].F, st);
+  }
+  for (int l = 1; l < L && e == hipSuccess; ++l)
+    e = ader::rg_nest(g[l], g[l - 1], r, a->rg[l - 1].F, a->rg[l].F, st);
+  // 3. status of every level (the previous one kept), changed?
+  for (int l = 0; l <= L && e == hipSuccess; ++l)
+    e = hipMemcpyAsync(a->rg[l].old, a->lv[l].st, g[l].N, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = ader::rg_status0(g[0].N, a->rg[0].F, a->lv[0].st, st);
+  for (int l = 1; l <= L && e == hipSuccess; ++l) {
+    e = ader::rg_dilate(g[l - 1], a->rg[l - 1].F, a->rg[l - 1].T, st);
+    if (e == hipSuccess)
+      e = ader::rg_status(g[l], g[l - 1], r, a->rg[l - 1].F, a->rg[l - 1].T,
+                          l < L ? a->rg[l].F : nullptr, a->lv[l].st, st);
+  }
+  unsigned int ch = 0;
+  if (e == hipSuccess) e = hipMemsetAsync(a->d_changed, 0, sizeof(unsigned int), st);
+  for (int l = 0; l <= L && e == hipSuccess; ++l)
+    e = ader::rg_diff(g[l].N, a->lv[l].st, a->rg[l].old, a->d_changed, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&ch, a->d_changed, sizeof(unsigned int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
   for (auto& f : a->h_flags) f.clear();
-  close_flags(g, F, bc, r, L);
+  if (e != hipSuccess) return hip_status(e, "ader_amr_regrid");
+  if (!ch) return ADER_OK;
   // (the stencil check of the build holds by construction here: an active
   // cell's stencil, M <= r cells wide, lies in the children of its mother's
   // Voronoi neighbours, which are flagged or near-flagged)
-  Status S = status_from_flags(g, F, bc, r, L);
-  if (S == a->h_status) return ADER_OK;
-  // 3. new lists; new cells from their mothers, coarse to fine; removed cells NaN
-  Status old = std::move(a->h_status);
-  a->h_status = std::move(S);
+  // 4. new lists; new cells from their mothers' reconstruction, coarse to
+  //    fine (a new cell's mother may be new itself); removed cells NaN
   for (int l = 0; l <= L; ++l)
-    if (ader_status st = set_level_lists(a, l)) return st;
-  for (int l = 1; l <= L; ++l) {
-    std::vector<int32_t> born, gone;
-    const std::vector<int8_t>& s = a->h_status[l];
-    for (int64_t i = 0; i < (int64_t)s.size(); ++i) {
-      if (s[i] != ader::kAbsent && old[l][i] == ader::kAbsent) born.push_back((int32_t)i);
-      if (s[i] == ader::kAbsent && old[l][i] != ader::kAbsent) gone.push_back((int32_t)i);
-    }
-    if (ader_status st = children_pass(a, l, born)) return st;
-    if (!gone.empty()) {
-      int32_t* dl = nullptr;
-      e = fill_buf(a->tmp[0], &dl, gone.data(), sizeof(int32_t) * gone.size());
-      if (e == hipSuccess)
-        e = ader::launch_fill_list(a->lv[l].u, a->lv[l].ncells, a->nv, dl,
-                                   (int64_t)gone.size(), std::nan(""), a->stream);
-      const hipError_t es = hipStreamSynchronize(a->stream);
-      if (e == hipSuccess) e = es;
-      if (e != hipSuccess) return hip_status(e, "ader_amr_regrid");
-    }
+    if (ader_status s = set_level_lists(a, l)) return s;
+  for (int l = 1; l <= L && e == hipSuccess; ++l) {
+    const int64_t Nc = g[l - 1].N, Nf = g[l].N;
+    auto& Rc = a->rg[l - 1];
+    auto& Rf = a->rg[l];
+    int64_t nm = 0, nt = 0;
+    e = select_count(a, ader::kSelMothers, a->lv[l - 1].st, nullptr, Nc, Rc.list, &nm);
+    if (e == hipSuccess) e = select_count(a, ader::kSelBorn, a->lv[l].st, Rf.old, Nf, Rf.list, &nt);
+    if (e != hipSuccess || nt == 0) continue;
+    if (e == hipSuccess) e = ader::rg_positions(Rc.slot, Nc, Rc.list, nm, st);
+    double *wa = nullptr, *wh = nullptr;
+    if (e == hipSuccess)
+      e = fill_buf(a->tmp[0], &wa, nullptr,
+                   sizeof(double) * a->impl->weno_scratch_per_cell() * (size_t)nm);
+    if (e == hipSuccess)
+      e = fill_buf(a->tmp[1], &wh, nullptr, sizeof(double) * a->impl->wh_per_cell() * (size_t)nm);
+    if (e != hipSuccess) break;
+    double* wb = wa + (size_t)a->nv * (a->M + 1) * ipow(2 * a->M + 1, a->d - 1) * nm;
+    e = children_from(a, l, Rc.list, nm, Rc.slot, wa, wb, wh, Rf.list, nt);
   }
+  for (int l = 1; l <= L && e == hipSuccess; ++l)
+    e = ader::rg_gone(g[l].N, a->nv, a->lv[l].u, a->lv[l].st, a->rg[l].old, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_status(e, "ader_amr_regrid");
   // the recorded step holds the old lists: record again at the next step
   if (a->exec) {
     (void)hipGraphExecDestroy(a->exec);
@@ -771,8 +810,8 @@ ader_status ader_amr_get_level(ader_amr a, int level, double* u, int8_t* status)
   const ader::AmrLevel& v = a->lv[level];
   if (e == hipSuccess && u)
     e = hipMemcpy(u, v.u, sizeof(double) * a->nv * v.ncells, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && status) e = hipMemcpy(status, v.st, v.ncells, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_status(e, "ader_amr_get_level");
-  if (status) std::memcpy(status, a->h_status[level].data(), v.ncells);
   return ADER_OK;
 }
 

@@ -143,6 +143,7 @@ k_amr_subavg(double* __restrict__ u, int64_t ld, const int32_t* __restrict__ tar
   int cc[3];
   dense_coords<DIM>(targets[i], nn, cc);
   const int r = ac.r;
+  if (tslot[i] < 0) return;  // no reconstructed mother (never for a consistent mesh)
   const double* w = wh + ((int64_t)tslot[i] * NV + v) * NS;
   double acc_z = 0.0;
 #pragma unroll

@@ -109,4 +109,44 @@ hipError_t launch_amr_dt(const double* partial, AmrDtArgs a, AmrClock* clock, Ws
 hipError_t launch_fill_list(double* u, int64_t ld, int nv, const int32_t* list, int64_t n,
                             double value, hipStream_t st);
 
+// ----- device-side mesh change (amr_regrid.hip) -----
+struct RgGrid {
+  int dim;
+  int n[3];   // cells per axis of the level
+  int bc[3];  // boundary kinds per axis
+  int64_t N;  // n0 n1 n2
+};
+enum { kSelActive = 0, kSelVChild = 1, kSelVMother = 2, kSelMothers = 3, kSelBorn = 4 };
+
+// F = refine / keep flags from the Loehner indicator of phi (see k_rg_lohner)
+hipError_t rg_lohner(const RgGrid& g, const double* phi, const int8_t* st, double eps,
+                     double chi_ref, double chi_rec, uint8_t* F, hipStream_t s);
+// out = Voronoi neighbourhood of the flagged cells of in
+hipError_t rg_dilate(const RgGrid& g, const uint8_t* in, uint8_t* out, hipStream_t s);
+// Fc |= some child flagged in Ff
+hipError_t rg_mothers_or(const RgGrid& fine, const RgGrid& coarse, int r, const uint8_t* Ff,
+                         uint8_t* Fc, hipStream_t s);
+// Ff &= Fc[mother]
+hipError_t rg_nest(const RgGrid& fine, const RgGrid& coarse, int r, const uint8_t* Fc,
+                   uint8_t* Ff, hipStream_t s);
+// status of a level >= 1 from the coarser level's flags and near flags
+hipError_t rg_status(const RgGrid& fine, const RgGrid& coarse, int r, const uint8_t* Fc,
+                     const uint8_t* near_c, const uint8_t* Ff, int8_t* st, hipStream_t s);
+hipError_t rg_status0(int64_t N, const uint8_t* F0, int8_t* st, hipStream_t s);
+// *changed |= 1 where a and b differ
+hipError_t rg_diff(int64_t N, const int8_t* a, const int8_t* b, unsigned int* changed,
+                   hipStream_t s);
+// NaN in every variable of the cells absent in st_new and not in st_old
+hipError_t rg_gone(int64_t N, int nv, double* u, const int8_t* st_new, const int8_t* st_old,
+                   hipStream_t s);
+// pos = -1, then pos[list[j]] = j
+hipError_t rg_positions(int32_t* pos, int64_t N, const int32_t* list, int64_t n, hipStream_t s);
+// tslot[i] = slot_c[mother of targets[i]]
+hipError_t rg_slots(const RgGrid& fine, const RgGrid& coarse, int r, const int32_t* targets,
+                    int64_t nt, const int32_t* slot_c, int32_t* tslot, hipStream_t s);
+// ascending dense indices i with the selection 'mode' (kSel*) into out,
+// their number into *d_count (device); temp == nullptr queries *temp_bytes
+hipError_t rg_select(int mode, const int8_t* st, const int8_t* old, int64_t N, int32_t* out,
+                     int* d_count, void* temp, size_t* temp_bytes, hipStream_t s);
+
 }  // namespace ader
