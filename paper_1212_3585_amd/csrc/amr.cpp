@@ -1,4 +1,5 @@
-// AMR driver: mesh construction on the host, per-level device data, and the
+// AMR driver: mesh construction on the host, per-level device data, the
+// device-side regrid, and the
 // local-time-stepping schedule of one level-0 step (Section 3), optionally
 // recorded once as a HIP graph and replayed.
 //
@@ -17,15 +18,18 @@
 // The indicator is evaluated in plain double arithmetic, term by term, so the
 // integer refinement decisions are reproducible.
 //
-// Regrid (ader_amr_regrid), at a common time of all levels:
+// After the build, the status arrays and level lists live on the device only.
+//
+// Regrid (ader_amr_regrid), at a common time of all levels, on the device
+// (kernels in amr_regrid.hip; only counts and a changed flag come back):
 //   1. virtual mothers averaged; virtual children take the sub-cell averages
-//      of their mothers' reconstruction, coarse to fine (device);
-//   2. flags on the host from the indicator variable: an active cell is
-//      refined when chi > chi_ref, a virtual mother stays refined unless
-//      chi < chi_rec; buffer layers, closure and status as in the build;
-//   3. new level lists and scratch; cells that did not exist take the
-//      sub-cell averages of their mothers' reconstruction, coarse to fine
-//      (device); removed cells are set to NaN.
+//      of their mothers' reconstruction, coarse to fine;
+//   2. flags from the indicator variable: an active cell is refined when
+//      chi > chi_ref, a virtual mother stays refined unless chi < chi_rec;
+//      buffer layers, closure and status as in the build;
+//   3. new level lists (stream compaction) and scratch; cells that did not
+//      exist take the sub-cell averages of their mothers' reconstruction,
+//      coarse to fine; removed cells are set to NaN.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
