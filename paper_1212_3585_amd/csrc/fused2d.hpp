@@ -243,13 +243,14 @@ __device__ __forceinline__ void cell2d_tile(int tile_x, int tile_y, const double
   const R thr = (R)mp.tol * fmax(R(1), wcell);
   bool done = !cell_ok;
   int iters = 0;
-  for (int it = 1; it <= mp.maxit; ++it) {
+  // one Picard sweep from qa into qb; returns this lane's largest change
+  auto sweep = [&](const R (&qa)[NV][n], R (&qb)[NV][n]) -> R {
     R Rs[NV][n];
 #pragma unroll
     for (int s = 0; s < n; ++s) {
       R qs[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) qs[v] = q[v][s];
+      for (int v = 0; v < NV; ++v) qs[v] = qa[v][s];
       R F[DIM][NV];
       phys_fluxes<SYS, DIM, R>(qs, gamma, ch, adv, F);
 #pragma unroll
@@ -273,17 +274,42 @@ __device__ __forceinline__ void cell2d_tile(int tile_x, int tile_y, const double
         for (int sp = 0; sp < n; ++sp)
           acc += cget<R>(c.tinvw[s][sp], c.tinvw_f[s][sp]) * Rs[v][sp];
         const R qn = w[v] - acc;
-        delta = fmax(delta, fabs(qn - q[v][s]));
-        q[v][s] = qn;
+        delta = fmax(delta, fabs(qn - qa[v][s]));
+        qb[v][s] = qn;
       }
     }
-    // a cell has converged when none of its 16 lanes moved by more than thr
+    return delta;
+  };
+  // a cell has converged when none of its 16 lanes moved by more than thr;
+  // returns true when every cell of the wavefront has
+  auto converged = [&](R delta, int it) -> bool {
     const uint64_t moved = __ballot(node_ok && !(delta <= thr));
     if (!done && (moved & cell_lanes) == 0) {
       done = true;
       iters = it;
     }
-    if (!__any(!done)) break;
+    return !__any(!done);
+  };
+  // two sweeps per trip, alternating the two state arrays (no copies); the
+  // exits are wavefront-uniform
+  R q2[NV][n];
+  bool in_q2 = false;
+  for (int it = 1; it <= mp.maxit; it += 2) {
+    if (converged(sweep(q, q2), it)) {
+      in_q2 = true;
+      break;
+    }
+    if (it + 1 > mp.maxit) {
+      in_q2 = true;
+      break;
+    }
+    if (converged(sweep(q2, q), it + 1)) break;
+  }
+  if (in_q2) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int s = 0; s < n; ++s) q[v][s] = q2[v][s];
   }
   if (cell_ok && !done) iters = mp.maxit;
   block_report(cell_ok && lead ? (unsigned)iters : 0u,
