@@ -216,7 +216,9 @@ def amr_leg(ader, label, dim, n0, r, L, M, ic, precision, steps, cfl=0.5, regrid
     A.build()
     build_s = time.perf_counter() - t0
     counts = [A.counts(l) for l in range(L + 1)]
-    A.step(1e9)                      # warm-up, records the graph
+    A.step(1e9)                      # warm-up (sets the level steps)
+    pb, fb, tune_ms = A.tune(reps=3)  # launch shapes of the predictor and the face fluxes
+    A.step(1e9)                      # records the graph with the tuned shapes
     A.clock()
     cu0 = A.stats()["cell_updates"]
     t0 = time.perf_counter()
@@ -230,7 +232,8 @@ def amr_leg(ader, label, dim, n0, r, L, M, ic, precision, steps, cfl=0.5, regrid
            "fp32 predictor / fp64", "levels": counts, "mesh_build_s": build_s,
            "level0_steps": steps, "cell_updates": cu, "seconds": el,
            "cell_updates_per_s": cu / el, "ms_per_level0_step": el / steps * 1e3,
-           "t_reached": t_sim, "status_flags": st["flags"]}
+           "t_reached": t_sim, "status_flags": st["flags"],
+           "autotune": {"predict_block": pb, "flux_block": fb, "ms_per_launch": tune_ms}}
     if regrid_steps > 0:
         cu0 = st["cell_updates"]
         t_regrid, changed = 0.0, 0

@@ -392,6 +392,20 @@ ader_status ader_amr_set_flags(ader_amr amr, int level, const uint8_t* flags);
 ader_status ader_amr_build(ader_amr amr);
 ader_status ader_amr_regrid(ader_amr amr, int* changed);
 ader_status ader_amr_step(ader_amr amr, double t_end, void* stream);
+/* Autotuning of the AMR kernels' launch shapes, after at least one step
+ * (the level steps must be set).  On the level with the most active cells,
+ * it times one untimed and 'reps' (1..1000) timed launches of each candidate.
+ * Candidates: the predictor's block of 128, 256 or 512 threads (cells of
+ * (M+1)^d lanes each; only sizes whose LDS fits; the 2D fp64 matrix-core
+ * predictor has its one layout) and the face-flux kernel's block of about
+ * 128, 256 or 512 threads.  It keeps the fastest of each, writes them to
+ * *pred_block and *flux_block (may be NULL), and writes the mean ms of the
+ * six candidates to ms_out[6] (predictor 128/256/512, then flux; -1 where
+ * not a candidate; may be NULL).  Results do not depend on the shapes.  The
+ * level's scratch is overwritten; the averages, the clock and the
+ * statistics are kept.  Synchronous; the step graph is recorded again. */
+ader_status ader_amr_tune(ader_amr amr, int reps, int* pred_block, int* flux_block,
+                          double* ms_out);
 ader_status ader_amr_clock(ader_amr amr, double* t, int64_t* steps, double* dt0);
 /* Level averages (host [nvar][cells]; absent cells NaN) and status (host
  * [cells]: -2 absent, -1 virtual mother, 0 active, 1 virtual child). */

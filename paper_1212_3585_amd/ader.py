@@ -35,6 +35,7 @@ EXPORTS = [
     "ader_server_stats_get",
     "ader_amr_create", "ader_amr_destroy", "ader_amr_level_cells", "ader_amr_set_level",
     "ader_amr_set_flags", "ader_amr_build", "ader_amr_regrid", "ader_amr_step", "ader_amr_clock",
+    "ader_amr_tune",
     "ader_amr_get_level", "ader_amr_counts", "ader_amr_stats",
     "ader_status_string", "ader_last_error",
 ]
@@ -145,6 +146,8 @@ def load_library():
         "ader_amr_set_flags": [vp, ctypes.c_int, vp],
         "ader_amr_build": [vp],
         "ader_amr_regrid": [vp, ctypes.POINTER(ctypes.c_int)],
+        "ader_amr_tune": [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                          ctypes.POINTER(ctypes.c_int), vp],
         "ader_amr_step": [vp, dbl, vp],
         "ader_amr_clock": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl)],
         "ader_amr_get_level": [vp, ctypes.c_int, vp, vp],
@@ -544,6 +547,18 @@ class Amr:
         ch = ctypes.c_int()
         _check(self.lib.ader_amr_regrid(self._h, ctypes.byref(ch)), "ader_amr_regrid")
         return bool(ch.value)
+
+    def tune(self, reps=3):
+        """Pick the AMR kernels' block shapes (after a step); returns
+        (pred_block, flux_block, {"predict": {block: ms}, "flux": {...}})."""
+        pb, fb = ctypes.c_int(), ctypes.c_int()
+        ms = np.zeros(6)
+        _check(self.lib.ader_amr_tune(self._h, int(reps), ctypes.byref(pb), ctypes.byref(fb),
+                                      ms.ctypes.data_as(ctypes.c_void_p)), "ader_amr_tune")
+        sizes = (128, 256, 512)
+        return pb.value, fb.value, {
+            "predict": {b: float(m) for b, m in zip(sizes, ms[:3]) if m >= 0},
+            "flux": {b: float(m) for b, m in zip(sizes, ms[3:]) if m >= 0}}
 
     def step(self, t_end, stream=None):
         _check(self.lib.ader_amr_step(self._h, float(t_end), _stream(stream)), "ader_amr_step")

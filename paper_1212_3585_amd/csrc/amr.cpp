@@ -110,6 +110,7 @@ struct ader_amr_s {
   bool built = false;
   double t_end_set = -1.0;
   uint64_t cell_updates = 0, updates_per_step = 0, regrids = 0;
+  ader::AmrShape shape;  // launch shapes of the tuned kernels (ader_amr_tune)
   ader::AmrDtArgs dtargs{};
 };
 
@@ -419,7 +420,7 @@ ader_status record_advance(ader_amr a, int l, int sub, hipStream_t st) {
   for (int lev = a->L - 1; lev >= l && e == hipSuccess; --lev)
     e = im->average(a->lv[lev], a->lv[lev + 1], a->r, st);
   if (e == hipSuccess && l > 0) e = im->project(a->lv[l], a->lv[l - 1], a->ac, sub, st);
-  if (e == hipSuccess) e = im->predict(a->lv[l], &a->clock->dt[l], a->dc, st);
+  if (e == hipSuccess) e = im->predict(a->lv[l], &a->clock->dt[l], a->dc, a->shape, st);
   if (e != hipSuccess) return hip_status(e, "ader_amr_step");
   if (l < a->L) {
     // the finer level's memory is read at its virtual children only
@@ -430,7 +431,7 @@ ader_status record_advance(ader_amr a, int l, int sub, hipStream_t st) {
       if (ader_status stt = record_advance(a, l + 1, s, st)) return stt;
   }
   e = im->update(a->lv[l], l > 0 ? &a->lv[l - 1] : nullptr, l < a->L ? &a->lv[l + 1] : nullptr,
-                 &a->clock->dt[l], sub, a->dc, a->ac, st);
+                 &a->clock->dt[l], sub, a->dc, a->ac, a->shape, st);
   return hip_status(e, "ader_amr_step");
 }
 
@@ -792,6 +793,76 @@ ader_status ader_amr_regrid(ader_amr a, int* changed) {
   }
   a->regrids += 1;
   if (changed) *changed = 1;
+  return ADER_OK;
+}
+
+ader_status ader_amr_tune(ader_amr a, int reps, int* pred_block, int* flux_block,
+                          double* ms_out) {
+  if (!a || !a->built) return fail(ADER_EINVAL, "mesh not built");
+  if (reps < 1 || reps > 1000) return fail(ADER_EINVAL, "reps must be in 1..1000");
+  if (a->cell_updates == 0) return fail(ADER_EINVAL, "take a step first (the level steps)");
+  hipStream_t st = a->stream;
+  hipError_t e = hipDeviceSynchronize();
+  // the level with the most active cells
+  int lt = 0;
+  for (int l = 1; l <= a->L; ++l)
+    if (a->lv[l].nact > a->lv[lt].nact) lt = l;
+  const ader::AmrLevel& v = a->lv[lt];
+  const ader::AmrLevel* coarse = lt > 0 ? &a->lv[lt - 1] : nullptr;
+  const ader::AmrLevel* fine = lt < a->L ? &a->lv[lt + 1] : nullptr;
+  // the tuning launches must not count in the statistics
+  std::vector<ader::WsHeader> saved(a->L + 1);
+  for (int l = 0; l <= a->L && e == hipSuccess; ++l)
+    e = hipMemcpy(&saved[l], a->lv[l].hdr, sizeof(ader::WsHeader), hipMemcpyDeviceToHost);
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+  ader::AmrShape best = a->shape;
+  float best_ms[2] = {0.0f, 0.0f};
+  for (int which = 0; which < 2 && e == hipSuccess; ++which) {
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+      const int b = ader::kAmrBlockChoices[i];
+      double* slot = ms_out ? &ms_out[which * 3 + i] : nullptr;
+      if (slot) *slot = -1.0;
+      if (v.nact == 0 || (which == 0 && !a->impl->pred_block_ok(b))) continue;
+      ader::AmrShape sh = a->shape;
+      sh.pred_block = b;
+      auto run = [&]() {
+        return which == 0 ? a->impl->predict(v, &a->clock->dt[lt], a->dc, sh, st)
+                          : a->impl->flux_only(v, coarse, fine, &a->clock->dt[lt], 0, a->dc,
+                                               a->ac, b, st);
+      };
+      e = run();  // untimed
+      if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+      for (int k = 0; k < reps && e == hipSuccess; ++k) e = run();
+      if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+      if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+      if (e != hipSuccess) break;
+      ms /= (float)reps;
+      if (slot) *slot = ms;
+      if (best_ms[which] == 0.0f || ms < best_ms[which]) {
+        best_ms[which] = ms;
+        if (which == 0)
+          best.pred_block = b;
+        else
+          best.flux_block = b;
+      }
+    }
+  }
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  for (int l = 0; l <= a->L && e == hipSuccess; ++l)
+    e = hipMemcpy(a->lv[l].hdr, &saved[l], sizeof(ader::WsHeader), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_status(e, "ader_amr_tune");
+  a->shape = best;
+  if (a->exec) {  // the recorded step holds the old shapes
+    (void)hipGraphExecDestroy(a->exec);
+    a->exec = nullptr;
+  }
+  if (pred_block) *pred_block = best.pred_block;
+  if (flux_block) *flux_block = best.flux_block;
   return ADER_OK;
 }
 

@@ -309,14 +309,14 @@ struct AmrUpdArgs {
 // Shape of the face-flux kernel: a group of G lanes per (cell, axis k); lane
 // g < NPT of a group owns space-time point (s = g / NT, tb = g % NT) of the
 // face.  CPB cells per block.
-template <int DIM, int M>
+template <int DIM, int M, int TB = kBlock>
 struct AmrFluxShape {
   static constexpr int n = M + 1;
   static constexpr int NT = Pow<n, DIM - 1>::v;  // transverse nodes of a face
   static constexpr int NPT = n * NT;              // space-time points of a face
   static constexpr int G = NPT <= 4 ? 4 : (NPT <= 8 ? 8 : (NPT <= 16 ? 16 : (NPT <= 32 ? 32 : 64)));
   static constexpr int LPC = DIM * G;             // lanes per cell
-  static constexpr int CPB = LPC >= 256 ? 1 : 256 / LPC;
+  static constexpr int CPB = LPC >= TB ? 1 : TB / LPC;  // about TB threads
   static constexpr int BLOCK = CPB * LPC;
 };
 
@@ -358,11 +358,11 @@ __device__ __forceinline__ int amr_face_kind(const AmrUpdArgs& a, const MeshPara
 // evaluated once.  Face-averaged fluxes go to
 // fbuf[(i * 2 DIM + 2 k + side) * NV + v].  A face to a virtual child also
 // adds its flux to the child's memory.
-template <int DIM, int M, int SYS, typename R>
-__global__ void __launch_bounds__((AmrFluxShape<DIM, M>::BLOCK))
+template <int DIM, int M, int SYS, typename R, int TB = kBlock>
+__global__ void __launch_bounds__((AmrFluxShape<DIM, M, TB>::BLOCK))
 k_amr_flux(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, double* __restrict__ fbuf,
            WsHeader* hdr) {
-  using Sh = AmrFluxShape<DIM, M>;
+  using Sh = AmrFluxShape<DIM, M, TB>;
   constexpr int n = M + 1;
   constexpr int NV = NVars<SYS, DIM>::v;
   constexpr int NST = Pow<n, DIM + 1>::v;

@@ -52,8 +52,41 @@ class AmrImpl final : public AmrImplBase {
     return hipGetLastError();
   }
 
+  static constexpr bool kMfmaPredictor = DIM == 2 && std::is_same<R, double>::value;
+
+  // the generic predictor's LDS: DIM NV block values of R (at most 64 KiB)
+  template <int BLK>
+  static constexpr bool pred_fits() {
+    return (size_t)DIM * NV * BLK * sizeof(R) + 2048 <= 65536;
+  }
+
+  bool pred_block_ok(int block) const override {
+    if (kMfmaPredictor) return block == 256;
+    switch (block) {
+      case 128: return pred_fits<128>();
+      case 256: return pred_fits<256>();
+      case 512: return pred_fits<512>();
+      default: return false;
+    }
+  }
+
+  template <int BLK>
+  hipError_t launch_predict(const AmrLevel& lv, const double* dt, const DevConsts& c,
+                            hipStream_t st) const {
+    if constexpr (!pred_fits<BLK>()) {
+      return hipErrorInvalidConfiguration;
+    } else {
+      constexpr int NS = Pow<n, DIM>::v;
+      const int64_t np = lv.nact;
+      hipLaunchKernelGGL((k_predict<DIM, M, SYS, R, R, BLK>),
+                         dim3((unsigned)((np + BLK / NS - 1) / (BLK / NS))), dim3(BLK), 0, st,
+                         (const double*)lv.wh, static_cast<R*>(lv.qh), np, dt, lv.mp, c, lv.hdr);
+      return hipGetLastError();
+    }
+  }
+
   hipError_t predict(const AmrLevel& lv, const double* dt, const DevConsts& c,
-                     hipStream_t st) const override {
+                     const AmrShape& sh, hipStream_t st) const override {
     const int64_t np = lv.nact;
     if (np == 0) return hipSuccess;
     unsigned int* flags = &lv.hdr->status;
@@ -76,10 +109,12 @@ class AmrImpl final : public AmrImplBase {
                          dim3((unsigned)((np + 4 * (kBlock / 64) - 1) / (4 * (kBlock / 64)))),
                          dim3(kBlock), 0, st, (const double*)lv.wh, qh, np, dt, lv.mp, c, lv.hdr);
     } else {
-      constexpr int NS = Pow<n, DIM>::v;
-      hipLaunchKernelGGL((k_predict<DIM, M, SYS, R, R>),
-                         dim3((unsigned)((np + kBlock / NS - 1) / (kBlock / NS))), dim3(kBlock),
-                         0, st, (const double*)lv.wh, qh, np, dt, lv.mp, c, lv.hdr);
+      (void)qh;
+      switch (sh.pred_block) {
+        case 128: return launch_predict<128>(lv, dt, c, st);
+        case 512: return launch_predict<512>(lv, dt, c, st);
+        default: return launch_predict<256>(lv, dt, c, st);
+      }
     }
     return hipGetLastError();
   }
@@ -108,10 +143,8 @@ class AmrImpl final : public AmrImplBase {
     return hipGetLastError();
   }
 
-  hipError_t update(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
-                    const double* dt, int sub, const DevConsts& c, const AmrConsts& ac,
-                    hipStream_t st) const override {
-    if (lv.nact == 0) return hipSuccess;
+  static AmrUpdArgs upd_args(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
+                             const double* dt, int sub, const AmrConsts& ac) {
     AmrUpdArgs a{};
     a.u = lv.u;
     a.st = lv.st;
@@ -133,10 +166,38 @@ class AmrImpl final : public AmrImplBase {
     a.dt = dt;
     a.sub = sub;
     a.r = ac.r;
-    using Sh = AmrFluxShape<DIM, M>;
+    return a;
+  }
+
+  template <int TB>
+  static hipError_t launch_flux(const AmrUpdArgs& a, const AmrLevel& lv, const DevConsts& c,
+                                const AmrConsts& ac, hipStream_t st) {
+    using Sh = AmrFluxShape<DIM, M, TB>;
     const unsigned nb = (unsigned)((lv.nact + Sh::CPB - 1) / Sh::CPB);
-    hipLaunchKernelGGL((k_amr_flux<DIM, M, SYS, R>), dim3(nb), dim3(Sh::BLOCK), 0, st, a, lv.mp,
-                       c, ac, lv.fbuf, lv.hdr);
+    hipLaunchKernelGGL((k_amr_flux<DIM, M, SYS, R, TB>), dim3(nb), dim3(Sh::BLOCK), 0, st, a,
+                       lv.mp, c, ac, lv.fbuf, lv.hdr);
+    return hipGetLastError();
+  }
+
+  hipError_t flux_only(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
+                       const double* dt, int sub, const DevConsts& c, const AmrConsts& ac,
+                       int flux_block, hipStream_t st) const override {
+    if (lv.nact == 0) return hipSuccess;
+    const AmrUpdArgs a = upd_args(lv, coarse, fine, dt, sub, ac);
+    switch (flux_block) {
+      case 128: return launch_flux<128>(a, lv, c, ac, st);
+      case 512: return launch_flux<512>(a, lv, c, ac, st);
+      default: return launch_flux<256>(a, lv, c, ac, st);
+    }
+  }
+
+  hipError_t update(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
+                    const double* dt, int sub, const DevConsts& c, const AmrConsts& ac,
+                    const AmrShape& sh, hipStream_t st) const override {
+    if (lv.nact == 0) return hipSuccess;
+    hipError_t e = flux_only(lv, coarse, fine, dt, sub, c, ac, sh.flux_block, st);
+    if (e != hipSuccess) return e;
+    const AmrUpdArgs a = upd_args(lv, coarse, fine, dt, sub, ac);
     hipLaunchKernelGGL((k_amr_apply<DIM, SYS>), dim3(amr_blocks(lv.nact)), dim3(kBlock), 0, st,
                        a, lv.mp, (const double*)lv.fbuf, lv.hdr);
     return hipGetLastError();

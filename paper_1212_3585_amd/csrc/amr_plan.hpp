@@ -57,6 +57,15 @@ struct AmrLevel {
   MeshParams mp{};            // the level's mesh (n, dx, ld = ncells)
 };
 
+// Launch shapes of the tuned AMR kernels (ader_amr_tune): threads per block
+// of the generic predictor and about-threads per block of the face-flux
+// kernel, each 128, 256 or 512.
+struct AmrShape {
+  int pred_block = 256;
+  int flux_block = 256;
+};
+constexpr int kAmrBlockChoices[3] = {128, 256, 512};
+
 class AmrImplBase {
  public:
   virtual ~AmrImplBase() = default;
@@ -76,12 +85,20 @@ class AmrImplBase {
                              int sub, hipStream_t st) const = 0;
   // reconstruction + predictor of the active cells of 'lv' with step *dt
   virtual hipError_t predict(const AmrLevel& lv, const double* dt, const DevConsts& c,
-                             hipStream_t st) const = 0;
+                             const AmrShape& sh, hipStream_t st) const = 0;
+  // whether the predictor of this configuration has a tunable block (the 2D
+  // fp64 matrix-core predictor has a fixed layout), and whether a block size
+  // fits (LDS)
+  virtual bool pred_block_ok(int block) const = 0;
   // finite-volume update of the active cells of 'lv' (substep 'sub' of the
   // coarser level's step); coarse / fine may be null at the ends
   virtual hipError_t update(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
                             const double* dt, int sub, const DevConsts& c, const AmrConsts& ac,
-                            hipStream_t st) const = 0;
+                            const AmrShape& sh, hipStream_t st) const = 0;
+  // the face-flux kernel alone (for tuning; its fluxes go to the scratch)
+  virtual hipError_t flux_only(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
+                               const double* dt, int sub, const DevConsts& c,
+                               const AmrConsts& ac, int flux_block, hipStream_t st) const = 0;
   // regrid: reconstruction of the listed cells 'moth' (nm of them) of
   // 'coarse' into wh (scratch wa, wb as for predict), then targets[i] of
   // 'fine' = sub-cell average of w_h of slot tslot[i]

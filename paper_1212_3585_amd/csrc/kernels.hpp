@@ -516,9 +516,9 @@ __device__ __forceinline__ void pick_row(const DevConsts& c, int a, R (&row)[n])
 
 // Space-time predictor of 'ncells' cells whose nodal reconstructions are
 // wh[(cell * NV + v) * NS + a].  Output qh[(cell * NV + v) * NST + a + NS * s]
-// in type OUT.  One lane per spatial node a; CPB cells per 256-thread block.
-template <int DIM, int M, int SYS, typename R, typename OUT>
-__global__ void __launch_bounds__(kBlock)
+// in type OUT.  One lane per spatial node a; CPB cells per BLK-thread block.
+template <int DIM, int M, int SYS, typename R, typename OUT, int BLK = kBlock>
+__global__ void __launch_bounds__(BLK)
 k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
           const double* __restrict__ dt_dev, MeshParams mp, DevConsts c, WsHeader* hdr) {
   constexpr int n = M + 1;
@@ -526,9 +526,9 @@ k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
   constexpr int NST = NS * n;
   constexpr int NV = NVars<SYS, DIM>::v;
   constexpr int G = NS;
-  constexpr int CPB = kBlock / G;
+  constexpr int CPB = BLK / G;
   using U = typename Bits<R>::U;
-  __shared__ R shF[DIM * NV * kBlock];
+  __shared__ R shF[DIM * NV * BLK];
   __shared__ U shDelta[CPB];
   __shared__ U shMag[CPB];
 
@@ -591,7 +591,7 @@ k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
 #pragma unroll
       for (int k = 0; k < DIM; ++k)
 #pragma unroll
-        for (int v = 0; v < NV; ++v) shF[(k * NV + v) * kBlock + tid] = cour[k] * F[k][v];
+        for (int v = 0; v < NV; ++v) shF[(k * NV + v) * BLK + tid] = cour[k] * F[k][v];
       __syncthreads();
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -604,7 +604,7 @@ k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
             const int base = tid - ak[k] * stride;
 #pragma unroll
             for (int b = 0; b < n; ++b)
-              acc += drow[k][b] * shF[(k * NV + v) * kBlock + base + b * stride];
+              acc += drow[k][b] * shF[(k * NV + v) * BLK + base + b * stride];
           }
         }
         Racc[v][s] = acc;

@@ -245,3 +245,8 @@ def test_tile_rows_validation(ader_mod):
     assert lib.ader_set_tile_rows(plan3, 8) == -2
     lib.ader_plan_destroy(plan3)
     assert lib.ader_set_tile_rows(None, 8) == -1
+
+
+def test_amr_tune_needs_a_built_mesh(ader_mod):
+    lib = ader_mod.load_library()
+    assert lib.ader_amr_tune(None, 3, None, None, None) == -1

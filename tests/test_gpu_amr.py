@@ -158,3 +158,34 @@ def test_amr_mixed_precision_error(ader):
         A.step(1.0)
     err = _compare(H, A, tol=1e-5)
     print(f"fp32-predictor AMR relative L1 vs fp64 oracle: {err:.3e}")
+
+
+@pytest.mark.parametrize("dim,precision", [(2, 1), (3, 0), (2, 0)])
+def test_amr_tune_keeps_the_bits(ader, dim, precision):
+    say(f"AMR autotuner ({dim}D, precision {precision}): tuned shapes give the same bits")
+    n0, r = (6, 3) if dim == 2 else (4, 2)
+    L = 2 if dim == 2 else 1
+    Uf = wl.perturbed_smooth_euler((n0 * r ** L,) * dim, 13)
+    Us = _levels_from_fine(Uf, r, L)
+    if dim == 2:
+        flags = _patch_flags(n0, r)
+    else:
+        F0 = np.zeros((n0,) * 3, bool)
+        F0[1, 1:3, 1] = True
+        flags = [F0]
+    out = []
+    for tune in (False, True):
+        H, A = _make(ader, dim, 2, n0, r, L, Us, flags=flags, precision=precision)
+        A.step(1.0)
+        if tune:
+            pb, fb, ms = A.tune(reps=2)
+            assert pb in (128, 256, 512) and fb in (128, 256, 512)
+            assert set(ms["flux"]) == {128, 256, 512} and ms["predict"]
+            assert all(m > 0 for d in ms.values() for m in d.values())
+        for _ in range(2):
+            A.step(1.0)
+        out.append(([A.level(l) for l in range(L + 1)], A.stats()))
+    for (Ua, sa), (Ub, sb) in zip(out[0][0], out[1][0]):
+        assert np.array_equal(sa, sb)
+        assert np.array_equal(np.nan_to_num(Ua, nan=7.0), np.nan_to_num(Ub, nan=7.0))
+    assert out[0][1] == out[1][1]       # statistics untouched by the tuning launches
