@@ -417,19 +417,18 @@ hipError_t children_from(ader_amr a, int l, const int32_t* moth, int64_t nm, con
 ader_status record_advance(ader_amr a, int l, int sub, hipStream_t st) {
   const ader::AmrImplBase* im = a->impl;
   hipError_t e = hipSuccess;
-  for (int lev = a->L - 1; lev >= l && e == hipSuccess; --lev)
+  // virtual mothers of the finer levels, finest first; then this level's
+  // averaging, projection and the finer level's memory in one launch
+  for (int lev = a->L - 1; lev > l && e == hipSuccess; --lev)
     e = im->average(a->lv[lev], a->lv[lev + 1], a->r, st);
-  if (e == hipSuccess && l > 0) e = im->project(a->lv[l], a->lv[l - 1], a->ac, sub, st);
+  if (e == hipSuccess)
+    e = im->prepare(a->lv[l], l > 0 ? &a->lv[l - 1] : nullptr,
+                    l < a->L ? &a->lv[l + 1] : nullptr, a->ac, sub, st);
   if (e == hipSuccess) e = im->predict(a->lv[l], &a->clock->dt[l], a->dc, a->shape, st);
   if (e != hipSuccess) return hip_status(e, "ader_amr_step");
-  if (l < a->L) {
-    // the finer level's memory is read at its virtual children only
-    const ader::AmrLevel& f = a->lv[l + 1];
-    e = ader::launch_fill_list(f.mem, f.ncells, a->d * 2 * a->nv, f.vc, f.nvc, 0.0, st);
-    if (e != hipSuccess) return hip_status(e, "ader_amr_step");
+  if (l < a->L)
     for (int s = 0; s < a->r; ++s)
       if (ader_status stt = record_advance(a, l + 1, s, st)) return stt;
-  }
   e = im->update(a->lv[l], l > 0 ? &a->lv[l - 1] : nullptr, l < a->L ? &a->lv[l + 1] : nullptr,
                  &a->clock->dt[l], sub, a->dc, a->ac, a->shape, st);
   return hip_status(e, "ader_amr_step");

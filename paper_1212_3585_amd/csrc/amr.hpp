@@ -7,9 +7,9 @@
 //                   active cells (the CFL rule, reading R1, per level)
 //   k_amr_dt        level-0 step from all levels' maxima, level steps, clock
 //   k_amr_average   virtual mothers = mean of their r^d children (eq. average)
-//   k_amr_project   virtual children = sub-cell average of the mother's
-//                   space-time predictor at the substep's mother-local time
-//                   (Section 3.1.3)
+//   k_amr_prepare   one launch per level substep for the averaging, the
+//                   projection and the clearing of the finer level's memory
+//   k_amr_weno2d    both WENO passes of a 2D level's active cells
 //   k_amr_weno_x    first WENO pass of the active cells, stencil indices from
 //                   the dense grid; later passes and the predictor are the
 //                   level-list kernels (level.hpp, predictor kernels)
@@ -215,42 +215,128 @@ __device__ __forceinline__ void eval_predictor(const R* __restrict__ q, const do
   }
 }
 
+// The work of one level substep before its reconstruction, in one launch:
+//   threads [0, nvm)            virtual mothers of the level = mean of their
+//                               children (eq. average);
+//   threads [nvm, nvm + nvc)    virtual children of the level = sub-cell
+//                               average of the mother's predictor at the
+//                               substep's mother-local time (Section 3.1.3);
+//   the rest                    the finer level's memory at its virtual
+//                               children cleared (its r substeps follow).
+// The three sets are disjoint; nothing reads what another writes.
+struct AmrPrepArgs {
+  double* u;
+  int64_t ld;
+  int n[3];
+  const int32_t* vm;
+  int64_t nvm;
+  const int32_t* vc;
+  int64_t nvc;
+  const double* uf;  // finer level (averages), null on the finest level
+  int64_t ldf;
+  int nf[3];
+  const int32_t* pos_c;  // coarser level (projection), null on level 0
+  const void* qh_c;
+  int nc[3];
+  double* mem_f;          // finer level's memory, its virtual children vcf
+  const int32_t* vcf;
+  int64_t nvcf;
+  int sub;
+};
+
 template <int DIM, int M, int NV, typename R>
 __global__ void __launch_bounds__(kBlock)
-k_amr_project(double* __restrict__ u, int64_t ld, const int32_t* __restrict__ vc, int64_t nvc,
-              int n0, int n1, int n2, const int32_t* __restrict__ pos_c, int nc0, int nc1,
-              int nc2, const R* __restrict__ qh_c, AmrConsts ac, int sub, WsHeader* hdr) {
+k_amr_prepare(AmrPrepArgs a, AmrConsts ac, WsHeader* hdr) {
   constexpr int n = M + 1;
   constexpr int NST = Pow<n, DIM + 1>::v;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   unsigned int flags = 0;
-  if (i < nvc) {
-    const int nn[3] = {n0, n1, n2}, ncc[3] = {nc0, nc1, nc2};
-    const int64_t cell = vc[i];
-    int c[3], m[3], o[3];
-    dense_coords<DIM>(cell, nn, c);
-    for (int k = 0; k < 3; ++k) {
-      m[k] = c[k] / ac.r;
-      o[k] = c[k] % ac.r;
+  const int r = ac.r;
+  if (i < a.nvm) {
+    const int64_t cell = a.vm[i];
+    int c[3];
+    dense_coords<DIM>(cell, a.n, c);
+    const int nchild = DIM == 2 ? r * r : r * r * r;
+    double sum[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sum[v] = 0.0;
+    for (int b = 0; b < nchild; ++b) {
+      int f[3] = {c[0] * r + b % r, DIM > 1 ? c[1] * r + (b / r) % r : 0,
+                  DIM > 2 ? c[2] * r + b / (r * r) : 0};
+      const int64_t child = dense_index<DIM>(f, a.nf);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sum[v] += a.uf[v * a.ldf + child];
     }
-    const int32_t mp = pos_c[dense_index<DIM>(m, ncc)];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) a.u[v * a.ld + cell] = sum[v] / nchild;
+  } else if (i < a.nvm + a.nvc) {
+    const int64_t cell = a.vc[i - a.nvm];
+    int c[3], m[3], o[3];
+    dense_coords<DIM>(cell, a.n, c);
+    for (int k = 0; k < 3; ++k) {
+      m[k] = c[k] / r;
+      o[k] = c[k] % r;
+    }
+    const int32_t mp = a.pos_c[dense_index<DIM>(m, a.nc)];
     if (mp < 0) {
       flags |= kFlagBadIndex;  // a virtual child whose mother is not active
     } else {
       double wt[4], wax[3][4];
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
-        wt[p] = p < n ? ac.at_sub[sub][p] : 0.0;
+        wt[p] = p < n ? ac.at_sub[a.sub][p] : 0.0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) wax[k][p] = p < n ? ac.sub_avg[o[k]][p] : 0.0;
       }
       double val[NV];
-      eval_predictor<DIM, M, NV, R>(qh_c + (int64_t)mp * NV * NST, wt, wax, val);
+      eval_predictor<DIM, M, NV, R>(static_cast<const R*>(a.qh_c) + (int64_t)mp * NV * NST, wt,
+                                    wax, val);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) u[v * ld + cell] = val[v];
+      for (int v = 0; v < NV; ++v) a.u[v * a.ld + cell] = val[v];
     }
+  } else {
+    const int64_t j = i - a.nvm - a.nvc;
+    constexpr int E = 2 * DIM * NV;  // memory entries per cell
+    if (j < a.nvcf * E) a.mem_f[(j / a.nvcf) * a.ldf + a.vcf[j % a.nvcf]] = 0.0;
   }
   block_report(0u, flags, hdr);
+}
+
+// Both WENO passes of a 2D level's active cells in one launch, one thread per
+// (cell, variable): the 2M+1 x lines of the stencil, then the n y lines, the
+// same line operations as the two-pass kernels.  wh[(p NV + v) n^2 + px + n py].
+template <int M, int NV>
+__global__ void __launch_bounds__(kBlock)
+k_amr_weno2d(const double* __restrict__ u, int64_t ld, const int32_t* __restrict__ act,
+             int64_t nact, MeshParams mp, double* __restrict__ wh, DevConsts c) {
+  constexpr int n = M + 1;
+  constexpr int S = 2 * M + 1;
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= nact * NV) return;
+  const int v = (int)(t % NV);
+  const int64_t p = t / NV;
+  int cc[3];
+  dense_coords<2>(act[p], mp.n, cc);
+  double xo[S][n];
+#pragma unroll
+  for (int oy = 0; oy < S; ++oy) {
+    const int gy = bc_map(cc[1] + oy - M, mp.n[1], mp.bc[1]);
+    const int64_t row = (int64_t)v * ld + (int64_t)mp.n[0] * gy;
+    double vals[S];
+#pragma unroll
+    for (int o = 0; o < S; ++o) vals[o] = u[row + bc_map(cc[0] + o - M, mp.n[0], mp.bc[0])];
+    weno_line<M>(vals, c, xo[oy]);
+  }
+  double* dp = wh + (p * NV + v) * n * n;
+#pragma unroll
+  for (int px = 0; px < n; ++px) {
+    double vals[S], w[n];
+#pragma unroll
+    for (int o = 0; o < S; ++o) vals[o] = xo[o][px];
+    weno_line<M>(vals, c, w);
+#pragma unroll
+    for (int q = 0; q < n; ++q) dp[px + n * q] = w[q];
+  }
 }
 
 // First WENO pass (along x) of the active cells; the (2M+1)^d stencil is

@@ -43,12 +43,34 @@ class AmrImpl final : public AmrImplBase {
     return hipGetLastError();
   }
 
-  hipError_t project(const AmrLevel& lv, const AmrLevel& c, const AmrConsts& ac, int sub,
-                     hipStream_t st) const override {
-    if (lv.nvc == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_amr_project<DIM, M, NV, R>), dim3(amr_blocks(lv.nvc)), dim3(kBlock), 0,
-                       st, lv.u, lv.ncells, lv.vc, lv.nvc, lv.n[0], lv.n[1], lv.n[2], c.pos,
-                       c.n[0], c.n[1], c.n[2], static_cast<const R*>(c.qh), ac, sub, lv.hdr);
+  hipError_t prepare(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
+                     const AmrConsts& ac, int sub, hipStream_t st) const override {
+    AmrPrepArgs a{};
+    a.u = lv.u;
+    a.ld = lv.ncells;
+    for (int k = 0; k < 3; ++k) a.n[k] = lv.n[k];
+    if (fine) {
+      a.vm = lv.vm;
+      a.nvm = lv.nvm;
+      a.uf = fine->u;
+      a.ldf = fine->ncells;
+      for (int k = 0; k < 3; ++k) a.nf[k] = fine->n[k];
+      a.mem_f = fine->mem;
+      a.vcf = fine->vc;
+      a.nvcf = fine->nvc;
+    }
+    if (coarse) {
+      a.vc = lv.vc;
+      a.nvc = lv.nvc;
+      a.pos_c = coarse->pos;
+      a.qh_c = coarse->qh;
+      for (int k = 0; k < 3; ++k) a.nc[k] = coarse->n[k];
+    }
+    a.sub = sub;
+    const int64_t total = a.nvm + a.nvc + a.nvcf * 2 * DIM * NV;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_amr_prepare<DIM, M, NV, R>), dim3(amr_blocks(total)), dim3(kBlock), 0,
+                       st, a, ac, lv.hdr);
     return hipGetLastError();
   }
 
@@ -92,12 +114,20 @@ class AmrImpl final : public AmrImplBase {
     unsigned int* flags = &lv.hdr->status;
     double* pass0 = lv.wa;
     double* pass1 = DIM == 2 ? lv.wh : lv.wb;
+    if constexpr (DIM == 2) {
+      (void)flags;
+      (void)pass0;
+      (void)pass1;
+      hipLaunchKernelGGL((k_amr_weno2d<M, NV>), dim3(amr_blocks(np * NV)), dim3(kBlock), 0, st,
+                         (const double*)lv.u, lv.ncells, lv.act, np, lv.mp, lv.wh, c);
+    } else {
     hipLaunchKernelGGL((k_amr_weno_x<DIM, M, NV>), dim3(amr_blocks(np * NV * Pow<S, DIM - 1>::v)),
                        dim3(kBlock), 0, st, lv.u, lv.ncells, lv.act, np, lv.mp, pass0, c);
     hipLaunchKernelGGL((k_level_weno_pass<DIM, M, NV, 1>),
                        dim3(amr_blocks(np * NV * n * Pow<S, DIM - 2>::v)), dim3(kBlock), 0, st,
                        (const double*)nullptr, (int64_t)0, (const int32_t*)nullptr,
                        (const double*)pass0, pass1, np, c, flags);
+    }
     if constexpr (DIM == 3) {
       hipLaunchKernelGGL((k_level_weno_pass<DIM, M, NV, 2>), dim3(amr_blocks(np * NV * n * n)),
                          dim3(kBlock), 0, st, (const double*)nullptr, (int64_t)0,

@@ -80,9 +80,11 @@ class AmrImplBase {
   // virtual mothers of 'coarse' from their children on 'fine'
   virtual hipError_t average(const AmrLevel& coarse, const AmrLevel& fine, int r,
                              hipStream_t st) const = 0;
-  // virtual children of 'lv' from the predictor of 'coarse' at substep 'sub'
-  virtual hipError_t project(const AmrLevel& lv, const AmrLevel& coarse, const AmrConsts& ac,
-                             int sub, hipStream_t st) const = 0;
+  // one level substep's averaging (from 'fine'), projection (from 'coarse'
+  // at substep 'sub') and the clearing of fine's memory at its virtual
+  // children; coarse / fine may be null at the ends
+  virtual hipError_t prepare(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
+                             const AmrConsts& ac, int sub, hipStream_t st) const = 0;
   // reconstruction + predictor of the active cells of 'lv' with step *dt
   virtual hipError_t predict(const AmrLevel& lv, const double* dt, const DevConsts& c,
                              const AmrShape& sh, hipStream_t st) const = 0;
