@@ -189,3 +189,32 @@ def test_amr_tune_keeps_the_bits(ader, dim, precision):
         assert np.array_equal(sa, sb)
         assert np.array_equal(np.nan_to_num(Ua, nan=7.0), np.nan_to_num(Ub, nan=7.0))
     assert out[0][1] == out[1][1]       # statistics untouched by the tuning launches
+
+
+@pytest.mark.parametrize("r,L,M", [(2, 3, 2), (4, 1, 3), (2, 2, 1)])
+def test_amr_factors_and_depths(ader, r, L, M):
+    say(f"AMR 2D r={r} L={L} M={M}: nested patches, 2 level-0 steps vs oracle, then a regrid")
+    n0 = 8
+    Us = _levels_from_fine(wl.perturbed_smooth_euler((n0 * r ** L,) * 2, 20 + r + L), r, L)
+    flags = []
+    for l in range(L):
+        F = np.zeros((n0 * r ** l,) * 2, bool)
+        lo, hi = (3 * r ** l, 5 * r ** l) if l == 0 else (4 * r ** l - 1, 4 * r ** l + 1)
+        F[lo:hi, lo:hi] = True
+        flags.append(F)
+    H, A = _make(ader, 2, M, n0, r, L, Us, flags=flags)
+    for c_gpu, c_or in zip([A.counts(l) for l in range(L + 1)], H.counts()):
+        assert c_gpu == c_or
+    for _ in range(2):
+        amr_step(H, 0.0, 1.0)
+        A.step(1.0)
+    _compare(H, A)
+    from oracle.amr import regrid
+    G = [np.roll(f, 1, axis=0) for f in flags]     # move every patch by one cell
+    for l, f in enumerate(G):
+        A.set_flags(l, f)
+    assert regrid(H, flags=G) == A.regrid()
+    amr_step(H, 0.0, 1.0)
+    A.step(1.0)
+    _compare(H, A)
+    assert A.stats()["flags"] == 0
