@@ -444,7 +444,7 @@ __device__ __forceinline__ int amr_face_kind(const AmrUpdArgs& a, const MeshPara
 // evaluated once.  Face-averaged fluxes go to
 // fbuf[(i * 2 DIM + 2 k + side) * NV + v].  A face to a virtual child also
 // adds its flux to the child's memory.
-template <int DIM, int M, int SYS, typename R, int TB = kBlock>
+template <int DIM, int M, int SYS, typename R, int TB = kBlock, int FLUX = -1>
 __global__ void __launch_bounds__((AmrFluxShape<DIM, M, TB>::BLOCK))
 k_amr_flux(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, double* __restrict__ fbuf,
            WsHeader* hdr) {
@@ -526,9 +526,9 @@ k_amr_flux(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, double* __res
       }
       double Fpt[NV];
       if (side)
-        numerical_flux<SYS, DIM>(qm, qp, k, mp, c, Fpt);
+        numerical_flux<SYS, DIM, FLUX>(qm, qp, k, mp, c, Fpt);
       else
-        numerical_flux<SYS, DIM>(qp, qm, k, mp, c, Fpt);
+        numerical_flux<SYS, DIM, FLUX>(qp, qm, k, mp, c, Fpt);
       double wtp = c.w[s];
       {
         const int tt[2] = {tb % n, tb / n};

@@ -204,8 +204,13 @@ class AmrImpl final : public AmrImplBase {
                                 const AmrConsts& ac, hipStream_t st) {
     using Sh = AmrFluxShape<DIM, M, TB>;
     const unsigned nb = (unsigned)((lv.nact + Sh::CPB - 1) / Sh::CPB);
-    hipLaunchKernelGGL((k_amr_flux<DIM, M, SYS, R, TB>), dim3(nb), dim3(Sh::BLOCK), 0, st, a,
-                       lv.mp, c, ac, lv.fbuf, lv.hdr);
+    // one instantiation per flux (only Euler has the Osher-type flux)
+    if (SYS == 1 && lv.mp.flux == 1)
+      hipLaunchKernelGGL((k_amr_flux<DIM, M, SYS, R, TB, 1>), dim3(nb), dim3(Sh::BLOCK), 0, st,
+                         a, lv.mp, c, ac, lv.fbuf, lv.hdr);
+    else
+      hipLaunchKernelGGL((k_amr_flux<DIM, M, SYS, R, TB, 0>), dim3(nb), dim3(Sh::BLOCK), 0, st,
+                         a, lv.mp, c, ac, lv.fbuf, lv.hdr);
     return hipGetLastError();
   }
 

@@ -169,9 +169,16 @@ k_face2d_batch(const SolveDesc* __restrict__ ds, int ns, DevConsts c) {
   const SolveClock* ck = d.clock;
   if (!ck->active) return;
   const int lb = (int)(blockIdx.x - d.face_block0);
-  face2d_tile<M, SYS, TR>(lb % d.ftiles_x, lb / d.ftiles_x, static_cast<const TR*>(d.traces),
-                          d.u[ck->cur & 1], d.u[(ck->cur + 1) & 1], d.mp.ld, &ck->dt, d.mp, c,
-                          d.hdr);
+  // the same flux instantiations as the single-solve face kernel, so a
+  // solve's result is bitwise that of the step loop (uniform per block)
+  if (SYS == 1 && d.mp.flux == 1)
+    face2d_tile<M, SYS, TR, 1>(lb % d.ftiles_x, lb / d.ftiles_x, static_cast<const TR*>(d.traces),
+                               d.u[ck->cur & 1], d.u[(ck->cur + 1) & 1], d.mp.ld, &ck->dt, d.mp,
+                               c, d.hdr);
+  else
+    face2d_tile<M, SYS, TR, 0>(lb % d.ftiles_x, lb / d.ftiles_x, static_cast<const TR*>(d.traces),
+                               d.u[ck->cur & 1], d.u[(ck->cur + 1) & 1], d.mp.ld, &ck->dt, d.mp,
+                               c, d.hdr);
 }
 
 }  // namespace ader

@@ -397,7 +397,8 @@ k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
 constexpr int kFaceTX = 16, kFaceTY = 4;
 
 // One 16 x 4 tile of the face kernel (every thread of the block calls it).
-template <int M, int SYS, typename TR>
+// FLUX: -1 numerical flux chosen at run time, 0 Rusanov, 1 Osher-type.
+template <int M, int SYS, typename TR, int FLUX = -1>
 __device__ __forceinline__ void face2d_tile(int tile_x, int tile_y, const TR* __restrict__ traces,
                                             const double* __restrict__ u_in,
                                             double* __restrict__ u_out, int64_t ld,
@@ -471,7 +472,7 @@ __device__ __forceinline__ void face2d_tile(int tile_x, int tile_y, const TR* __
         }
       }
       double Fpt[NV];
-      numerical_flux<SYS, 2>(qL, qR, k, mp, c, Fpt);
+      numerical_flux<SYS, 2, FLUX>(qL, qR, k, mp, c, Fpt);
 #pragma unroll
       for (int v = 0; v < NV; ++v) Fp[v] = wts * Fpt[v];
     }
@@ -518,12 +519,13 @@ __device__ __forceinline__ void face2d_tile(int tile_x, int tile_y, const TR* __
   (void)C;
 }
 
-template <int M, int SYS, typename TR>
+template <int M, int SYS, typename TR, int FLUX = -1>
 __global__ void __launch_bounds__(kBlock)
 k_face2d(const TR* __restrict__ traces, const double* __restrict__ u_in,
          double* __restrict__ u_out, int64_t ld, const double* __restrict__ dt_dev,
          MeshParams mp, DevConsts c, WsHeader* hdr) {
-  face2d_tile<M, SYS, TR>(blockIdx.x, blockIdx.y, traces, u_in, u_out, ld, dt_dev, mp, c, hdr);
+  face2d_tile<M, SYS, TR, FLUX>(blockIdx.x, blockIdx.y, traces, u_in, u_out, ld, dt_dev, mp, c,
+                                hdr);
 }
 
 }  // namespace ader

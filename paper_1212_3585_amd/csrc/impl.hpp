@@ -201,8 +201,13 @@ struct Impl final : ImplBase {
     {
       StageTimer timer(&p.prof, ADER_STAGE_FLUX, st);
       dim3 grid((p.mp.n[0] + kFaceTX - 1) / kFaceTX, (p.mp.n[1] + kFaceTY - 1) / kFaceTY);
-      hipLaunchKernelGGL((k_face2d<M, SYS, R>), grid, dim3(kBlock), 0, st, (const R*)tr, u_in,
-                         u_out, ld, dt, mp, p.dc, hdr);
+      // one instantiation per flux (only Euler has the Osher-type flux)
+      if (SYS == 1 && p.mp.flux == 1)
+        hipLaunchKernelGGL((k_face2d<M, SYS, R, 1>), grid, dim3(kBlock), 0, st, (const R*)tr,
+                           u_in, u_out, ld, dt, mp, p.dc, hdr);
+      else
+        hipLaunchKernelGGL((k_face2d<M, SYS, R, 0>), grid, dim3(kBlock), 0, st, (const R*)tr,
+                           u_in, u_out, ld, dt, mp, p.dc, hdr);
     }
     return hipGetLastError();
   }

@@ -296,7 +296,10 @@ __device__ __forceinline__ void euler_abs_jacobian_apply(const double (&q)[DIM +
 // Numerical flux between traces qL | qR across a face normal to axis k:
 // Rusanov (eq. rusanov) or the Osher-type flux (eq. osher, Euler only; for
 // linear advection it equals the upwind flux, which Rusanov already is).
-template <int SYS, int DIM>
+// FLUX = -1 selects by mp.flux at run time; 0 / 1 fix Rusanov / Osher at
+// compile time (a kernel instantiated for one flux does not carry the
+// registers of the other).
+template <int SYS, int DIM, int FLUX = -1>
 __device__ __forceinline__ void numerical_flux(const double (&qL)[NVars<SYS, DIM>::v],
                                                const double (&qR)[NVars<SYS, DIM>::v], int k,
                                                const MeshParams& mp, const DevConsts& c,
@@ -306,8 +309,8 @@ __device__ __forceinline__ void numerical_flux(const double (&qL)[NVars<SYS, DIM
   double fL[NV], fR[NV], sL, sR;
   phys_flux_dir<SYS, DIM>(qL, k, mp.gamma, mp.ch, adv, fL, sL);
   phys_flux_dir<SYS, DIM>(qR, k, mp.gamma, mp.ch, adv, fR, sR);
-  if constexpr (SYS == 1) {
-    if (mp.flux == 1) {
+  if constexpr (SYS == 1 && FLUX != 0) {
+    if (FLUX == 1 || mp.flux == 1) {
       double dq[NV], acc[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
