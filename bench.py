@@ -204,6 +204,7 @@ def amr_leg(ader, label, dim, n0, r, L, M, ic, precision, steps, cfl=0.5, regrid
     active-cell substeps per second over 'steps' level-0 steps on the static
     mesh; then 'regrid_steps' steps each followed by a regrid (refine above
     chi 0.2, recoarsen below 0.1), regrid time included in that rate."""
+    import numpy as np
     tol = 1e-14 if precision == ader.PREC_FP64 else 1e-6
     prob = ader.Problem(dim=dim, M=M, n=(n0,) * dim + (1,) * (3 - dim), lo=(-1.0,) * 3,
                         hi=(1.0,) * 3, bc=(ader.BC_TRANSMISSIVE,) * 3, cfl=cfl,
@@ -216,6 +217,17 @@ def amr_leg(ader, label, dim, n0, r, L, M, ic, precision, steps, cfl=0.5, regrid
     A.build()
     build_s = time.perf_counter() - t0
     counts = [A.counts(l) for l in range(L + 1)]
+
+    def totals():
+        """Integral of each conserved variable over the active cells."""
+        tot = 0.0
+        for l in range(L + 1):
+            U, stat = A.level(l)
+            vol = (2.0 / (n0 * r ** l)) ** dim
+            tot = tot + vol * U[:, stat == 0].sum(axis=1)
+        return tot
+
+    tot0 = totals()
     A.step(1e9)                      # warm-up (sets the level steps)
     pb, fb, tune_ms = A.tune(reps=3)  # launch shapes of the predictor and the face fluxes
     A.step(1e9)                      # records the graph with the tuned shapes
@@ -253,6 +265,11 @@ def amr_leg(ader, label, dim, n0, r, L, M, ic, precision, steps, cfl=0.5, regrid
             "cell_updates": cu, "seconds": el, "cell_updates_per_s": cu / el,
             "regrid_ms_avg": t_regrid / regrid_steps * 1e3,
             "levels_after": [A.counts(l) for l in range(L + 1)], "status_flags": st["flags"]}
+    # conservation over every step of the leg (no wave reaches the boundary
+    # in this time): relative drift of each conserved variable's total
+    tot1 = totals()
+    scale = float(np.abs(tot0).max())
+    out["conservation_max_rel_drift"] = float(np.abs(tot1 - tot0).max() / scale)
     A.close()
     return out
 
