@@ -218,3 +218,40 @@ def test_amr_factors_and_depths(ader, r, L, M):
     A.step(1.0)
     _compare(H, A)
     assert A.stats()["flags"] == 0
+
+
+@pytest.mark.parametrize("system,flux", [("mhd", "rusanov"), ("linadv", "rusanov"),
+                                         ("euler", "osher")])
+def test_amr_other_systems_and_fluxes(ader, system, flux):
+    say(f"AMR 2D {system} ({flux}) r=3 L=1 M=2: 2 level-0 steps vs oracle, then a regrid")
+    from gpu_helpers import make_pair
+    from oracle.amr import Hierarchy, regrid
+    n0, r, L = 8, 3, 1
+    op, gp = make_pair(ader, 2, 2, (n0, n0), (0.0, 0.0), (1.0, 1.0), system=system, flux=flux)
+    nf = n0 * r
+    if system == "mhd":
+        Uf = wl.orszag_tang(nf, seed=5)
+    elif system == "linadv":
+        Uf = wl.perturbed_smooth_euler((nf, nf), 9)[:1]
+    else:
+        Uf = wl.perturbed_smooth_euler((nf, nf), 9)
+    Us = _levels_from_fine(Uf, r, L)
+    F0 = np.zeros((n0, n0), bool)
+    F0[3:5, 2:6] = True
+    H = Hierarchy(op, r, L, Us, flags=[F0])
+    A = ader.Amr(gp, r=r, max_level=L)
+    for l in range(L + 1):
+        A.set_level(l, Us[l])
+    A.set_flags(0, F0)
+    A.build()
+    for _ in range(2):
+        amr_step(H, 0.0, 1.0)
+        A.step(1.0)
+    _compare(H, A)
+    G0 = np.roll(F0, 1, axis=1)
+    A.set_flags(0, G0)
+    assert regrid(H, flags=[G0]) == A.regrid()
+    amr_step(H, 0.0, 1.0)
+    A.step(1.0)
+    _compare(H, A)
+    assert A.stats()["flags"] == 0
