@@ -455,8 +455,8 @@ ader_status ader_profile_end(ader_plan plan, double* stage_ms, int64_t* stage_la
       stage_ms[r.stage] += ms;
       stage_launches[r.stage] += 1;
     }
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
   }
   pr.recs.clear();
   pr.on = false;

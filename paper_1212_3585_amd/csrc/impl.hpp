@@ -16,6 +16,9 @@ inline unsigned int blocks_for(int64_t threads, int per_block = kBlock) {
 }
 
 template <int DIM, int M, int SYS, typename R>
+LevelLayout level_layout_for(const PlanData& p, int64_t npred);
+
+template <int DIM, int M, int SYS, typename R>
 struct Impl final : ImplBase {
   static constexpr int n = M + 1;
   static constexpr int NS = Pow<n, DIM>::v;
