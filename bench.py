@@ -295,6 +295,33 @@ def amr_legs(ader, wl):
     return out
 
 
+def vortex_leg(ader, wl, torch):
+    """Isentropic vortex, 20x20, M = 2, periodic [0,10]^2, CFL 0.9, to t = 1:
+    per-step latency (a step = CFL kernel + cell kernel + face kernel, with
+    the host reading dt back) and the error against the exact solution, the
+    initial state translated by (t, t)."""
+    import numpy as np
+    n, t_end = 20, 1.0
+    prob = ader.Problem(dim=2, M=2, n=(n, n, 1), lo=(0, 0, 0), hi=(10, 10, 1), cfl=0.9)
+    s = ader.Solver(prob)
+    u0 = torch.tensor(wl.to_soa(wl.isentropic_vortex(n)), dtype=torch.float64, device="cuda")
+    s.run(u0, t_end)                                   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, t, steps = s.run(u0, t_end)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    got = wl.from_soa(u.cpu().numpy(), (n, n))
+    exact = wl.isentropic_vortex(n, t=t)
+    flags, _ = s.read_status()
+    return {"workload": "2D Euler isentropic vortex (eps 5), 20x20 on periodic [0,10]^2, M = 2, "
+                        "Rusanov, CFL 0.9, to t = 1, fp64",
+            "steps": steps, "t": t, "ms_per_step": wall / steps * 1e3,
+            "l1_vs_exact": float(np.abs(got - exact).sum() / np.abs(exact).sum()),
+            "l1_rho_vs_exact": float(np.abs(got[0] - exact[0]).sum() / np.abs(exact[0]).sum()),
+            "status_flags": flags}
+
+
 def serving_leg(ader, wl, count, hbm_bytes=16 << 30, seed=4):
     """Closed loop (all requests at t = 0) for the maximum rate, then Poisson
     arrivals (seed 5) at 0.5 and 0.9 of it: p50 / p99 latency and solves/s."""
@@ -467,6 +494,8 @@ def main():
         for k in ("fp64", "fp32"):
             l1[k] = float(np.abs(outs[k] - ref).sum() / np.abs(ref).sum())
 
+    log("bench: isentropic vortex 20^2 (latency, error against the exact solution)")
+    vortex = vortex_leg(ader, wl, torch)
     serving = None
     if args.serve_requests > 0:
         serving = serving_leg(ader, wl, args.serve_requests)
@@ -515,6 +544,7 @@ def main():
                      "flops_per_launch": flops_launch,
                      "avg_launch_ms": avg_s * 1e3},
         "cpu_baseline": cpu,
+        "vortex": vortex,
         "serving": serving,
         "amr": amr,
     }

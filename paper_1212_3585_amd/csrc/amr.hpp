@@ -9,7 +9,6 @@
 //   k_amr_average   virtual mothers = mean of their r^d children (eq. average)
 //   k_amr_prepare   one launch per level substep for the averaging, the
 //                   projection and the clearing of the finer level's memory
-//   k_amr_weno2d    both WENO passes of a 2D level's active cells
 //   k_amr_weno_x    first WENO pass of the active cells, stencil indices from
 //                   the dense grid; later passes and the predictor are the
 //                   level-list kernels (level.hpp, predictor kernels)
@@ -300,43 +299,6 @@ k_amr_prepare(AmrPrepArgs a, AmrConsts ac, WsHeader* hdr) {
     if (j < a.nvcf * E) a.mem_f[(j / a.nvcf) * a.ldf + a.vcf[j % a.nvcf]] = 0.0;
   }
   block_report(0u, flags, hdr);
-}
-
-// Both WENO passes of a 2D level's active cells in one launch, one thread per
-// (cell, variable): the 2M+1 x lines of the stencil, then the n y lines, the
-// same line operations as the two-pass kernels.  wh[(p NV + v) n^2 + px + n py].
-template <int M, int NV>
-__global__ void __launch_bounds__(kBlock)
-k_amr_weno2d(const double* __restrict__ u, int64_t ld, const int32_t* __restrict__ act,
-             int64_t nact, MeshParams mp, double* __restrict__ wh, DevConsts c) {
-  constexpr int n = M + 1;
-  constexpr int S = 2 * M + 1;
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t >= nact * NV) return;
-  const int v = (int)(t % NV);
-  const int64_t p = t / NV;
-  int cc[3];
-  dense_coords<2>(act[p], mp.n, cc);
-  double xo[S][n];
-#pragma unroll
-  for (int oy = 0; oy < S; ++oy) {
-    const int gy = bc_map(cc[1] + oy - M, mp.n[1], mp.bc[1]);
-    const int64_t row = (int64_t)v * ld + (int64_t)mp.n[0] * gy;
-    double vals[S];
-#pragma unroll
-    for (int o = 0; o < S; ++o) vals[o] = u[row + bc_map(cc[0] + o - M, mp.n[0], mp.bc[0])];
-    weno_line<M>(vals, c, xo[oy]);
-  }
-  double* dp = wh + (p * NV + v) * n * n;
-#pragma unroll
-  for (int px = 0; px < n; ++px) {
-    double vals[S], w[n];
-#pragma unroll
-    for (int o = 0; o < S; ++o) vals[o] = xo[o][px];
-    weno_line<M>(vals, c, w);
-#pragma unroll
-    for (int q = 0; q < n; ++q) dp[px + n * q] = w[q];
-  }
 }
 
 // First WENO pass (along x) of the active cells; the (2M+1)^d stencil is

@@ -79,7 +79,9 @@ class AmrImpl final : public AmrImplBase {
   // the generic predictor's LDS: DIM NV block values of R (at most 64 KiB)
   template <int BLK>
   static constexpr bool pred_fits() {
-    return (size_t)DIM * NV * BLK * sizeof(R) + 2048 <= 65536;
+    // fluxes of the block, plus (2D) the block's fused reconstruction
+    constexpr size_t wsh = DIM == 2 ? (size_t)(BLK / Pow<n, DIM>::v) * NV * Pow<n, DIM>::v * 8 : 0;
+    return (size_t)DIM * NV * BLK * sizeof(R) + wsh + 2048 <= 65536;
   }
 
   bool pred_block_ok(int block) const override {
@@ -100,9 +102,20 @@ class AmrImpl final : public AmrImplBase {
     } else {
       constexpr int NS = Pow<n, DIM>::v;
       const int64_t np = lv.nact;
-      hipLaunchKernelGGL((k_predict<DIM, M, SYS, R, R, BLK>),
-                         dim3((unsigned)((np + BLK / NS - 1) / (BLK / NS))), dim3(BLK), 0, st,
-                         (const double*)lv.wh, static_cast<R*>(lv.qh), np, dt, lv.mp, c, lv.hdr);
+      const dim3 grid((unsigned)((np + BLK / NS - 1) / (BLK / NS)));
+      if constexpr (DIM == 2) {  // reconstruction fused into the predictor
+        FuseWeno fw;
+        fw.u = lv.u;
+        fw.ld = lv.ncells;
+        fw.act = lv.act;
+        hipLaunchKernelGGL((k_predict<DIM, M, SYS, R, R, BLK, true>), grid, dim3(BLK), 0, st,
+                           (const double*)nullptr, static_cast<R*>(lv.qh), np, dt, lv.mp, c,
+                           lv.hdr, fw);
+      } else {
+        hipLaunchKernelGGL((k_predict<DIM, M, SYS, R, R, BLK>), grid, dim3(BLK), 0, st,
+                           (const double*)lv.wh, static_cast<R*>(lv.qh), np, dt, lv.mp, c,
+                           lv.hdr);
+      }
       return hipGetLastError();
     }
   }
@@ -115,11 +128,10 @@ class AmrImpl final : public AmrImplBase {
     double* pass0 = lv.wa;
     double* pass1 = DIM == 2 ? lv.wh : lv.wb;
     if constexpr (DIM == 2) {
+      // 2D: the predictor kernels reconstruct their own cells (fused)
       (void)flags;
       (void)pass0;
       (void)pass1;
-      hipLaunchKernelGGL((k_amr_weno2d<M, NV>), dim3(amr_blocks(np * NV)), dim3(kBlock), 0, st,
-                         (const double*)lv.u, lv.ncells, lv.act, np, lv.mp, lv.wh, c);
     } else {
     hipLaunchKernelGGL((k_amr_weno_x<DIM, M, NV>), dim3(amr_blocks(np * NV * Pow<S, DIM - 1>::v)),
                        dim3(kBlock), 0, st, lv.u, lv.ncells, lv.act, np, lv.mp, pass0, c);
@@ -135,9 +147,14 @@ class AmrImpl final : public AmrImplBase {
     }
     R* qh = static_cast<R*>(lv.qh);
     if constexpr (DIM == 2 && std::is_same<R, double>::value) {
-      hipLaunchKernelGGL((k_predict_mfma2d<M, SYS, R>),
+      FuseWeno fw;
+      fw.u = lv.u;
+      fw.ld = lv.ncells;
+      fw.act = lv.act;
+      hipLaunchKernelGGL((k_predict_mfma2d<M, SYS, R, true>),
                          dim3((unsigned)((np + 4 * (kBlock / 64) - 1) / (4 * (kBlock / 64)))),
-                         dim3(kBlock), 0, st, (const double*)lv.wh, qh, np, dt, lv.mp, c, lv.hdr);
+                         dim3(kBlock), 0, st, (const double*)nullptr, qh, np, dt, lv.mp, c,
+                         lv.hdr, fw);
     } else {
       (void)qh;
       switch (sh.pred_block) {

@@ -440,6 +440,63 @@ __device__ __forceinline__ void weno_line(const double (&v)[2 * M + 1], const De
   }
 }
 
+// Reconstruction fused into a predictor (2D level lists): the block first
+// reconstructs its own cells from the dense grid into LDS.  u, ld: the level's
+// averages; act: the dense indices of the predicted cells.
+struct FuseWeno {
+  const double* u = nullptr;
+  int64_t ld = 0;
+  const int32_t* act = nullptr;
+};
+
+// Both WENO passes of one 2D cell (cx, cy) and variable v from the dense grid
+// (boundary maps of mp): the 2M+1 x lines, then the n y lines, the same line
+// operations as the two-pass kernels.  out[px + n py].
+template <int M>
+__device__ __forceinline__ void weno2d_cell(const double* __restrict__ u, int64_t ld, int cx,
+                                            int cy, int v, const MeshParams& mp,
+                                            const DevConsts& c, double* out) {
+  constexpr int n = M + 1;
+  constexpr int S = 2 * M + 1;
+  double xo[S][n];
+#pragma unroll
+  for (int oy = 0; oy < S; ++oy) {
+    const int gy = bc_map(cy + oy - M, mp.n[1], mp.bc[1]);
+    const int64_t row = (int64_t)v * ld + (int64_t)mp.n[0] * gy;
+    double vals[S];
+#pragma unroll
+    for (int o = 0; o < S; ++o) vals[o] = u[row + bc_map(cx + o - M, mp.n[0], mp.bc[0])];
+    weno_line<M>(vals, c, xo[oy]);
+  }
+#pragma unroll
+  for (int px = 0; px < n; ++px) {
+    double vals[S], w[n];
+#pragma unroll
+    for (int o = 0; o < S; ++o) vals[o] = xo[o][px];
+    weno_line<M>(vals, c, w);
+#pragma unroll
+    for (int q = 0; q < n; ++q) out[px + n * q] = w[q];
+  }
+}
+
+// The prologue of a fused predictor block: cells first_cell + lc, lc < cpb,
+// reconstructed into sWh[(lc NV + v) n^2 + node] by the block's threads.
+template <int M, int NV>
+__device__ __forceinline__ void weno2d_block(const FuseWeno& fw, int64_t first_cell, int cpb,
+                                             int64_t ncells, const MeshParams& mp,
+                                             const DevConsts& c, double* sWh) {
+  constexpr int NS = (M + 1) * (M + 1);
+  for (int item = threadIdx.x; item < cpb * NV; item += blockDim.x) {
+    const int lc = item / NV, v = item % NV;
+    const int64_t cell = first_cell + lc;
+    if (cell >= ncells) continue;
+    const int32_t idx = fw.act[cell];
+    const int cx = (int)(idx % mp.n[0]), cy = (int)(idx / mp.n[0]);
+    weno2d_cell<M>(fw.u, fw.ld, cx, cy, v, mp, c, sWh + (lc * NV + v) * NS);
+  }
+  __syncthreads();
+}
+
 // WENO pass along axis K.  The input field holds 'nin' nodal components per
 // variable (1 for the averages; n for the y pass; n^2 for the z pass), laid
 // out src[(v * nin + comp) * sld + cell].  Each thread handles one
@@ -520,10 +577,12 @@ __device__ __forceinline__ void pick_row(const DevConsts& c, int a, R (&row)[n])
 // Space-time predictor of 'ncells' cells whose nodal reconstructions are
 // wh[(cell * NV + v) * NS + a].  Output qh[(cell * NV + v) * NST + a + NS * s]
 // in type OUT.  One lane per spatial node a; CPB cells per BLK-thread block.
-template <int DIM, int M, int SYS, typename R, typename OUT, int BLK = kBlock>
+template <int DIM, int M, int SYS, typename R, typename OUT, int BLK = kBlock,
+          bool FUSE = false>
 __global__ void __launch_bounds__(BLK)
 k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
-          const double* __restrict__ dt_dev, MeshParams mp, DevConsts c, WsHeader* hdr) {
+          const double* __restrict__ dt_dev, MeshParams mp, DevConsts c, WsHeader* hdr,
+          FuseWeno fw = FuseWeno()) {
   constexpr int n = M + 1;
   constexpr int NS = Pow<n, DIM>::v;
   constexpr int NST = NS * n;
@@ -557,10 +616,21 @@ k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
 #pragma unroll
   for (int k = 0; k < DIM; ++k) pick_row<n, R>(c, ak[k], drow[k]);
 
+  // w_hat: from the global reconstruction, or (FUSE, 2D) from the block's own
+  // reconstruction in LDS
+  const double* wsrc = wh;
+  int64_t wcell = cell;
+  if constexpr (FUSE) {
+    static_assert(DIM == 2, "fused reconstruction in 2D only");
+    __shared__ double sWh[CPB * NV * NS];
+    weno2d_block<M, NV>(fw, (int64_t)blockIdx.x * CPB, CPB, ncells, mp, c, sWh);
+    wsrc = sWh;
+    wcell = lc;
+  }
   R w[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v)
-    w[v] = active ? (R)wh[(cell * NV + v) * NS + a] : (v == 0 || v == NV - 1 ? R(1) : R(0));
+    w[v] = active ? (R)wsrc[(wcell * NV + v) * NS + a] : (v == 0 || v == NV - 1 ? R(1) : R(0));
   R q[NV][n];
 #pragma unroll
   for (int v = 0; v < NV; ++v)

@@ -47,11 +47,11 @@ __device__ __forceinline__ double cell_max(double x) {
   return x;
 }
 
-template <int M, int SYS, typename OUT>
+template <int M, int SYS, typename OUT, bool FUSE = false>
 __global__ void __launch_bounds__(kBlock)
 k_predict_mfma2d(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
                  const double* __restrict__ dt_dev, MeshParams mp, DevConsts c,
-                 WsHeader* hdr) {
+                 WsHeader* hdr, FuseWeno fw = FuseWeno()) {
   constexpr int DIM = 2;
   constexpr int n = M + 1;
   constexpr int NS = n * n;
@@ -76,10 +76,21 @@ k_predict_mfma2d(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t nc
   const double gamma = mp.gamma;
   const double adv[3] = {mp.adv[0], mp.adv[1], mp.adv[2]};
 
+  // w_hat: from the global reconstruction, or (FUSE) from the block's own
+  // reconstruction in LDS
+  const double* wsrc = wh;
+  int64_t wcell = cell;
+  if constexpr (FUSE) {
+    constexpr int CPB = 4 * (kBlock / 64);
+    __shared__ double sWh[CPB * NV * NS];
+    weno2d_block<M, NV>(fw, (int64_t)blockIdx.x * CPB, CPB, ncells, mp, c, sWh);
+    wsrc = sWh;
+    wcell = wave * 4 + b1;
+  }
   double w[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v)
-    w[v] = active ? wh[(cell * NV + v) * NS + a] : (v == 0 || v == NV - 1 ? 1.0 : 0.0);
+    w[v] = active ? wsrc[(wcell * NV + v) * NS + a] : (v == 0 || v == NV - 1 ? 1.0 : 0.0);
   double q[NV][n];
 #pragma unroll
   for (int v = 0; v < NV; ++v)
