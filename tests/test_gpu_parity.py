@@ -124,7 +124,12 @@ def test_predictor_parity(ader, dim, M, system, ncells):
     (2, 0, (16, 16), "periodic", "euler"),
     (3, 2, (9, 8, 7), "transmissive", "euler"),
     (3, 1, (8, 6, 5), "periodic", "euler"),
-    (3, 3, (6, 5, 7), "periodic", "euler")])
+    (3, 3, (6, 5, 7), "periodic", "euler"),
+    # meshes narrower than the (2M+1)-cell stencil: it wraps or clamps
+    (2, 3, (3, 5), "periodic", "euler"),
+    (2, 2, (1, 8), "transmissive", "euler"),
+    (2, 1, (2, 2), "periodic", "euler"),
+    (3, 2, (2, 3, 2), "periodic", "euler")])
 def test_step_parity(ader, dim, M, n, bc, system):
     say(f"step dim={dim} M={M} n={n} bc={bc} {system}")
     if system == "euler":
