@@ -211,7 +211,7 @@ __device__ __forceinline__ void cell2d_tile(int tile_x, int tile_y, const double
   const double dval = pick_entry<n>(c.dmat, b0, b2);
   const double mx = (dt / mp.dx[0]) * dval;
   const double my = (dt / mp.dx[1]) * dval;
-  const double idv = (b0 == b2) ? 1.0 : 0.0;
+  const int taddr = transpose_addr(lane);
   float cxm[4], cyr[4];
   xor_row<n>(c, px, dt / mp.dx[0], cxm);
   ror_row<n>(c, py, dt / mp.dx[1], cyr);
@@ -257,7 +257,7 @@ __device__ __forceinline__ void cell2d_tile(int tile_x, int tile_y, const double
       for (int v = 0; v < NV; ++v) {
         if constexpr (kMatrix) {
           const double rx = __builtin_amdgcn_mfma_f64_4x4x4f64(mx, F[0][v], 0.0, 0, 0, 0);
-          const double gt = __builtin_amdgcn_mfma_f64_4x4x4f64(F[1][v], idv, 0.0, 0, 0, 0);
+          const double gt = lane_transpose(F[1][v], taddr);
           Rs[v][s] = __builtin_amdgcn_mfma_f64_4x4x4f64(gt, my, rx, 0, 0, 0);
         } else {
           Rs[v][s] = xor_line_b0(F[0][v], cxm) + ror_line_b1(F[1][v], cyr);
@@ -336,7 +336,7 @@ __device__ __forceinline__ void cell2d_tile(int tile_x, int tile_y, const double
 #pragma unroll
       for (int s = 0; s < n; ++s) {
         const double tx = __builtin_amdgcn_mfma_f64_4x4x4f64(ex, q[v][s], 0.0, 0, 0, 0);
-        const double qt = __builtin_amdgcn_mfma_f64_4x4x4f64(q[v][s], idv, 0.0, 0, 0, 0);
+        const double qt = lane_transpose(q[v][s], taddr);
         const double ty = __builtin_amdgcn_mfma_f64_4x4x4f64(qt, ey, 0.0, 0, 0, 0);
         if (cell_ok) {
           if (b2 < 2 && b0 < n)  // x face b2 (0 low, 1 high), transverse node b0

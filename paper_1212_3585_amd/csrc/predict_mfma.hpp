@@ -12,9 +12,10 @@
 //   * nodal fluxes f*, g* at the lane's n space-time nodes (lane-local);
 //   * x derivative: data as operand B against (dt/dx) D in operand A
 //     (contracts p_x on b2, result stays in the home layout);
-//   * y derivative: a transpose (data as operand A against the identity)
-//     moves p_y to b2, then data as operand A against (dt/dy) D^T contracts
-//     p_y and returns the home layout, accumulated onto the x part;
+//   * y derivative: a lane transpose (b0 <-> b2 inside each cell, through
+//     the LDS crossbar, not on the matrix pipe) moves p_y to b2, then data
+//     as operand A against (dt/dy) D^T contracts p_y and returns the home
+//     layout, accumulated onto the x part;
 //   * time product with (time factor of K^1)^-1 diag(w) and the update
 //     q = w_hat - ... are lane-local.
 // A cell stops counting iterations when its largest update falls below
@@ -47,6 +48,21 @@ __device__ __forceinline__ double cell_max(double x) {
   return x;
 }
 
+// Byte address for lane_transpose: lane (b0, b1, b2) reads lane (b2, b1, b0).
+__device__ __forceinline__ int transpose_addr(int lane) {
+  return ((lane >> 4) | (lane & 0xC) | ((lane & 3) << 4)) << 2;
+}
+
+// Swaps the two node axes (b0 <-> b2) of every cell's 4 x 4 lanes with two
+// ds_bpermute (the LDS crossbar; no LDS memory is used).  An identity product
+// on the matrix cores would give the same values but hold the matrix pipe,
+// the kernel's bottleneck, for 16 cycles.  Every lane must be active.
+__device__ __forceinline__ double lane_transpose(double x, int addr) {
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(x));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+
 template <int M, int SYS, typename OUT, bool FUSE = false>
 __global__ void __launch_bounds__(kBlock)
 k_predict_mfma2d(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
@@ -72,7 +88,7 @@ k_predict_mfma2d(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t nc
   const double dval = pick_entry<n>(c.dmat, b0, b2);
   const double mx = (dt / mp.dx[0]) * dval;   // operand A: D[i=b0][k=b2]
   const double my = (dt / mp.dx[1]) * dval;   // operand B: D^T[k=b2][j=b0]
-  const double idv = (b0 == b2) ? 1.0 : 0.0;  // operand B: identity
+  const int taddr = transpose_addr(lane);
   const double gamma = mp.gamma;
   const double adv[3] = {mp.adv[0], mp.adv[1], mp.adv[2]};
 
@@ -118,7 +134,7 @@ k_predict_mfma2d(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t nc
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const double rx = __builtin_amdgcn_mfma_f64_4x4x4f64(mx, F[0][v], 0.0, 0, 0, 0);
-        const double gt = __builtin_amdgcn_mfma_f64_4x4x4f64(F[1][v], idv, 0.0, 0, 0, 0);
+        const double gt = lane_transpose(F[1][v], taddr);
         R[v][s] = __builtin_amdgcn_mfma_f64_4x4x4f64(gt, my, rx, 0, 0, 0);
       }
     }
