@@ -50,14 +50,16 @@ def predictor_flops_per_cell_iteration(dim, M, nv, euler=True):
 def weno_flops_per_line(M):
     """One 1D WENO reconstruction (eqs. rec.x, sigmas, omegas, weno).
 
-    per stencil: the n x n inverse (2 n^2), sigma as sum over alpha = 1..M of
-    Gauss-weighted squared derivatives at n nodes (M n (2 n + 3)), the weight
+    per stencil: the n x n inverse (2 n^2); sigma as the sum of the squared
+    Legendre coefficients of the derivatives alpha = 1..M, M (M + 1) / 2
+    coefficients of n products each (2 n + 2 per coefficient); the weight
     lambda / (sigma + eps)^8 (5); then the sum and normalisation of the
     weights (2 per stencil) and the combination (2 n per stencil).
     """
     n = M + 1
     nst = 3 if M % 2 == 0 else 4
-    return nst * (2 * n * n + M * n * (2 * n + 3) + 5) + 2 * nst + 2 * n * nst
+    nr = M * (M + 1) // 2
+    return nst * (2 * n * n + nr * (2 * n + 2) + 5) + 2 * nst + 2 * n * nst
 
 
 def cell_kernel_flops(dim, M, nv, picard_sweeps_total, ncells):

@@ -87,8 +87,6 @@ void fill_dev_consts(const RefConstants& r, int M, DevConsts* out) {
       c.tinvw[a][b] = (double)r.time_inv_w[a][b];
       c.dmat_f[a][b] = (float)r.dmat[a][b];
       c.tinvw_f[a][b] = (float)r.time_inv_w[a][b];
-      c.sigma[a][b] = (double)r.sigma[a][b];
-      for (int al = 0; al < M; ++al) c.dnode[al][a][b] = (double)r.dnode[al][a][b];
     }
   }
   for (int j = 0; j < kOsherNodes; ++j) {
@@ -99,6 +97,8 @@ void fill_dev_consts(const RefConstants& r, int M, DevConsts* out) {
     c.lam[s] = (double)r.lambda[s];
     for (int pp = 0; pp < n; ++pp)
       for (int e = 0; e < n; ++e) c.rec_inv[s][pp][e] = (double)r.rec_inv[s][pp][e];
+    for (int k = 0; k < r.nsig_rows; ++k)
+      for (int e = 0; e < n; ++e) c.sig_rows[s][k][e] = (double)r.sig_rows[s][k][e];
   }
 }
 

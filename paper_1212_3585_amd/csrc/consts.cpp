@@ -230,6 +230,38 @@ bool build_ref_constants(int M, RefConstants* out) {
       for (int m = 0; m < n; ++m)
         c.sigma[p][m] += integral(mul(dp[p], dp[m]), 0.0L, 1.0L);
   }
+
+  // Legendre polynomials orthonormal on [0, 1] (Gram-Schmidt on powers of t)
+  Poly leg[kMaxN];
+  for (int i = 0; i < n; ++i) {
+    Poly p;
+    p.c[i] = 1;
+    for (int j = 0; j < i; ++j) {
+      const long double pr = integral(mul(p, leg[j]), 0.0L, 1.0L);
+      for (int k = 0; k < kDeg; ++k) p.c[k] -= pr * leg[j].c[k];
+    }
+    const long double nrm = std::sqrt(integral(mul(p, p), 0.0L, 1.0L));
+    for (int k = 0; k < kDeg; ++k) p.c[k] /= nrm;
+    leg[i] = p;
+  }
+  // coefficient rows of the derivatives in that basis, then composed with
+  // each stencil's inverse reconstruction matrix
+  long double lrow[kMaxN * (kMaxN - 1) / 2][kMaxN];
+  int nr = 0;
+  for (int l = 0; l < n; ++l) dp[l] = psi[l];
+  for (int alpha = 1; alpha <= M; ++alpha) {
+    for (int l = 0; l < n; ++l) dp[l] = deriv(dp[l]);
+    for (int i = 0; i <= M - alpha; ++i, ++nr)
+      for (int p = 0; p < n; ++p) lrow[nr][p] = integral(mul(dp[p], leg[i]), 0.0L, 1.0L);
+  }
+  c.nsig_rows = nr;
+  for (int s = 0; s < c.nstencils; ++s)
+    for (int r = 0; r < nr; ++r)
+      for (int e = 0; e < n; ++e) {
+        long double acc = 0;
+        for (int p = 0; p < n; ++p) acc += lrow[r][p] * c.rec_inv[s][p][e];
+        c.sig_rows[s][r][e] = acc;
+      }
   return true;
 }
 

@@ -33,6 +33,13 @@ struct RefConstants {
   long double sigma[kMaxN][kMaxN];           // oscillation matrix
   // dnode[alpha-1][k][p] = d^alpha psi_p / dxi^alpha at node k, alpha = 1..M
   long double dnode[kMaxN - 1][kMaxN][kMaxN];
+  // sig_rows[s][r][e]: stencil s's averages -> the coefficients, in Legendre
+  // polynomials orthonormal on [0, 1], of the derivatives alpha = 1..M of its
+  // reconstruction (r runs over alpha, then over the degrees 0..M-alpha).
+  // By Parseval, the sum of their squares is the oscillation indicator of
+  // eq. sigmas.
+  int nsig_rows = 0;
+  long double sig_rows[kMaxN][kMaxN * (kMaxN - 1) / 2][kMaxN];
   // Gauss-Legendre rule on [0, 1] of the Osher path integral (eq. osher)
   long double path_s[kOsherNodes], path_w[kOsherNodes];
 };

@@ -104,19 +104,6 @@ __device__ __forceinline__ float row_max_f(float x) {
   return x;
 }
 
-// A separate view of the constant table for one phase of a kernel.  The
-// table sits in the constant kernel-argument segment; loads through the
-// same view in different phases would be merged by the compiler and the
-// values held in scalar registers across the phases, which spills them.
-// The offset is zero, but the compiler cannot see that (an empty asm
-// statement on a scalar register), so every phase re-reads its constants
-// from the scalar cache where it uses them.
-__device__ __forceinline__ const DevConsts& phase_view(const DevConsts& c) {
-  int zero = 0;
-  asm volatile("" : "+s"(zero));
-  return *reinterpret_cast<const DevConsts*>(reinterpret_cast<const char*>(&c) + zero);
-}
-
 // One 4 x TY tile (tile indices tile_x, tile_y) of the cell kernel.  Every
 // thread of the block calls it (it synchronises the block).
 template <int M, int SYS, int TY, typename R>
@@ -154,7 +141,6 @@ __device__ __forceinline__ void cell2d_tile(int tile_x, int tile_y, const double
   __syncthreads();
   // 2. x pass: one thread per (variable, staged row, tile column)
   for (int e = tid; e < NV * RY * TX; e += NT) {
-    const DevConsts& cw = phase_view(c);
     const int cx = e % TX;
     const int ry = (e / TX) % RY;
     const int v = e / (TX * RY);
@@ -162,14 +148,13 @@ __device__ __forceinline__ void cell2d_tile(int tile_x, int tile_y, const double
 #pragma unroll
     for (int o = 0; o < 2 * M + 1; ++o) vals[o] = sU[(v * RY + ry) * RX + cx + o];
     double w[n];
-    weno_line<M>(vals, cw, w);
+    weno_line<M>(vals, c, w);
 #pragma unroll
     for (int p = 0; p < n; ++p) sWx[((v * RY + ry) * TX + cx) * n + p] = w[p];
   }
   __syncthreads();
   // 3. y pass: one thread per (tile cell, variable, x node)
   for (int e = tid; e < TX * TY * NV * n; e += NT) {
-    const DevConsts& cw = phase_view(c);
     const int px = e % n;
     const int v = (e / n) % NV;
     const int cl = e / (n * NV);  // tile cell: cx + TX cy
@@ -178,7 +163,7 @@ __device__ __forceinline__ void cell2d_tile(int tile_x, int tile_y, const double
 #pragma unroll
     for (int o = 0; o < 2 * M + 1; ++o) vals[o] = sWx[((v * RY + cy + o) * TX + cx) * n + px];
     double w[n];
-    weno_line<M>(vals, cw, w);
+    weno_line<M>(vals, c, w);
 #pragma unroll
     for (int p = 0; p < n; ++p) sWh[(cl * NV + v) * NS + px + n * p] = w[p];
   }

@@ -32,8 +32,9 @@ struct DevConsts {
   double tinvw[4][4];  // (time factor of K^1)^-1 diag(w)
   double psi0[4], psi1[4], w[4];
   double rec_inv[4][4][4];  // per stencil: [p][e]
-  double sigma[4][4];
-  double dnode[3][4][4];  // [alpha-1][k][p]: alpha-th derivative of psi_p at node k
+  // [stencil][r][e]: stencil averages -> Legendre coefficients of the
+  // reconstruction's derivatives (orders 1..M); their squares sum to sigma
+  double sig_rows[4][6][4];
   double lam[4];
   double path_s[3], path_w[3];  // Osher path-integral Gauss-Legendre rule on [0, 1]
   float dmat_f[4][4];
@@ -404,20 +405,19 @@ __device__ __forceinline__ void weno_line(const double (&v)[2 * M + 1], const De
       for (int e = 0; e < n; ++e) acc += c.rec_inv[s][p][e] * v[base + e];
       ws[s][p] = acc;
     }
-    // sigma = sum_alpha int_0^1 (d^alpha w / dxi^alpha)^2 (eq. sigmas), the
-    // squared derivative values at the Gauss nodes summed with the weights
+    // sigma = sum_alpha int_0^1 (d^alpha w / dxi^alpha)^2 (eq. sigmas): each
+    // derivative expanded in Legendre polynomials orthonormal on [0, 1], so
+    // the integral of its square is the sum of its squared coefficients.
+    // The rows map the stencil averages straight to those coefficients and
+    // annihilate constants, so a large mean value does not cancel in sigma.
+    constexpr int NR = M * (M + 1) / 2;
     double sig = 0.0;
 #pragma unroll
-    for (int al = 0; al < M; ++al) {
-      double part = 0.0;
+    for (int r = 0; r < NR; ++r) {
+      double d = 0.0;
 #pragma unroll
-      for (int k = 0; k < n; ++k) {
-        double d = 0.0;
-#pragma unroll
-        for (int p = 0; p < n; ++p) d += c.dnode[al][k][p] * ws[s][p];
-        part += c.w[k] * (d * d);
-      }
-      sig += part;
+      for (int e = 0; e < n; ++e) d += c.sig_rows[s][r][e] * v[base + e];
+      sig += d * d;
     }
     double x = sig + 1.0e-14;
     x = x * x;  // ^2
