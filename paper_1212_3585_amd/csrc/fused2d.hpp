@@ -254,11 +254,7 @@ __device__ __forceinline__ void cell2d_tile(int tile_x, int tile_y, const double
     for (int v = 0; v < NV; ++v) {
 #pragma unroll
       for (int s = 0; s < n; ++s) {
-        R acc = R(0);
-#pragma unroll
-        for (int sp = 0; sp < n; ++sp)
-          acc += cget<R>(c.tinvw[s][sp], c.tinvw_f[s][sp]) * Rs[v][sp];
-        const R qn = w[v] - acc;
+        const R qn = time_update<n>(w[v], Rs[v], c.tinvw, c.tinvw_f, s);
         delta = fmax(delta, fabs(qn - qa[v][s]));
         qb[v][s] = qn;
       }

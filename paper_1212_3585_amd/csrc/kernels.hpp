@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace ader {
 
@@ -560,6 +561,29 @@ template <typename R> __device__ __forceinline__ R cget(const double& d, const f
 template <> __device__ __forceinline__ double cget<double>(const double& d, const float&) { return d; }
 template <> __device__ __forceinline__ float cget<float>(const double&, const float& f) { return f; }
 
+// New predictor value at time node s of eq. stdg.final:
+// w_hat - sum_sp A[s][sp] r[sp], with A the time factor of (K^1)^-1 diag(w).
+// fp64: one chain of fused multiply-adds that starts from w_hat.  fp32: the
+// sum first, then one subtraction.  A chain from w_hat rounds every step at
+// the scale of |w_hat|; the fp32 stopping threshold (1e-6 relative) is only
+// about eight ulps of that, and the sweeps would then stall above it.  In
+// fp64 the threshold (1e-14) is about 45 ulps.
+template <int n, typename R>
+__device__ __forceinline__ R time_update(R w_hat, const R (&r)[n], const double (&A)[4][4],
+                                         const float (&Af)[4][4], int s) {
+  if constexpr (std::is_same<R, double>::value) {
+    R q = w_hat;
+#pragma unroll
+    for (int sp = 0; sp < n; ++sp) q -= A[s][sp] * r[sp];
+    return q;
+  } else {
+    R acc = R(0);
+#pragma unroll
+    for (int sp = 0; sp < n; ++sp) acc += Af[s][sp] * r[sp];
+    return w_hat - acc;
+  }
+}
+
 // Select row 'a' of a 4x4 constant table into registers (unrolled selects, so
 // a lane-dependent row never turns into an indexed private-memory access).
 template <int n, typename R>
@@ -689,11 +713,7 @@ k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
     for (int v = 0; v < NV; ++v) {
 #pragma unroll
       for (int s = 0; s < n; ++s) {
-        R acc = R(0);
-#pragma unroll
-        for (int sp = 0; sp < n; ++sp)
-          acc += cget<R>(c.tinvw[s][sp], c.tinvw_f[s][sp]) * Racc[v][sp];
-        const R qn = w[v] - acc;
+        const R qn = time_update<n>(w[v], Racc[v], c.tinvw, c.tinvw_f, s);
         delta = fmax(delta, fabs(qn - q[v][s]));
         if (!done) q[v][s] = qn;
       }

@@ -143,10 +143,7 @@ k_predict_mfma2d(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t nc
     for (int v = 0; v < NV; ++v) {
 #pragma unroll
       for (int s = 0; s < n; ++s) {
-        double acc = 0.0;
-#pragma unroll
-        for (int sp = 0; sp < n; ++sp) acc += c.tinvw[s][sp] * R[v][sp];
-        const double qn = w[v] - acc;
+        const double qn = time_update<n>(w[v], R[v], c.tinvw, c.tinvw_f, s);
         delta = fmax(delta, fabs(qn - q[v][s]));
         // a cell that has converged keeps sweeping with its wavefront: each
         // further sweep moves q by less than the tolerance towards the fixed
