@@ -223,6 +223,26 @@ def test_mixed_precision_error_is_stated(ader, dim, M, n):
     assert err < 1e-5
 
 
+@pytest.mark.parametrize("precision,tol", [(0, 1e-14), (1, 1e-6)])
+def test_picard_stops_by_tolerance_on_kh_512(ader, precision, tol):
+    """The full-size shear layer (512^2, M = 3) over 25 steps: in both
+    forms every cell's Picard iteration ends by its tolerance, none at the
+    cap.  The fp32 threshold is only a few ulps of the state, so a time
+    update that rounds at the scale of w_hat on every term stalls above it."""
+    say(f"KH 512x512 M=3 precision {precision}: 25 steps, no cell at picard_max")
+    N = 512
+    _, gp = make_pair(ader, 2, 3, (N, N), (0, 0), (1, 1), precision=precision, tol=tol)
+    s = ader.Solver(gp)
+    s.clear_status()
+    _, _, steps = s.run(to_device(_kh(N)), 10.0, max_steps=25)
+    flags, iters = s.read_status()
+    assert steps == 25
+    assert flags == 0, flags
+    mean = iters / (N * N * steps)
+    print(f"mean Picard sweeps per cell: {mean:.2f}")
+    assert mean < (10 if precision else 16)
+
+
 def test_conservation_on_device(ader):
     say("conservation KH 96x80 M=3")
     U = _kh(96)[:, :, :80]
