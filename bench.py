@@ -62,13 +62,26 @@ def weno_flops_per_line(M):
     return nst * (2 * n * n + nr * (2 * n + 2) + 5) + 2 * nst + 2 * n * nst
 
 
+def predictor_flops_first_sweep(dim, M, nv, euler=True):
+    """Algorithmic flops of a cell's first Picard sweep, which starts from
+    q = w_hat at every time node: the physical fluxes, their dt/dx scaling
+    and the spatial derivative products at the n^d spatial nodes only; then
+    per space-time node and variable the product with the row sum of the
+    time matrix and the subtraction from w_hat (2)."""
+    n = M + 1
+    cflux = dim * dim + 5 * dim + 3 if euler else dim
+    return n ** dim * (cflux + dim * nv + nv * 2 * dim * n) + n ** (dim + 1) * nv * 2
+
+
 def cell_kernel_flops(dim, M, nv, picard_sweeps_total, ncells):
     """Algorithmic flops of one launch of the fused cell kernel: WENO
     (nv (1 + n) lines per cell in 2D), the Picard sweeps counted on the
-    device, and the four face traces (2 n flops per trace value)."""
+    device (every cell's first sweep at its reduced cost), and the four face
+    traces (2 n flops per trace value)."""
     n = M + 1
     weno = ncells * nv * (1 + n) * weno_flops_per_line(M)
-    picard = picard_sweeps_total * predictor_flops_per_cell_iteration(dim, M, nv)
+    picard = ((picard_sweeps_total - ncells) * predictor_flops_per_cell_iteration(dim, M, nv)
+              + ncells * predictor_flops_first_sweep(dim, M, nv))
     traces = ncells * 2 * dim * nv * n ** dim * 2 * n
     return weno + picard + traces
 

@@ -261,6 +261,41 @@ __device__ __forceinline__ void cell2d_tile(int tile_x, int tile_y, const double
     }
     return delta;
   };
+  // The first sweep starts from q = w_hat at every time node: one flux
+  // evaluation and one pair of derivative products serve all n nodes, and
+  // the time product reduces to the row sums of A (the same iterate as a
+  // general sweep, in exact arithmetic).
+  R arow[n];
+#pragma unroll
+  for (int s = 0; s < n; ++s) {
+    R acc = R(0);
+#pragma unroll
+    for (int sp = 0; sp < n; ++sp) acc += cget<R>(c.tinvw[s][sp], c.tinvw_f[s][sp]);
+    arow[s] = acc;
+  }
+  auto first_sweep = [&](R (&qb)[NV][n]) -> R {
+    R F[DIM][NV];
+    phys_fluxes<SYS, DIM, R>(w, gamma, ch, adv, F);
+    R delta = R(0);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      R r;
+      if constexpr (kMatrix) {
+        const double rx = __builtin_amdgcn_mfma_f64_4x4x4f64(mx, F[0][v], 0.0, 0, 0, 0);
+        const double gt = lane_transpose(F[1][v], taddr);
+        r = __builtin_amdgcn_mfma_f64_4x4x4f64(gt, my, rx, 0, 0, 0);
+      } else {
+        r = xor_line_b0(F[0][v], cxm) + ror_line_b1(F[1][v], cyr);
+      }
+#pragma unroll
+      for (int s = 0; s < n; ++s) {
+        const R qn = w[v] - arow[s] * r;
+        delta = fmax(delta, fabs(qn - w[v]));
+        qb[v][s] = qn;
+      }
+    }
+    return delta;
+  };
   // a cell has converged when none of its 16 lanes moved by more than thr;
   // returns true when every cell of the wavefront has
   auto converged = [&](R delta, int it) -> bool {
@@ -275,7 +310,8 @@ __device__ __forceinline__ void cell2d_tile(int tile_x, int tile_y, const double
   // exits are wavefront-uniform
   R q2[NV][n];
   bool in_q2 = false;
-  for (int it = 1; it <= mp.maxit; it += 2) {
+  const bool first_done = converged(first_sweep(q), 1);
+  for (int it = 2; !first_done && it <= mp.maxit; it += 2) {
     if (converged(sweep(q, q2), it)) {
       in_q2 = true;
       break;

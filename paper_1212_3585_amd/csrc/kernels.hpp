@@ -675,7 +675,73 @@ k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
   const R thr = (R)mp.tol * fmax(R(1), lc < CPB ? Bits<R>::val(shMag[lc]) : R(0));
   bool done = !active;
   int iters = 0;
-  for (int it = 1; it <= mp.maxit; ++it) {
+  // sum_k (dt/dx_k) D^(k) f_k at this lane's node from the fluxes F of the
+  // block's nodes at one time level (through LDS; synchronises the block)
+  auto derivative = [&](const R (&F)[DIM][NV], R (&out)[NV]) {
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) shF[(k * NV + v) * BLK + tid] = cour[k] * F[k][v];
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      R acc = R(0);
+      // lanes past the last whole cell of the block read nothing
+      if (lc < CPB) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          const int stride = k == 0 ? 1 : (k == 1 ? n : n * n);
+          const int base = tid - ak[k] * stride;
+#pragma unroll
+          for (int b = 0; b < n; ++b)
+            acc += drow[k][b] * shF[(k * NV + v) * BLK + base + b * stride];
+        }
+      }
+      out[v] = acc;
+    }
+    __syncthreads();
+  };
+  // records this sweep's largest change per cell; true when every cell of
+  // the block has converged (block-uniform)
+  auto converged = [&](R delta, int it) -> bool {
+    if (!done) atomicMax(&shDelta[lc], Bits<R>::of(delta));
+    __syncthreads();
+    if (!done) {
+      const R dcell = Bits<R>::val(shDelta[lc]);
+      if (dcell <= thr) {
+        done = true;
+        iters = it;
+      }
+    }
+    return __syncthreads_and(done);
+  };
+  // The first sweep starts from q = w_hat at every time node: one flux
+  // evaluation and one derivative serve all n nodes, and the time product
+  // reduces to the row sums of A (the same iterate as a general sweep, in
+  // exact arithmetic).
+  bool all_done;
+  {
+    if (tid < CPB) shDelta[tid] = 0;
+    R F[DIM][NV];
+    phys_fluxes<SYS, DIM, R>(w, gamma, ch, adv, F);
+    R r[NV];
+    derivative(F, r);
+    R delta = R(0);
+#pragma unroll
+    for (int s = 0; s < n; ++s) {
+      R arow = R(0);
+#pragma unroll
+      for (int sp = 0; sp < n; ++sp) arow += cget<R>(c.tinvw[s][sp], c.tinvw_f[s][sp]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const R qn = w[v] - arow * r[v];
+        delta = fmax(delta, fabs(qn - w[v]));
+        q[v][s] = qn;
+      }
+    }
+    all_done = converged(delta, 1);
+  }
+  for (int it = 2; !all_done && it <= mp.maxit; ++it) {
     if (tid < CPB) shDelta[tid] = 0;
     R Racc[NV][n];
 #pragma unroll
@@ -685,28 +751,10 @@ k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
       for (int v = 0; v < NV; ++v) qs[v] = q[v][s];
       R F[DIM][NV];
       phys_fluxes<SYS, DIM, R>(qs, gamma, ch, adv, F);
+      R r[NV];
+      derivative(F, r);
 #pragma unroll
-      for (int k = 0; k < DIM; ++k)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) shF[(k * NV + v) * BLK + tid] = cour[k] * F[k][v];
-      __syncthreads();
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        R acc = R(0);
-        // lanes past the last whole cell of the block read nothing
-        if (lc < CPB) {
-#pragma unroll
-          for (int k = 0; k < DIM; ++k) {
-            const int stride = k == 0 ? 1 : (k == 1 ? n : n * n);
-            const int base = tid - ak[k] * stride;
-#pragma unroll
-            for (int b = 0; b < n; ++b)
-              acc += drow[k][b] * shF[(k * NV + v) * BLK + base + b * stride];
-          }
-        }
-        Racc[v][s] = acc;
-      }
-      __syncthreads();
+      for (int v = 0; v < NV; ++v) Racc[v][s] = r[v];
     }
     R delta = R(0);
 #pragma unroll
@@ -718,16 +766,7 @@ k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
         if (!done) q[v][s] = qn;
       }
     }
-    if (!done) atomicMax(&shDelta[lc], Bits<R>::of(delta));
-    __syncthreads();
-    if (!done) {
-      const R dcell = Bits<R>::val(shDelta[lc]);
-      if (dcell <= thr) {
-        done = true;
-        iters = it;
-      }
-    }
-    if (__syncthreads_and(done)) break;
+    all_done = converged(delta, it);
   }
   if (active && !done) iters = mp.maxit;
   block_report(active && a == 0 ? (unsigned)iters : 0u,

@@ -122,7 +122,44 @@ k_predict_mfma2d(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t nc
   const uint64_t cell_lanes = 0x000F000F000F000FULL << (4 * b1);
   bool done = !cell_ok;
   int iters = 0;
-  for (int it = 1; it <= mp.maxit; ++it) {
+  // converged: none of the cell's lanes moved by more than thr (padding
+  // lanes hold a constant state and take no part); true when every cell of
+  // the wavefront has
+  auto converged = [&](double delta, int it) -> bool {
+    const uint64_t moved = __ballot(node_ok && !(delta <= thr));
+    if (!done && (moved & cell_lanes) == 0) {
+      done = true;
+      iters = it;
+    }
+    return !__any(!done);
+  };
+  // The first sweep starts from q = w_hat at every time node: one flux
+  // evaluation and one pair of derivative products serve all n nodes, and
+  // the time product reduces to the row sums of A (the same iterate as a
+  // general sweep, in exact arithmetic).
+  bool all_done;
+  {
+    double F[DIM][NV];
+    phys_fluxes<SYS, DIM, double>(w, gamma, mp.ch, adv, F);
+    double delta = 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double rx = __builtin_amdgcn_mfma_f64_4x4x4f64(mx, F[0][v], 0.0, 0, 0, 0);
+      const double gt = lane_transpose(F[1][v], taddr);
+      const double r = __builtin_amdgcn_mfma_f64_4x4x4f64(gt, my, rx, 0, 0, 0);
+#pragma unroll
+      for (int s = 0; s < n; ++s) {
+        double arow = 0.0;
+#pragma unroll
+        for (int sp = 0; sp < n; ++sp) arow += c.tinvw[s][sp];
+        const double qn = w[v] - arow * r;
+        delta = fmax(delta, fabs(qn - w[v]));
+        q[v][s] = qn;
+      }
+    }
+    all_done = converged(delta, 1);
+  }
+  for (int it = 2; !all_done && it <= mp.maxit; ++it) {
     double R[NV][n];
 #pragma unroll
     for (int s = 0; s < n; ++s) {
@@ -151,14 +188,7 @@ k_predict_mfma2d(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t nc
         q[v][s] = qn;
       }
     }
-    // converged: none of the cell's lanes moved by more than thr (padding
-    // lanes hold a constant state and take no part)
-    const uint64_t moved = __ballot(node_ok && !(delta <= thr));
-    if (!done && (moved & cell_lanes) == 0) {
-      done = true;
-      iters = it;
-    }
-    if (!__any(!done)) break;
+    all_done = converged(delta, it);
   }
   if (cell_ok && !done) iters = mp.maxit;
   block_report(cell_ok && lane == 4 * b1 ? (unsigned)iters : 0u,
