@@ -20,7 +20,7 @@
 //   Traces go to HBM as trace[face][cell][v][s][b] (b: transverse node,
 //   s: time node), face = x-low, x-high, y-low, y-high.
 //
-// k_face2d   one block = a 16 x 4 tile of cells; one 16-lane group per face,
+// k_face2d   one block = a 16 x 8 tile of cells; one 16-lane group per face,
 //            one lane per space-time Gauss point of the face: Rusanov flux
 //            (eq. rusanov) or Osher-type flux (eq. osher) between the two traces, weighted by the Gauss
 //            weights and summed over the group (eqs. flux:F, flux:G); then the
@@ -411,9 +411,9 @@ k_cell2d(const double* __restrict__ u, int64_t ld, R* __restrict__ traces,
   cell2d_tile<M, SYS, TY, R>(blockIdx.x, blockIdx.y, u, ld, traces, dt_dev, mp, c, hdr);
 }
 
-constexpr int kFaceTX = 16, kFaceTY = 4;
+constexpr int kFaceTX = 16, kFaceTY = 8;
 
-// One 16 x 4 tile of the face kernel (every thread of the block calls it).
+// One 16 x 8 tile of the face kernel (every thread of the block calls it).
 // FLUX: -1 numerical flux chosen at run time, 0 Rusanov, 1 Osher-type.
 template <int M, int SYS, typename TR, int FLUX = -1>
 __device__ __forceinline__ void face2d_tile(int tile_x, int tile_y, const TR* __restrict__ traces,
