@@ -220,7 +220,7 @@ ader_status ader_plan_create(const ader_problem* prob, ader_plan* out) {
     off = align256(off + sizeof(double) * d.nv * (size_t)d.nfaces[k]);
   }
   d.off_dtp = off;
-  off = align256(off + sizeof(double) * ader::kDtMaxBlocks);
+  off = align256(off + sizeof(double) * ader::kDtUniformBlocks);
   d.off_tr = off;
   if (pr.dim == 2)  // four face traces per cell: nv x n (transverse) x n (time) each
     off = align256(off + p->impl->qh_elem_size() * 4 * (size_t)d.nv * d.n * d.n * C);

@@ -44,7 +44,7 @@ struct Impl final : ImplBase {
     const MeshParams mp = params(p, ld);
     StageTimer timer(&p.prof, ADER_STAGE_DT, st);
     unsigned int nb = blocks_for(p.ncells);
-    if (nb > (unsigned)kDtMaxBlocks) nb = kDtMaxBlocks;
+    if (nb > (unsigned)kDtUniformBlocks) nb = kDtUniformBlocks;
     double* partial = reinterpret_cast<double*>(ws + p.off_dtp);
     hipLaunchKernelGGL((k_dt<DIM, SYS>), dim3(nb), dim3(kBlock), 0, st, u, mp, hdr, partial,
                        p.prob.cfl, t, t_end, dt);

@@ -935,6 +935,10 @@ __global__ void k_clear_status(WsHeader* hdr) {
 
 // few blocks: every block adds one arrival to a single counter
 constexpr int kDtMaxBlocks = 128;
+// the uniform mesh's time step: one block per compute unit
+constexpr int kDtUniformBlocks = 256;
+// cells per thread whose loads are issued together in k_dt
+constexpr int kDtCellsPerTrip = 4;
 
 // Time step in one launch: per-block maximum of sum_k (|v_k| + c)/dx_k over
 // a grid-stride range of cells, written to partial[block]; the last block to
@@ -949,20 +953,32 @@ k_dt(const double* __restrict__ u, MeshParams mp, WsHeader* hdr, double* partial
   __shared__ bool last;
   double smax = 0.0;
   const double adv[3] = {mp.adv[0], mp.adv[1], mp.adv[2]};
-  for (int64_t cell = (int64_t)blockIdx.x * kBlock + threadIdx.x; cell < mp.ncells;
-       cell += (int64_t)gridDim.x * kBlock) {
-    double q[NV];
+  // grid-stride over the cells, kDtCellsPerTrip cells per thread and trip:
+  // their loads are issued before any of them is evaluated
+  constexpr int U = kDtCellsPerTrip;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t first = (int64_t)blockIdx.x * kBlock + threadIdx.x; first < mp.ncells;
+       first += U * stride) {
+    double q[U][NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) q[v] = u[v * mp.ld + cell];
-    double s = 0.0;
+    for (int j = 0; j < U; ++j) {
+      const int64_t cell = first + j * stride;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      double f[NV], sp;
-      phys_flux_dir<SYS, DIM>(q, k, mp.gamma, mp.ch, adv, f, sp);
-      s += sp / mp.dx[k];
+      for (int v = 0; v < NV; ++v) q[j][v] = cell < mp.ncells ? u[v * mp.ld + cell] : 0.0;
     }
-    // a NaN must win the maximum so that it reaches dt and the status word
-    smax = (s != s || s > smax) ? s : smax;
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (first + j * stride >= mp.ncells) continue;
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        double f[NV], sp;
+        phys_flux_dir<SYS, DIM>(q[j], k, mp.gamma, mp.ch, adv, f, sp);
+        s += sp / mp.dx[k];
+      }
+      // a NaN must win the maximum so that it reaches dt and the status word
+      smax = (s != s || s > smax) ? s : smax;
+    }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
