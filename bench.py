@@ -109,6 +109,8 @@ def device_source_hash():
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_cell2d_kh512_m3.json")
+CLOCK_FILE = os.path.join(ROOT, "profiles", "clock_k_cell2d_kh512_m3.json")
+NOMINAL_CLOCK_GHZ = 2.4
 
 
 def recorded_traffic():
@@ -122,6 +124,20 @@ def recorded_traffic():
     if rec.get("device_source_sha256") != device_source_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def recorded_clock_ghz():
+    """Shader clock measured during the fp64 cell kernel (GRBM_GUI_ACTIVE of
+    one XCD over the dispatch's duration, from the committed counter run), or
+    None when the kernels have changed since."""
+    try:
+        with open(CLOCK_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("device_source_sha256") != device_source_hash():
+        return None
+    return rec.get("measured_clock_ghz")
 
 
 def traffic_probe():
@@ -516,6 +532,7 @@ def main():
         serving = serving_leg(ader, wl, args.serve_requests)
     amr = None if args.no_amr else amr_legs(ader, wl)
 
+    clock = recorded_clock_ghz()
     line = {
         "metric": "cell-updates/s (FP32-predictor vs FP64) at stated L1 err; "
                   "p50/p99 solve latency",
@@ -556,6 +573,9 @@ def main():
                                "(WENO + Picard predictor + traces)",
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": recorded_traffic(),
+                     "measured_clock_ghz": clock,
+                     "frac_at_measured_clock": (None if clock is None else achieved / (
+                         FP64_PEAK_TFLOPS * clock / NOMINAL_CLOCK_GHZ)),
                      "flops_per_launch": flops_launch,
                      "avg_launch_ms": avg_s * 1e3},
         "cpu_baseline": cpu,
