@@ -217,20 +217,6 @@ bool build_ref_constants(int M, RefConstants* out) {
     if (!invert(n, rec, c.rec_inv[s])) return false;
   }
 
-  // Sigma_pm = sum_{alpha=1..M} int_0^1 psi_p^(alpha) psi_m^(alpha)
-  for (int p = 0; p < n; ++p)
-    for (int m = 0; m < n; ++m) c.sigma[p][m] = 0;
-  Poly dp[kMaxN];
-  for (int l = 0; l < n; ++l) dp[l] = psi[l];
-  for (int alpha = 1; alpha <= M; ++alpha) {
-    for (int l = 0; l < n; ++l) dp[l] = deriv(dp[l]);
-    for (int k = 0; k < n; ++k)
-      for (int l = 0; l < n; ++l) c.dnode[alpha - 1][k][l] = eval(dp[l], c.nodes[k]);
-    for (int p = 0; p < n; ++p)
-      for (int m = 0; m < n; ++m)
-        c.sigma[p][m] += integral(mul(dp[p], dp[m]), 0.0L, 1.0L);
-  }
-
   // Legendre polynomials orthonormal on [0, 1] (Gram-Schmidt on powers of t)
   Poly leg[kMaxN];
   for (int i = 0; i < n; ++i) {
@@ -248,6 +234,7 @@ bool build_ref_constants(int M, RefConstants* out) {
   // each stencil's inverse reconstruction matrix
   long double lrow[kMaxN * (kMaxN - 1) / 2][kMaxN];
   int nr = 0;
+  Poly dp[kMaxN];
   for (int l = 0; l < n; ++l) dp[l] = psi[l];
   for (int alpha = 1; alpha <= M; ++alpha) {
     for (int l = 0; l < n; ++l) dp[l] = deriv(dp[l]);

@@ -30,9 +30,6 @@ struct RefConstants {
   int stencil_left[kMaxN];  // L of each stencil (R = M - L)
   long double lambda[kMaxN];
   long double rec_inv[kMaxN][kMaxN][kMaxN];  // [stencil][p][e]
-  long double sigma[kMaxN][kMaxN];           // oscillation matrix
-  // dnode[alpha-1][k][p] = d^alpha psi_p / dxi^alpha at node k, alpha = 1..M
-  long double dnode[kMaxN - 1][kMaxN][kMaxN];
   // sig_rows[s][r][e]: stencil s's averages -> the coefficients, in Legendre
   // polynomials orthonormal on [0, 1], of the derivatives alpha = 1..M of its
   // reconstruction (r runs over alpha, then over the degrees 0..M-alpha).
