@@ -190,11 +190,12 @@ __device__ __forceinline__ void phys_flux_dir(const double (&q)[NVars<SYS, DIM>:
     speed = fabs(adv[k]);
   } else if constexpr (SYS == 1) {
     const double rho = q[0];
+    const double inv_rho = recip(rho);  // one refined reciprocal, no divisions
     double vel[DIM];
     double kin = 0.0;
 #pragma unroll
     for (int m = 0; m < DIM; ++m) {
-      vel[m] = q[1 + m] / rho;
+      vel[m] = q[1 + m] * inv_rho;
       kin += q[1 + m] * vel[m];
     }
     const double E = q[DIM + 1];
@@ -210,16 +211,17 @@ __device__ __forceinline__ void phys_flux_dir(const double (&q)[NVars<SYS, DIM>:
     for (int m = 0; m < DIM; ++m)
       if (m == k) f[1 + m] += p;
     f[DIM + 1] = vk * (E + p);
-    speed = fabs(vk) + sqrt(gamma * p / rho);
+    speed = fabs(vk) + sqrt(gamma * p * inv_rho);
   } else {
     // GLM-MHD (Section 4.2); |largest eigenvalue| = max(|v_k| + c_f, c_h)
     // with the textbook fast magnetosonic speed c_f
     const double rho = q[0];
+    const double inv_rho = recip(rho);  // one refined reciprocal, no divisions
     double vel[3], B[3];
     double kin = 0.0, B2 = 0.0, vB = 0.0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      vel[i] = q[1 + i] / rho;
+      vel[i] = q[1 + i] * inv_rho;
       B[i] = q[5 + i];
       kin += q[1 + i] * vel[i];
       B2 += B[i] * B[i];
@@ -243,8 +245,8 @@ __device__ __forceinline__ void phys_flux_dir(const double (&q)[NVars<SYS, DIM>:
 #pragma unroll
     for (int i = 0; i < 3; ++i) f[5 + i] = i == k ? psi : vk * B[i] - vel[i] * Bk;
     f[8] = ch * ch * Bk;
-    const double a2 = gamma * p / rho;
-    const double b2 = B2 * kInv4Pi / rho, bk2 = Bk * Bk * kInv4Pi / rho;
+    const double a2 = gamma * p * inv_rho;
+    const double b2 = B2 * kInv4Pi * inv_rho, bk2 = Bk * Bk * kInv4Pi * inv_rho;
     const double sum = a2 + b2;
     const double cf = sqrt(0.5 * (sum + sqrt(fmax(sum * sum - 4.0 * a2 * bk2, 0.0))));
     speed = fmax(fabs(vk) + cf, ch);
