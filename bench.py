@@ -451,6 +451,10 @@ def main():
     ap.add_argument("--amr-only", action="store_true",
                     help="only the AMR legs (for profiling them); prints {\"amr\": [...]}")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU; --gpus must be 1",
+              file=sys.stderr)
+        sys.exit(2)
     if args.traffic_probe:
         traffic_probe()
         return
@@ -459,11 +463,6 @@ def main():
         ader.require_gpu()
         print(json.dumps({"amr": amr_legs(ader, wl)}), flush=True)
         return
-    if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU; --gpus must be 1",
-              file=sys.stderr)
-        sys.exit(2)
-
     import numpy as np
     import torch
 
