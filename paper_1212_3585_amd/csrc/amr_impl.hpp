@@ -6,6 +6,7 @@
 
 #include "amr.hpp"
 #include "predict_mfma.hpp"
+#include "predict_wave.hpp"
 
 namespace ader {
 
@@ -112,7 +113,10 @@ class AmrImpl final : public AmrImplBase {
                            (const double*)nullptr, static_cast<R*>(lv.qh), np, dt, lv.mp, c,
                            lv.hdr, fw);
       } else {
-        hipLaunchKernelGGL((k_predict<DIM, M, SYS, R, R, BLK>), grid, dim3(BLK), 0, st,
+        // wavefront-local exchanges (no LDS round trips, no block barriers)
+        constexpr int WCPB = (64 / WaveGroup<NS>::G) * (BLK / 64);
+        const dim3 wgrid((unsigned)((np + WCPB - 1) / WCPB));
+        hipLaunchKernelGGL((k_predict_wave<DIM, M, SYS, R, R, BLK>), wgrid, dim3(BLK), 0, st,
                            (const double*)lv.wh, static_cast<R*>(lv.qh), np, dt, lv.mp, c,
                            lv.hdr);
       }

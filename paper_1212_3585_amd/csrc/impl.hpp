@@ -8,6 +8,7 @@
 #include "fused2d.hpp"
 #include "level.hpp"
 #include "predict_mfma.hpp"
+#include "predict_wave.hpp"
 
 namespace ader {
 
@@ -91,6 +92,11 @@ struct Impl final : ImplBase {
       hipLaunchKernelGGL((k_predict_mfma2d<M, SYS, OUT>),
                          dim3(blocks_for(ncells, 4 * (kBlock / 64))), dim3(kBlock), 0, st, wh,
                          qh, ncells, dt, mp, p.dc, hdr);
+    } else if constexpr (DIM == 3) {
+      // wavefront-local exchanges (no LDS round trips, no block barriers)
+      constexpr int WCPB = (64 / WaveGroup<NS>::G) * (kBlock / 64);
+      hipLaunchKernelGGL((k_predict_wave<DIM, M, SYS, R, OUT>), dim3(blocks_for(ncells, WCPB)),
+                         dim3(kBlock), 0, st, wh, qh, ncells, dt, mp, p.dc, hdr);
     } else {
       hipLaunchKernelGGL((k_predict<DIM, M, SYS, R, OUT>), dim3(blocks_for(ncells, CPB)),
                          dim3(kBlock), 0, st, wh, qh, ncells, dt, mp, p.dc, hdr);
@@ -155,6 +161,11 @@ struct Impl final : ImplBase {
       if constexpr (DIM == 2 && std::is_same<R, double>::value) {
         hipLaunchKernelGGL((k_predict_mfma2d<M, SYS, R>),
                            dim3(blocks_for(L.npred, 4 * (kBlock / 64))), dim3(kBlock), 0, st,
+                           (const double*)wh, qh, L.npred, dt, mp, p.dc, hdr);
+      } else if constexpr (DIM == 3) {
+        constexpr int WCPB = (64 / WaveGroup<NS>::G) * (kBlock / 64);
+        hipLaunchKernelGGL((k_predict_wave<DIM, M, SYS, R, R>),
+                           dim3(blocks_for(L.npred, WCPB)), dim3(kBlock), 0, st,
                            (const double*)wh, qh, L.npred, dt, mp, p.dc, hdr);
       } else {
         hipLaunchKernelGGL((k_predict<DIM, M, SYS, R, R>),

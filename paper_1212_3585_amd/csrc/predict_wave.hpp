@@ -1,0 +1,195 @@
+// Space-time predictor with wavefront-local exchanges (used in 3D).
+//
+// The generic predictor (k_predict) gives every spatial node of a cell one
+// lane and exchanges the nodal fluxes through LDS, with two block barriers
+// per time node; in 3D that moves more LDS bytes per cell and sweep than the
+// arithmetic needs cycles.  Here a cell owns a power-of-two group of G >= n^d
+// lanes inside one wavefront (G = 8, 32, 64 for n^3 = 8, 27, 64), so the
+// derivative along axis k fetches the n - 1 other nodes of the lane's line
+// with ds_bpermute: no LDS memory, no barriers, and the stopping test is a
+// ballot over the cell's lanes.
+//
+// One Picard sweep of eq. stdg.final per loop trip, dimension by dimension:
+//   * nodal fluxes f_k at the lane's node and time node sp;
+//   * sum_k (dt/dx_k) D^(k) f_k from the line partners (lane-uniform
+//     offsets m = 1..n-1: partner (p_k + m) mod n, coefficient D[p_k][.]);
+//   * time product with (time factor of K^1)^-1 diag(w) and the update from
+//     w_hat (time_update);
+// and the first sweep from q = w_hat evaluates the fluxes once for all time
+// nodes (row sums of the time matrix).  A cell stops counting iterations at
+// the first sweep whose largest change is within tol * max(1, max |w_hat|);
+// its lanes sweep on with the wavefront, each further sweep moving q by less
+// than the tolerance.
+#pragma once
+
+#include "kernels.hpp"
+#include "predict_mfma.hpp"
+
+namespace ader {
+
+// lanes per cell: the smallest power of two that holds n^d nodes
+template <int NS> struct WaveGroup {
+  static constexpr int G = NS <= 1 ? 1 : NS <= 2 ? 2 : NS <= 4 ? 4 : NS <= 8 ? 8
+                         : NS <= 16 ? 16 : NS <= 32 ? 32 : 64;
+  static_assert(NS <= 64, "a cell must fit one wavefront");
+};
+
+template <typename R> __device__ __forceinline__ R lane_fetch(R x, int addr);
+template <> __device__ __forceinline__ double lane_fetch<double>(double x, int addr) {
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(x));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+template <> __device__ __forceinline__ float lane_fetch<float>(float x, int addr) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x)));
+}
+
+// maximum over the G lanes of this lane's group (G a power of two <= 64)
+template <int G, typename R>
+__device__ __forceinline__ R group_max(R x) {
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) x = fmax(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+template <int DIM, int M, int SYS, typename R, typename OUT, int BLK = kBlock>
+__global__ void __launch_bounds__(BLK)
+k_predict_wave(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
+               const double* __restrict__ dt_dev, MeshParams mp, DevConsts c, WsHeader* hdr) {
+  constexpr int n = M + 1;
+  constexpr int NS = Pow<n, DIM>::v;
+  constexpr int NST = NS * n;
+  constexpr int NV = NVars<SYS, DIM>::v;
+  constexpr int G = WaveGroup<NS>::G;
+  constexpr int CPW = 64 / G;            // cells per wavefront
+  constexpr int CPB = CPW * (BLK / 64);  // cells per block
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int slot = lane / G;
+  const int a_raw = lane % G;
+  const bool node_ok = a_raw < NS;
+  const int a = node_ok ? a_raw : 0;  // padding lanes mirror node 0 (never written out)
+  const int64_t cell = (int64_t)blockIdx.x * CPB + wave * CPW + slot;
+  const bool cell_ok = cell < ncells;
+  const bool active = cell_ok && node_ok;
+  const uint64_t cell_lanes = (G == 64 ? ~0ULL : ((1ULL << G) - 1ULL)) << (slot * G);
+
+  int ak[3] = {a % n, (a / n) % n, a / (n * n)};
+  const double dt = *dt_dev;
+  // coef[k][m]: (dt/dx_k) D[p_k][(p_k + m) mod n]; addr[k][m]: byte address
+  // of the lane holding that node of this lane's line (m = 0 is the lane)
+  R coef[DIM][n];
+  int addr[DIM][n];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    const int stride = k == 0 ? 1 : (k == 1 ? n : n * n);
+    const int base = slot * G + a - ak[k] * stride;
+#pragma unroll
+    for (int m = 0; m < n; ++m) {
+      const int b = (ak[k] + m) % n;
+      coef[k][m] = (R)((dt / mp.dx[k]) * pick_entry<n>(c.dmat, ak[k], b));
+      addr[k][m] = (base + b * stride) << 2;
+    }
+  }
+  const R gamma = (R)mp.gamma;
+  const R ch = (R)mp.ch;
+  const R adv[3] = {(R)mp.adv[0], (R)mp.adv[1], (R)mp.adv[2]};
+
+  R w[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+    w[v] = active ? (R)wh[(cell * NV + v) * NS + a] : (v == 0 || v == NV - 1 ? R(1) : R(0));
+
+  // stopping threshold of the cell: tol * max(1, max |w_hat|) over its nodes
+  R wmax = R(0);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) wmax = fmax(wmax, fabs(w[v]));
+  const R thr = (R)mp.tol * fmax(R(1), group_max<G>(node_ok ? wmax : R(0)));
+
+  // sum_k (dt/dx_k) D^(k) f_k at this lane's node
+  auto derivative = [&](const R (&F)[DIM][NV], R (&out)[NV]) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      R acc = R(0);
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        acc += coef[k][0] * F[k][v];
+#pragma unroll
+        for (int m = 1; m < n; ++m) acc += coef[k][m] * lane_fetch<R>(F[k][v], addr[k][m]);
+      }
+      out[v] = acc;
+    }
+  };
+  bool done = !cell_ok;
+  int iters = 0;
+  auto converged = [&](R delta, int it) -> bool {
+    const uint64_t moved = __ballot(node_ok && !(delta <= thr));
+    if (!done && (moved & cell_lanes) == 0) {
+      done = true;
+      iters = it;
+    }
+    return !__any(!done);
+  };
+
+  R q[NV][n];
+  bool all_done;
+  {
+    // first sweep from q = w_hat at every time node
+    R F[DIM][NV];
+    phys_fluxes<SYS, DIM, R>(w, gamma, ch, adv, F);
+    R r[NV];
+    derivative(F, r);
+    R delta = R(0);
+#pragma unroll
+    for (int s = 0; s < n; ++s) {
+      R arow = R(0);
+#pragma unroll
+      for (int sp = 0; sp < n; ++sp) arow += cget<R>(c.tinvw[s][sp], c.tinvw_f[s][sp]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const R qn = w[v] - arow * r[v];
+        delta = fmax(delta, fabs(qn - w[v]));
+        q[v][s] = qn;
+      }
+    }
+    all_done = converged(delta, 1);
+  }
+  for (int it = 2; !all_done && it <= mp.maxit; ++it) {
+    R Racc[NV][n];
+#pragma unroll
+    for (int s = 0; s < n; ++s) {
+      R qs[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) qs[v] = q[v][s];
+      R F[DIM][NV];
+      phys_fluxes<SYS, DIM, R>(qs, gamma, ch, adv, F);
+      R r[NV];
+      derivative(F, r);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Racc[v][s] = r[v];
+    }
+    R delta = R(0);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+      for (int s = 0; s < n; ++s) {
+        const R qn = time_update<n>(w[v], Racc[v], c.tinvw, c.tinvw_f, s);
+        delta = fmax(delta, fabs(qn - q[v][s]));
+        q[v][s] = qn;
+      }
+    }
+    all_done = converged(delta, it);
+  }
+  if (cell_ok && !done) iters = mp.maxit;
+  const bool lead = cell_ok && a_raw == 0;
+  block_report(lead ? (unsigned)iters : 0u, lead && !done ? kFlagNoConv : 0u, hdr);
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int s = 0; s < n; ++s) qh[(cell * NV + v) * NST + a + NS * s] = (OUT)q[v][s];
+  }
+}
+
+}  // namespace ader
