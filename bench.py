@@ -453,7 +453,7 @@ def main():
                     help="only the AMR legs (for profiling them); prints {\"amr\": [...]}")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU; --gpus must be 1",
+        print("bench.py: the benchmark runs on exactly one GPU; --gpus must be 1",
               file=sys.stderr)
         sys.exit(2)
     if args.traffic_probe:

@@ -44,7 +44,7 @@ extern "C" {
 typedef enum {
   ADER_OK = 0,
   ADER_EINVAL = -1,        /* invalid argument (null pointer, bad size ...) */
-  ADER_EUNSUPPORTED = -2,  /* valid problem outside what this build supports */
+  ADER_EUNSUPPORTED = -2,  /* valid problem outside what the library supports */
   ADER_EHIP = -3,          /* a HIP runtime call failed */
   ADER_EWORKSPACE = -4     /* workspace pointer null or misaligned */
 } ader_status;
@@ -110,7 +110,7 @@ typedef struct ader_plan_s* ader_plan;
  * time matrix of K^1 with its inverse; Sections 2.2 and 2.3) on the host.
  * *out receives a plan owned by the caller; release with ader_plan_destroy.
  * Errors: EINVAL (null pointers, non-finite or out-of-range fields),
- * EUNSUPPORTED (dim/M/system outside this build). */
+ * EUNSUPPORTED (dim/M/system outside what the library supports). */
 ader_status ader_plan_create(const ader_problem* prob, ader_plan* out);
 
 /* Release a plan (NULL is accepted). */
