@@ -548,8 +548,10 @@ __global__ void __launch_bounds__(kBlock)
 k_face2d(const TR* __restrict__ traces, const double* __restrict__ u_in,
          double* __restrict__ u_out, int64_t ld, const double* __restrict__ dt_dev,
          MeshParams mp, DevConsts c, WsHeader* hdr) {
-  face2d_tile<M, SYS, TR, FLUX>(blockIdx.x, blockIdx.y, traces, u_in, u_out, ld, dt_dev, mp, c,
-                                hdr);
+  // tiles in the reverse of the cell kernel's order: the traces written last
+  // are the ones still held in the caches when this kernel starts
+  const int tx = (int)(gridDim.x - 1 - blockIdx.x), ty = (int)(gridDim.y - 1 - blockIdx.y);
+  face2d_tile<M, SYS, TR, FLUX>(tx, ty, traces, u_in, u_out, ld, dt_dev, mp, c, hdr);
 }
 
 }  // namespace ader
