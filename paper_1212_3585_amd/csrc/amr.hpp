@@ -421,9 +421,11 @@ k_amr_flux(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, double* __res
   const int cs = tid / Sh::LPC;
   const int k = (tid % Sh::LPC) / G;
   const int g = tid % G;
-  // groups in the reverse of the predictor's order: the q_h written last are
-  // the ones still held in the caches when this kernel starts
-  const int64_t i = (int64_t)(gridDim.x - 1 - blockIdx.x) * Sh::CPB + cs;
+  // groups in the reverse of the predictor's order (2D: predictor forward;
+  // 3D: predictor reversed): the q_h written last are read first, while
+  // still cached
+  const int64_t blk = DIM == 2 ? (int64_t)(gridDim.x - 1 - blockIdx.x) : (int64_t)blockIdx.x;
+  const int64_t i = blk * Sh::CPB + cs;
   const bool valid = i < a.nact;
   unsigned int flags = 0;
   int cc[3] = {0, 0, 0};

@@ -42,7 +42,10 @@ k_level_weno_pass(const double* __restrict__ u, int64_t ld, const int32_t* __res
   constexpr int IN = Pow<n, K>::v * Pow<S, DIM - K>::v;
   constexpr int OUT = Pow<n, K + 1>::v * Pow<S, DIM - K - 1>::v;
   constexpr int LINES = IN / S;  // lines of this pass per (cell, variable)
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  // the y pass runs in reverse block order, so that it reads first the x-pass
+  // lines written last (still cached), and the z pass, forward, the y lines
+  const int64_t blk = K == 1 ? (int64_t)(gridDim.x - 1 - blockIdx.x) : (int64_t)blockIdx.x;
+  const int64_t t = blk * kBlock + threadIdx.x;
   if (t >= npred * NV * LINES) return;
   const int line = (int)(t % LINES);
   const int64_t pv = t / LINES;  // p * NV + v

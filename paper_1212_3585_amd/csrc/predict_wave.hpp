@@ -70,7 +70,9 @@ k_predict_wave(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncel
   const int a_raw = lane % G;
   const bool node_ok = a_raw < NS;
   const int a = node_ok ? a_raw : 0;  // padding lanes mirror node 0 (never written out)
-  const int64_t cell = (int64_t)blockIdx.x * CPB + wave * CPW + slot;
+  // reverse block order: the reconstructions written last by the preceding
+  // pass are read first, while still cached (the face kernel then runs forward)
+  const int64_t cell = (int64_t)(gridDim.x - 1 - blockIdx.x) * CPB + wave * CPW + slot;
   const bool cell_ok = cell < ncells;
   const bool active = cell_ok && node_ok;
   const uint64_t cell_lanes = (G == 64 ? ~0ULL : ((1ULL << G) - 1ULL)) << (slot * G);
