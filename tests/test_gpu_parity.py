@@ -84,7 +84,10 @@ def test_reconstruction_parity(ader, dim, M, n, bc):
 @pytest.mark.parametrize("dim,M,system,ncells", [
     (2, 1, "euler", 301), (2, 2, "euler", 333), (2, 3, "euler", 257),
     (3, 1, "euler", 70), (3, 2, "euler", 95), (3, 3, "euler", 9),
-    (2, 3, "linadv", 100), (3, 2, "linadv", 40), (2, 0, "euler", 17)])
+    (2, 3, "linadv", 100), (3, 2, "linadv", 40), (2, 0, "euler", 17),
+    # 3D lane groups of 1 (M = 0, several wavefronts and a partial one), 8
+    # (M = 1) and 32 (M = 2, a single cell)
+    (3, 0, "euler", 150), (3, 1, "linadv", 77), (3, 2, "euler", 1)])
 def test_predictor_parity(ader, dim, M, system, ncells):
     say(f"predict dim={dim} M={M} {system} ncells={ncells}")
     import torch
