@@ -482,8 +482,8 @@ __device__ __forceinline__ void face2d_tile(int tile_x, int tile_y, const TR* __
       double qL[NV], qR[NV];  // traces in the predictor precision, flux in fp64
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        qL[v] = (double)tL[(v * n + s) * n + b];
-        qR[v] = (double)tR[(v * n + s) * n + b];
+        qL[v] = (double)__builtin_nontemporal_load(&tL[(v * n + s) * n + b]);
+        qR[v] = (double)__builtin_nontemporal_load(&tR[(v * n + s) * n + b]);
       }
       if (mp.bc[k] != 0) {
         if (outL) {
