@@ -160,6 +160,21 @@ ader_status ader_debug_predict(ader_plan plan, const double* w_h,
                                int64_t ncells, double* q_h,
                                const double* dt_dev, void* ws, void* stream);
 
+/* ader_debug_traces (2D plans; EUNSUPPORTED for 3D): the fused 2D cell kernel
+ *   of ader_step alone, at the plan's tile height, on the averages u with
+ *   *dt_dev: reconstruction (Section 2.2), predictor (Section 2.3, eq.
+ *   stdg.final, in the plan's precision) and the predictor's values on the
+ *   four faces of every cell at the face's space-time Gauss points (the
+ *   operands of eqs. flux:F and flux:G), written as fp64 to
+ *     traces[((f * ncells + cell) * nvar + v) * n * n + s * n + b],
+ *   f = 0 x-low, 1 x-high, 2 y-low, 3 y-high face, s the time node, b the
+ *   transverse node; 4 ncells nvar n^2 doubles, caller-owned device memory.
+ *   The averages are not updated.  The workspace's status bits and counters
+ *   accumulate as in ader_step. */
+ader_status ader_debug_traces(ader_plan plan, const double* u, int64_t ld,
+                              const double* dt_dev, double* traces, void* ws,
+                              void* stream);
+
 /* Autotuning of the fused 2D cell kernel (2D plans; EUNSUPPORTED for 3D).
  * The cell kernel works on tiles of 4 x rows cells, one wavefront per tile
  * row; rows is 2, 4, 8 or 16 (at most 8 for GLM-MHD, whose kernel needs more

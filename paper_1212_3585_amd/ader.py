@@ -26,7 +26,7 @@ FLAG_NAN, FLAG_NONPHYSICAL, FLAG_NOCONV, FLAG_BADINDEX = 1, 2, 4, 8
 EXPORTS = [
     "ader_plan_create", "ader_plan_destroy", "ader_plan_nvar",
     "ader_workspace_bytes", "ader_clear_status", "ader_compute_dt", "ader_step",
-    "ader_debug_reconstruct", "ader_debug_predict", "ader_read_status",
+    "ader_debug_reconstruct", "ader_debug_predict", "ader_debug_traces", "ader_read_status",
     "ader_debug_constants", "ader_profile_begin", "ader_profile_end", "ader_tune",
     "ader_set_tile_rows",
     "ader_level_workspace_bytes", "ader_step_level",
@@ -120,6 +120,7 @@ def load_library():
         "ader_step": [vp, vp, vp, i64, vp, vp, vp],
         "ader_debug_reconstruct": [vp, vp, i64, vp, vp, vp],
         "ader_debug_predict": [vp, vp, i64, vp, vp, vp, vp],
+        "ader_debug_traces": [vp, vp, i64, vp, vp, vp, vp],
         "ader_read_status": [vp, vp, ctypes.POINTER(ctypes.c_uint32),
                              ctypes.POINTER(ctypes.c_uint64), vp],
         "ader_debug_constants": [vp, vp, vp, vp, vp],
@@ -309,6 +310,19 @@ class Solver:
                                            _ptr(self.ws), _stream(stream)),
                "ader_debug_predict")
         return qh
+
+    def traces(self, u, dt=None, stream=None):
+        """Face traces of the fused 2D cell kernel: [4 faces, cells, nvar, s, b]
+        (faces x-low, x-high, y-low, y-high; s time node, b transverse node)."""
+        import torch
+        n = self.problem.M + 1
+        dt = self.dt if dt is None else dt
+        tr = torch.empty((4, self.ncells, self.nvar, n, n), dtype=torch.float64,
+                         device=self.device)
+        _check(self.lib.ader_debug_traces(self._plan, _ptr(u), u.shape[1], _ptr(dt), _ptr(tr),
+                                          _ptr(self.ws), _stream(stream)),
+               "ader_debug_traces")
+        return tr
 
     def read_status(self, stream=None):
         flags = ctypes.c_uint32()

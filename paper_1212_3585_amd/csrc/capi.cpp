@@ -10,11 +10,6 @@
 #include "plan.hpp"
 #include "cell2d_launch.hpp"
 
-struct ader_plan_s {
-  ader::PlanData data;
-  const ader::ImplBase* impl = nullptr;
-};
-
 namespace {
 thread_local std::string g_last_error;
 bool is_finite(double x) { return std::isfinite(x); }
@@ -204,9 +199,18 @@ ader_status ader_plan_create(const ader_problem* prob, ader_plan* out) {
     d.nfaces[k] = nf;
   }
 
-  // workspace: header | Wx | Wxy (3D) | w_h | q_h | face fluxes
+  // workspace: header | CFL partial maxima | what ader_step uses | the rest.
+  //   2D: face traces (the fused step) | Wx | w_h | q_h (stage entry points)
+  //   3D: Wx | Wxy | w_h | q_h | face fluxes (all used by the step)
   size_t off = ader::kHeaderBytes;
   const size_t C = (size_t)ncells;
+  d.off_dtp = off;
+  off = align256(off + sizeof(double) * ader::kDtUniformBlocks);
+  d.off_tr = off;
+  if (pr.dim == 2) {  // four face traces per cell: nv x n (transverse) x n (time) each
+    off = align256(off + p->impl->qh_elem_size() * 4 * (size_t)d.nv * d.n * d.n * C);
+    d.step_bytes = off;
+  }
   d.off_wx = off;
   off = align256(off + sizeof(double) * d.nv * d.n * C);
   d.off_wxy = off;
@@ -215,15 +219,13 @@ ader_status ader_plan_create(const ader_problem* prob, ader_plan* out) {
   off = align256(off + sizeof(double) * d.nv * d.ns * C);
   d.off_qh = off;
   off = align256(off + p->impl->qh_elem_size() * d.nv * d.nst * C);
-  for (int k = 0; k < pr.dim; ++k) {
-    d.off_f[k] = off;
-    off = align256(off + sizeof(double) * d.nv * (size_t)d.nfaces[k]);
+  if (pr.dim == 3) {
+    for (int k = 0; k < pr.dim; ++k) {
+      d.off_f[k] = off;
+      off = align256(off + sizeof(double) * d.nv * (size_t)d.nfaces[k]);
+    }
+    d.step_bytes = off;
   }
-  d.off_dtp = off;
-  off = align256(off + sizeof(double) * ader::kDtUniformBlocks);
-  d.off_tr = off;
-  if (pr.dim == 2)  // four face traces per cell: nv x n (transverse) x n (time) each
-    off = align256(off + p->impl->qh_elem_size() * 4 * (size_t)d.nv * d.n * d.n * C);
   d.ws_bytes = off;
   *out = p;
   return ADER_OK;
@@ -298,6 +300,17 @@ ader_status ader_debug_predict(ader_plan plan, const double* w_h, int64_t ncells
   return hip_status(plan->impl->predict_debug(plan->data, w_h, ncells, q_h, dt_dev, (char*)ws,
                                               (hipStream_t)stream),
                     "ader_debug_predict");
+}
+
+ader_status ader_debug_traces(ader_plan plan, const double* u, int64_t ld, const double* dt_dev,
+                              double* traces, void* ws, void* stream) {
+  if (!plan || !dt_dev || !traces) return fail(ADER_EINVAL, "null argument");
+  if (plan->data.dim != 2) return fail(ADER_EUNSUPPORTED, "face traces are exposed for 2D plans");
+  if (ader_status s = check_state(plan, u, ld)) return s;
+  if (ader_status s = check_ws(plan, ws)) return s;
+  return hip_status(plan->impl->traces_debug(plan->data, u, ld, dt_dev, traces, (char*)ws,
+                                             (hipStream_t)stream),
+                    "ader_debug_traces");
 }
 
 ader_status ader_level_workspace_bytes(ader_plan plan, int64_t npred, size_t* bytes) {

@@ -12,6 +12,14 @@
 
 namespace ader {
 
+// out[i] = (double)in[i]
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_to_double(const T* __restrict__ in, double* __restrict__ out, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = (double)in[i];
+}
+
 inline unsigned int blocks_for(int64_t threads, int per_block = kBlock) {
   return (unsigned int)((threads + per_block - 1) / per_block);
 }
@@ -199,6 +207,20 @@ struct Impl final : ImplBase {
       a.n1 = p.mp.n[1];
       return launch_cell2d(rows, M, SYS, std::is_same<R, double>::value ? 0 : 1, a, p.dc,
                            reinterpret_cast<WsHeader*>(ws), st);
+    }
+  }
+
+  hipError_t traces_debug(const PlanData& p, const double* u_in, int64_t ld, const double* dt,
+                          double* out, char* ws, hipStream_t st) const override {
+    if constexpr (DIM != 2) {
+      return hipErrorInvalidConfiguration;
+    } else {
+      hipError_t e = cell2d(p, u_in, ld, dt, ws, p.cell_rows, st);
+      if (e != hipSuccess) return e;
+      const int64_t count = 4 * p.ncells * NV * n * n;
+      hipLaunchKernelGGL((k_to_double<R>), dim3(blocks_for(count)), dim3(kBlock), 0, st,
+                         reinterpret_cast<const R*>(ws + p.off_tr), out, count);
+      return hipGetLastError();
     }
   }
 

@@ -66,6 +66,7 @@ struct PlanData {
   size_t off_dtp = 0;  // per-block partial maxima of the time-step reduction
   size_t off_tr = 0;   // face traces of the fused 2D path
   size_t ws_bytes = 0;
+  size_t step_bytes = 0;  // leading part of the workspace that ader_step uses
   int cell_rows = 8;   // tile height of the fused 2D cell kernel (ader_tune)
   mutable Profiler prof;
 };
@@ -110,6 +111,10 @@ struct ImplBase {
   // the fused 2D cell kernel alone with tile height 'rows' (2D plans)
   virtual hipError_t cell2d(const PlanData& p, const double* u_in, int64_t ld, const double* dt,
                             char* ws, int rows, hipStream_t st) const = 0;
+  // the cell kernel at the plan's height, then its traces upcast to fp64 (2D plans)
+  virtual hipError_t traces_debug(const PlanData& p, const double* u_in, int64_t ld,
+                                  const double* dt, double* out, char* ws,
+                                  hipStream_t st) const = 0;
   virtual LevelLayout level_layout(const PlanData& p, int64_t npred) const = 0;
   virtual hipError_t step_level(const PlanData& p, const LevelArgs& L, const double* u_in,
                                 double* u_out, int64_t ld, const double* dt, char* ws,
@@ -120,3 +125,9 @@ const ImplBase* make_impl_2d(int M, int sys, int prec);
 const ImplBase* make_impl_3d(int M, int sys, int prec);
 
 }  // namespace ader
+
+// The opaque plan of the C ABI.
+struct ader_plan_s {
+  ader::PlanData data;
+  const ader::ImplBase* impl = nullptr;
+};

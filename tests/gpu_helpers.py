@@ -53,6 +53,13 @@ def rel_l1(a, b):
     return float(np.abs(a - b).sum() / np.abs(b).sum())
 
 
+def max_rel(a, b):
+    """Element-wise distance: max over entries of |a - b| / max(1, |b|)."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float((np.abs(a - b) / np.maximum(1.0, np.abs(b))).max())
+
+
 def rel_l1_per_var(a, b):
     """Per-variable relative L1 (informative: a variable near zero, such as the
     momentum of a gas at rest, makes its own ratio meaningless)."""

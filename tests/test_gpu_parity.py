@@ -1,9 +1,10 @@
 """Parity of the HIP path (through the C ABI) with the CPU fp64 oracle.
 
-Bar: relative L1 pooled over the conserved variables,
-sum_{v,cells} |gpu - oracle| / sum_{v,cells} |oracle| <= 1e-11, for the fp64
-path; the fp32-predictor path states its L1 error
-against the fp64 oracle and must stay below 1e-5.  Inputs are seeded and
+Bars for the fp64 path: relative L1 pooled over the conserved variables,
+sum_{v,cells} |gpu - oracle| / sum_{v,cells} |oracle| <= 1e-11, and element
+by element max |gpu - oracle| / max(1, |oracle|) <= 1e-11.  The
+fp32-predictor path states its error against the fp64 oracle, bounded at
+about ten times the measured value.  Inputs are seeded and
 shaped like the paper's tests; mesh sizes span several thread blocks and end
 in ragged tails.
 """
@@ -16,13 +17,20 @@ from oracle.scheme import all_cells
 from oracle.weno import reconstruct as oracle_reconstruct
 from paper_1212_3585_amd import workloads as wl
 
-from gpu_helpers import (from_device, gpu_qh_to_oracle_layout, make_pair,
+from gpu_helpers import (from_device, gpu_qh_to_oracle_layout, make_pair, max_rel,
                          oracle_wh_to_gpu_layout, rel_l1, rel_l1_per_var, say,
                          to_device)
 
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-11
+# fp32-predictor bars, about ten times the measured errors against the fp64
+# oracle (3 steps of the smooth test state; one step of the 3D blast sample)
+MIXED_STEP_L1 = {2: 1e-5, 3: 1e-5}
+MIXED_STEP_MAX = {2: 1e-4, 3: 1e-4}
+MIXED_BLAST_L1 = 1e-5
+MIXED_BLAST_MAX = 1e-4
+MIXED_TRACE_MAX = 1e-4
 
 
 def _kh(n, seed=1, amp=0.01):
@@ -118,6 +126,51 @@ def test_predictor_parity(ader, dim, M, system, ncells):
     assert abs(iters - int(it.sum())) <= max(2, 0.02 * it.sum())
 
 
+# ------------------------------------------------------------ cell kernel traces
+@pytest.mark.parametrize("M,n,bc,system,precision", [
+    (3, (37, 29), "periodic", "euler", 0), (2, (21, 18), "transmissive", "euler", 0),
+    (1, (13, 9), "periodic", "euler", 0), (0, (9, 7), "periodic", "euler", 0),
+    (3, (19, 17), "periodic", "mhd", 0), (3, (24, 13), "transmissive", "linadv", 0),
+    (3, (37, 29), "periodic", "euler", 1), (2, (21, 18), "transmissive", "euler", 1),
+    (1, (13, 9), "periodic", "euler", 1), (3, (19, 17), "periodic", "mhd", 1)])
+def test_cell_kernel_traces_parity(ader, M, n, bc, system, precision):
+    """The production 2D cell kernel (LDS WENO, matrix-core fp64 or DPP fp32
+    predictor, trace contraction) against the oracle's predictor traces on
+    all four faces of every cell, element by element (Section 2.3, eq.
+    stdg.final; the operands of eqs. flux:F and flux:G)."""
+    say(f"cell-kernel traces M={M} n={n} bc={bc} {system} precision={precision}")
+    import torch
+    from oracle.scheme import _predict_cells, traces as oracle_traces
+    if system == "euler":
+        U = _euler_random(n, 60 + M, 2)
+    elif system == "mhd":
+        U = wl.orszag_tang(n[0], seed=3)[:, :, :n[1]]
+    else:
+        U = wl.random_field((1,) + n, 61)
+    op, gp = make_pair(ader, 2, M, n, (0, 0), (1.0, 1.5), bc, system=system,
+                       precision=precision, tol=1e-14 if precision == 0 else 1e-6)
+    op64, _ = make_pair(ader, 2, M, n, (0, 0), (1.0, 1.5), bc, system=system)
+    dt = 0.9 * oracle.cfl_dt(op64, U)
+    q, it = _predict_cells(op64, U, all_cells(op64), dt)
+    s = ader.Solver(gp)
+    s.clear_status()
+    dtd = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    tr = s.traces(to_device(U), dt=dtd).cpu().numpy()       # [f, C, v, s, b]
+    worst = 0.0
+    for f in range(4):
+        ref = oracle_traces(q, op64, f // 2, f % 2)          # [v, C, s, b]
+        got = np.transpose(tr[f], (1, 0, 2, 3))
+        worst = max(worst, max_rel(got, ref))
+    flags, iters = s.read_status()
+    print(f"traces: element-wise max |gpu - oracle| / max(1, |oracle|) = {worst:.3e}")
+    assert flags == 0
+    if precision == 0:
+        assert worst <= 1e-12
+        assert abs(iters - int(it.sum())) <= max(2, 0.02 * it.sum())
+    else:
+        assert worst <= MIXED_TRACE_MAX
+
+
 # ------------------------------------------------------------ full step
 @pytest.mark.parametrize("dim,M,n,bc,system", [
     (2, 2, (20, 20), "periodic", "euler"),
@@ -155,6 +208,8 @@ def test_step_parity(ader, dim, M, n, bc, system):
         u, out = out, u
     got = from_device(u, n)
     assert rel_l1(got, Uo) <= TOL, (rel_l1(got, Uo), rel_l1_per_var(got, Uo))
+    print(f"step parity: pooled L1 {rel_l1(got, Uo):.2e}, element-wise {max_rel(got, Uo):.2e}")
+    assert max_rel(got, Uo) <= TOL
     flags, _ = s.read_status()
     assert flags == 0
 
@@ -171,6 +226,7 @@ def test_isentropic_vortex_to_t1(ader):
     assert ng == ns and abs(tg - 1.0) < 1e-14
     got = from_device(u, (N, N))
     assert rel_l1(got, Uo) <= TOL, rel_l1(got, Uo)
+    assert max_rel(got, Uo) <= TOL, max_rel(got, Uo)
     exact = wl.isentropic_vortex(N, t=1.0)
     assert np.abs(got[0] - exact[0]).mean() < 5e-3
 
@@ -186,8 +242,9 @@ def test_kelvin_helmholtz_ten_steps(ader):
     u, *_ = s.run(to_device(U0), 1.0, max_steps=10)
     got = from_device(u, (N, N))
     print("KH 64^2 10 steps: pooled", rel_l1(got, Uo), "per variable",
-          rel_l1_per_var(got, Uo))
+          rel_l1_per_var(got, Uo), "element-wise", max_rel(got, Uo))
     assert rel_l1(got, Uo) <= TOL, (rel_l1(got, Uo), rel_l1_per_var(got, Uo))
+    assert max_rel(got, Uo) <= TOL
 
 
 def test_kelvin_helmholtz_512_sampled(ader):
@@ -210,6 +267,7 @@ def test_kelvin_helmholtz_512_sampled(ader):
     ref, _ = oracle.step_cells(op, U0, dt, cells)
     g = got[:, cells[:, 0], cells[:, 1]]
     assert rel_l1(g, ref) <= TOL
+    assert max_rel(g, ref) <= TOL, max_rel(g, ref)
 
 
 @pytest.mark.parametrize("dim,M,n", [(2, 3, (48, 40)), (3, 2, (10, 9, 8))])
@@ -221,9 +279,12 @@ def test_mixed_precision_error_is_stated(ader, dim, M, n):
     Uo, *_ = oracle.run(op64, U, 1.0, max_steps=3)
     s = ader.Solver(gp)
     u, *_ = s.run(to_device(U), 1.0, max_steps=3)
-    err = rel_l1(from_device(u, n), Uo)
-    print(f"fp32-predictor relative L1 vs fp64 oracle after 3 steps: {err:.3e}")
-    assert err < 1e-5
+    got = from_device(u, n)
+    err = rel_l1(got, Uo)
+    print(f"fp32-predictor vs fp64 oracle after 3 steps ({dim}D): relative L1 {err:.3e}, "
+          f"element-wise {max_rel(got, Uo):.3e}")
+    assert err < MIXED_STEP_L1[dim]
+    assert max_rel(got, Uo) < MIXED_STEP_MAX[dim]
 
 
 @pytest.mark.parametrize("precision,tol", [(0, 1e-14), (1, 1e-6)])
@@ -312,6 +373,7 @@ def test_explosion_100_full_oracle(ader):
     u, *_ = s.run(to_device(U0), 1.0, max_steps=3)
     got = from_device(u, (N, N))
     assert rel_l1(got, Uo) <= TOL, (rel_l1(got, Uo), rel_l1_per_var(got, Uo))
+    assert max_rel(got, Uo) <= TOL, max_rel(got, Uo)
     assert s.read_status()[0] == 0
 
 
@@ -337,6 +399,7 @@ def test_explosion_900_sampled(ader):
     ref, _ = oracle.step_cells(op, U0, dt, cells)
     g = got[:, cells[:, 0], cells[:, 1]]
     assert rel_l1(g, ref) <= TOL, rel_l1(g, ref)
+    assert max_rel(g, ref) <= TOL, max_rel(g, ref)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -363,8 +426,10 @@ def test_blast_3d_64_sampled(ader, precision):
     ref, _ = oracle.step_cells(op, U0, dt, cells)
     g = got[:, cells[:, 0], cells[:, 1], cells[:, 2]]
     err = rel_l1(g, ref)
-    print(f"3D blast 64^3 precision {precision}: relative L1 {err:.3e}")
-    assert err <= (TOL if precision == 0 else 1e-5)
+    print(f"3D blast 64^3 precision {precision}: relative L1 {err:.3e}, "
+          f"element-wise {max_rel(g, ref):.3e}")
+    assert err <= (TOL if precision == 0 else MIXED_BLAST_L1)
+    assert max_rel(g, ref) <= (TOL if precision == 0 else MIXED_BLAST_MAX)
     assert s.read_status()[0] == 0
 
 
