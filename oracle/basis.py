@@ -16,6 +16,12 @@ unit interval [0, 1] of the reference coordinates (Section 2.2, eq. xi):
 Integrals are taken exactly from antiderivatives, not by quadrature, so that
 the properties the scheme relies on (diagonal mass matrix, exactness of the
 Gauss rule up to degree 2M+1) are results the tests can check, not inputs.
+
+The tables are built in long double and rounded once to fp64: the stencil
+integrals of Section 2.2 extrapolate the basis up to M cells away, where the
+antiderivatives cancel badly, and the WENO weights raise the oscillation
+indicators to the power r = 8, which turns table errors of a few hundred ulps
+into visible changes of w_h.  Everything applied per cell stays fp64.
 """
 from __future__ import annotations
 
@@ -23,13 +29,53 @@ from functools import lru_cache
 
 import numpy as np
 from numpy.polynomial import Polynomial
+from numpy.polynomial import legendre
 from numpy.polynomial.legendre import leggauss
+
+
+LD = np.longdouble
+
+
+def gauss_legendre_ld(n: int) -> tuple[np.ndarray, np.ndarray]:
+    """n Gauss-Legendre nodes and weights on [0, 1], in long double.
+
+    numpy's fp64 rule, refined by Newton steps on the Legendre series P_n
+    evaluated in long double; weights 2 / ((1 - x^2) P_n'(x)^2) on [-1, 1].
+    """
+    x, _ = leggauss(n)
+    x = x.astype(LD)
+    c = np.zeros(n + 1, dtype=LD)
+    c[n] = 1
+    dc = legendre.legder(c)
+    for _ in range(3):
+        x = x - legendre.legval(x, c) / legendre.legval(x, dc)
+    dp = legendre.legval(x, dc)
+    w = 2 / ((1 - x * x) * dp * dp)
+    return (x + 1) / 2, w / 2
 
 
 def gauss_legendre(n: int) -> tuple[np.ndarray, np.ndarray]:
     """n Gauss-Legendre nodes and weights mapped from [-1, 1] to [0, 1]."""
-    x, w = leggauss(n)
-    return 0.5 * (x + 1.0), 0.5 * w
+    x, w = gauss_legendre_ld(n)
+    return x.astype(np.float64), w.astype(np.float64)
+
+
+def inverse_ld(A: np.ndarray) -> np.ndarray:
+    """Inverse of a small square matrix by Gauss-Jordan elimination with
+    partial pivoting, in long double."""
+    A = np.array(A, dtype=LD)
+    n = A.shape[0]
+    aug = np.concatenate([A, np.eye(n, dtype=LD)], axis=1)
+    for c in range(n):
+        piv = c + int(np.argmax(np.abs(aug[c:, c])))
+        if aug[piv, c] == 0:
+            raise np.linalg.LinAlgError("singular matrix")
+        aug[[c, piv]] = aug[[piv, c]]
+        aug[c] = aug[c] / aug[c, c]
+        for r in range(n):
+            if r != c:
+                aug[r] = aug[r] - aug[r, c] * aug[c]
+    return aug[:, n:]
 
 
 def lagrange_basis(nodes: np.ndarray) -> list[Polynomial]:
@@ -48,10 +94,16 @@ def lagrange_basis(nodes: np.ndarray) -> list[Polynomial]:
     return basis
 
 
+def integral_ld(p: Polynomial, a, b):
+    """Integral of a polynomial over [a, b] via its antiderivative, in the
+    polynomial's own precision (long double for the tables' polynomials)."""
+    P = p.integ()
+    return P(LD(b)) - P(LD(a))
+
+
 def integrate(p: Polynomial, a: float, b: float) -> float:
     """Exact integral of a polynomial over [a, b] via its antiderivative."""
-    P = p.integ()
-    return float(P(b) - P(a))
+    return float(integral_ld(p, a, b))
 
 
 class Basis1D:
@@ -72,17 +124,23 @@ class Basis1D:
             raise ValueError("degree M must be >= 0")
         self.M = M
         self.n = n = M + 1
-        self.nodes, self.weights = gauss_legendre(n)
+        self.nodes_ld, self.weights_ld = gauss_legendre_ld(n)
+        self.nodes = self.nodes_ld.astype(np.float64)
+        self.weights = self.weights_ld.astype(np.float64)
+        # long-double basis for the tables; fp64 copies for evaluations
+        self.psi_ld = lagrange_basis(self.nodes_ld)
         self.psi = lagrange_basis(self.nodes)
+        dpsi = [p.deriv() for p in self.psi_ld]
         self.dpsi = [p.deriv() for p in self.psi]
-        self.psi0 = np.array([p(0.0) for p in self.psi])
-        self.psi1 = np.array([p(1.0) for p in self.psi])
-        self.mass = np.array([[integrate(self.psi[i] * self.psi[j], 0.0, 1.0)
-                               for j in range(n)] for i in range(n)])
-        self.stiff = np.array([[integrate(self.psi[i] * self.dpsi[j], 0.0, 1.0)
-                                for j in range(n)] for i in range(n)])
-        self.dmat = np.array([[self.dpsi[b](self.nodes[a]) for b in range(n)]
-                              for a in range(n)])
+        f64 = lambda rows: np.array(rows, dtype=LD).astype(np.float64)
+        self.psi0 = f64([p(LD(0)) for p in self.psi_ld])
+        self.psi1 = f64([p(LD(1)) for p in self.psi_ld])
+        self.mass = f64([[integral_ld(self.psi_ld[i] * self.psi_ld[j], 0, 1)
+                          for j in range(n)] for i in range(n)])
+        self.stiff = f64([[integral_ld(self.psi_ld[i] * dpsi[j], 0, 1)
+                           for j in range(n)] for i in range(n)])
+        self.dmat = f64([[dpsi[b](self.nodes_ld[a]) for b in range(n)]
+                         for a in range(n)])
 
     def time_matrix(self) -> np.ndarray:
         """Time factor of K^1 (Section 2.3, definition of K^1).
@@ -91,9 +149,10 @@ class Basis1D:
         and trial function s, psi_s'(1) psi_s(1) - int_0^1 psi_s'' psi_s dtau.
         """
         n = self.n
-        return np.array([[self.psi1[sp] * self.psi1[s]
-                          - integrate(self.dpsi[sp] * self.psi[s], 0.0, 1.0)
-                          for s in range(n)] for sp in range(n)])
+        p1 = [p(LD(1)) for p in self.psi_ld]
+        return np.array([[p1[sp] * p1[s]
+                          - integral_ld(self.psi_ld[sp].deriv() * self.psi_ld[s], 0, 1)
+                          for s in range(n)] for sp in range(n)], dtype=LD).astype(np.float64)
 
 
 @lru_cache(maxsize=None)

@@ -39,7 +39,7 @@ from functools import lru_cache
 
 import numpy as np
 
-from .basis import basis, integrate
+from .basis import LD, basis, integral_ld, inverse_ld
 
 LAMBDA_CENTRAL = 1.0e5
 LAMBDA_ONE_SIDED = 1.0
@@ -68,30 +68,36 @@ def reconstruction_matrix(M: int, L: int, R: int) -> np.ndarray:
     interval [0, 1]) holds int_o^(o+1) psi_p(xi) dxi: the average over that
     cell of the p-th basis function, in the home cell's reference coordinate.
     """
+    return reconstruction_matrix_ld(M, L, R).astype(np.float64)
+
+
+def reconstruction_matrix_ld(M: int, L: int, R: int) -> np.ndarray:
+    """reconstruction_matrix in long double (the inverse is taken from it)."""
     b = basis(M)
     offsets = range(-L, R + 1)
-    return np.array([[integrate(b.psi[p], o, o + 1.0) for p in range(b.n)]
-                     for o in offsets])
+    return np.array([[integral_ld(b.psi_ld[p], o, o + 1) for p in range(b.n)]
+                     for o in offsets], dtype=LD)
 
 
 def oscillation_matrix(M: int) -> np.ndarray:
     """Sigma_pm of eq. sigmas (derivatives of order 1..M, no mesh scaling)."""
     b = basis(M)
     n = b.n
-    S = np.zeros((n, n))
+    S = np.zeros((n, n), dtype=LD)
     for alpha in range(1, M + 1):
-        d = [p.deriv(alpha) for p in b.psi]
+        d = [p.deriv(alpha) for p in b.psi_ld]
         for p in range(n):
             for m in range(n):
-                S[p, m] += integrate(d[p] * d[m], 0.0, 1.0)
-    return S
+                S[p, m] += integral_ld(d[p] * d[m], 0, 1)
+    return S.astype(np.float64)
 
 
 @lru_cache(maxsize=None)
 def derivative_values(M: int) -> list:
     """[alpha-1][k, p] = d^alpha psi_p / dxi^alpha at Gauss node k, alpha = 1..M."""
     b = basis(M)
-    return [np.array([[p.deriv(alpha)(x) for p in b.psi] for x in b.nodes])
+    return [np.array([[p.deriv(alpha)(x) for p in b.psi_ld] for x in b.nodes_ld],
+                     dtype=LD).astype(np.float64)
             for alpha in range(1, M + 1)]
 
 
@@ -108,7 +114,8 @@ def oscillation_indicator(ws: np.ndarray, M: int) -> np.ndarray:
 def weno_constants(M: int):
     """Per-stencil inverse matrices, stencil windows, lambdas and Sigma."""
     sts = stencils(M)
-    inv = [np.linalg.inv(reconstruction_matrix(M, L, R)) for (L, R, _) in sts]
+    inv = [inverse_ld(reconstruction_matrix_ld(M, L, R)).astype(np.float64)
+           for (L, R, _) in sts]
     # window of stencil s inside the (2M+1)-cell line centred on the home cell
     windows = [(M - L, M + R + 1) for (L, R, _) in sts]
     lambdas = np.array([lam for (_, _, lam) in sts])

@@ -24,7 +24,9 @@ Workloads (conserved variables (rho, rho v, E), ideal gas):
   * linear advection of a smooth sine wave, and a seeded random field;
   * a generic test state on the unit cube: smooth sinusoidal density,
     velocity and pressure with seeded phases, a discontinuity (density x1.5,
-    pressure x1.8 for x < 0.4) and 1% seeded per-cell noise.
+    pressure x1.8 for x < 0.4) and 1% seeded per-cell noise;
+  * seeded tensor polynomials of degree <= M per axis (data every WENO
+    stencil reproduces).
 """
 from __future__ import annotations
 
@@ -177,6 +179,35 @@ def perturbed_smooth_euler(n, seed, noise=0.01, gamma=GAMMA):
     rho = rho * (1.0 + noise * r.uniform(-1.0, 1.0, size=rho.shape))
     vel = [v + noise * r.uniform(-1.0, 1.0, size=v.shape) for v in vel]
     return conserved_from_primitive(rho, vel, p, gamma)
+
+
+def polynomial_state(n, M, nv, lo, hi, seed, amp=0.1):
+    """Averages of seeded tensor polynomials of degree <= M per axis.
+
+    Variable v is base[v] + amp * sum_e c_e prod_k ((x_k - lo_k)/(hi_k - lo_k))^e_k
+    with c_e ~ U(-1, 1); the bases (1, 0, .., 0, 2.5) keep an Euler gas's
+    density and pressure positive.  Every WENO stencil reproduces such data,
+    so the reconstruction does not depend on the nonlinear weights.
+    """
+    d = len(n)
+    r = np.random.Generator(np.random.PCG64(seed))
+    base = np.zeros(nv)
+    base[0] = 1.0
+    if nv > 1:
+        base[-1] = 2.5
+    exps = list(np.ndindex(*([M + 1] * d)))
+    coef = r.uniform(-1.0, 1.0, size=(nv, len(exps)))
+
+    def fn(*c):
+        s = [(c[k] - lo[k]) / (hi[k] - lo[k]) for k in range(d)]
+        out = []
+        for v in range(nv):
+            acc = np.full(c[0].shape, base[v])
+            for j, e in enumerate(exps):
+                acc = acc + amp * coef[v, j] * np.prod([s[k] ** e[k] for k in range(d)], axis=0)
+            out.append(acc)
+        return np.stack(out)
+    return _cell_average(fn, tuple(n), tuple(lo), tuple(hi))
 
 
 def random_field(shape, seed, lo=-1.0, hi=1.0):

@@ -60,6 +60,16 @@ def max_rel(a, b):
     return float((np.abs(a - b) / np.maximum(1.0, np.abs(b))).max())
 
 
+def check_parity(got, ref, tol=1e-11, tol_max=None, label="parity"):
+    """Assert pooled relative L1 <= tol and element-wise max_rel <= tol_max
+    (default tol); print both; return them."""
+    l1, mx = rel_l1(got, ref), max_rel(got, ref)
+    print(f"{label}: pooled L1 {l1:.3e}, element-wise {mx:.3e}")
+    assert l1 <= tol, (l1, rel_l1_per_var(got, ref))
+    assert mx <= (tol if tol_max is None else tol_max), mx
+    return l1, mx
+
+
 def rel_l1_per_var(a, b):
     """Per-variable relative L1 (informative: a variable near zero, such as the
     momentum of a gas at rest, makes its own ratio meaningless)."""

@@ -1,7 +1,7 @@
 """AMR with local time stepping (ader_amr_*) against the oracle's AMR
 (oracle/amr.py): the same mesh from the same initial data (bit-exact status
 arrays), level averages of the active cells within 1e-11 pooled relative L1
-after level-0 steps, conservation, graph replay equal to direct launches,
+and element by element after level-0 steps, conservation, graph replay equal to direct launches,
 and the fp32-predictor form's stated error."""
 import numpy as np
 import pytest
@@ -10,7 +10,7 @@ from oracle import Euler, Problem as OProblem
 from oracle.amr import Hierarchy, amr_step
 from paper_1212_3585_amd import workloads as wl
 
-from gpu_helpers import rel_l1, say
+from gpu_helpers import max_rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -52,16 +52,24 @@ def _make(ader, dim, M, n0, r, L, Us, bc="periodic", flags=None, lo=0.0, hi=1.0,
     return H, A
 
 
-def _compare(H, A, tol=1e-11):
+def _compare(H, A, tol=1e-11, tol_max=None):
+    """Bit-exact status arrays; the active cells' averages within tol pooled
+    relative L1 and tol_max (default tol) element by element,
+    max |gpu - oracle| / max(1, |oracle|)."""
     num = den = 0.0
+    worst = 0.0
     for l in range(H.L + 1):
         U, st = A.level(l)
         assert np.array_equal(st, H.status[l])
         act = st == 0
         num += np.abs(U[:, act] - H.U[l][:, act]).sum()
         den += np.abs(H.U[l][:, act]).sum()
+        if act.any():
+            worst = max(worst, max_rel(U[:, act], H.U[l][:, act]))
     err = num / den
+    print(f"AMR parity: pooled L1 {err:.3e}, element-wise {worst:.3e}")
     assert err <= tol, err
+    assert worst <= (tol if tol_max is None else tol_max), worst
     return err
 
 
@@ -156,7 +164,8 @@ def test_amr_mixed_precision_error(ader):
     for _ in range(2):
         amr_step(H, 0.0, 1.0)
         A.step(1.0)
-    err = _compare(H, A, tol=1e-5)
+    # about ten times the measured 5.3e-8 pooled
+    err = _compare(H, A, tol=5e-7, tol_max=1e-5)
     print(f"fp32-predictor AMR relative L1 vs fp64 oracle: {err:.3e}")
 
 

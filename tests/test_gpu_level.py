@@ -1,12 +1,12 @@
 """ader_step_level: one step over explicit cell lists, against ader_step and
-the oracle (pooled relative L1 <= 1e-11)."""
+the oracle (pooled relative L1 and element-wise <= 1e-11)."""
 import numpy as np
 import pytest
 
 import oracle
 from paper_1212_3585_amd import workloads as wl
 
-from gpu_helpers import from_device, make_pair, rel_l1, say, to_device
+from gpu_helpers import check_parity, from_device, make_pair, rel_l1, say, to_device
 from level_views import mesh_level_view
 
 pytestmark = pytest.mark.gpu
@@ -45,7 +45,7 @@ def test_level_covering_the_mesh_equals_step(ader, precision):
     assert rel_l1(a, b) <= (1e-13 if precision == 0 else 1e-6)
     if precision == 0:
         Uo, _ = oracle.step(op, U, oracle.cfl_dt(op, U))
-        assert rel_l1(a, Uo) <= 1e-11
+        check_parity(a, Uo)
     assert s.read_level_status()[0] == 0
 
 
@@ -57,7 +57,7 @@ def test_level_3d_transmissive_against_oracle(ader):
     s = ader.Solver(gp)
     u, out = _step_level(ader, s, U, shape, 2, ["transmissive"] * 3, op.dx)
     Uo, _ = oracle.step(op, U, oracle.cfl_dt(op, U))
-    assert rel_l1(from_device(out, shape), Uo) <= 1e-11
+    check_parity(from_device(out, shape), Uo)
 
 
 def test_level_subset_band(ader):
@@ -71,7 +71,7 @@ def test_level_subset_band(ader):
     u, out = _step_level(ader, s, U, (N, N), 3, ["periodic"] * 2, op.dx, cells, dt)
     got = from_device(out, (N, N))
     ref, _ = oracle.step_cells(op, U, dt, cells)
-    assert rel_l1(got[:, cells[:, 0], cells[:, 1]], ref) <= 1e-11
+    check_parity(got[:, cells[:, 0], cells[:, 1]], ref)
     mask = np.ones((N, N), bool)
     mask[cells[:, 0], cells[:, 1]] = False
     assert np.array_equal(got[:, mask], U[:, mask])   # cells outside the level untouched

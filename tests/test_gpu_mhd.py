@@ -8,7 +8,7 @@ import pytest
 import oracle
 from paper_1212_3585_amd import workloads as wl
 
-from gpu_helpers import from_device, make_pair, rel_l1, say, to_device
+from gpu_helpers import check_parity, from_device, make_pair, max_rel, rel_l1, say, to_device
 
 pytestmark = pytest.mark.gpu
 L = 2.0 * np.pi
@@ -38,7 +38,7 @@ def test_mhd_step_parity(ader, M, n):
     op, gp = make_pair(ader, 2, M, (n, n), (0, 0), (L, L), system="mhd")
     U = wl.orszag_tang(n, seed=10 + M)
     got, ref, s = _steps(ader, op, gp, U, 3)
-    assert rel_l1(got, ref) <= 1e-11
+    check_parity(got, ref)
     assert s.read_status()[0] == 0
 
 
@@ -50,7 +50,7 @@ def test_mhd_orszag_tang_to_t(ader):
     u, t, steps = s.run(to_device(U0), 0.1)
     Uo, to, so, _ = oracle.run(op, U0, 0.1)
     assert steps == so and abs(t - to) <= 1e-14
-    assert rel_l1(from_device(u, (32, 32)), Uo) <= 1e-11
+    check_parity(from_device(u, (32, 32)), Uo)
 
 
 def test_mhd_3d_transmissive(ader):
@@ -64,7 +64,7 @@ def test_mhd_3d_transmissive(ader):
     B = [1.5 + 0 * rho, 0.8 * np.sin(2 * np.pi * X[0]), 0.5 * np.cos(2 * np.pi * X[1])]
     U = wl.mhd_conserved(rho, vel, 1.0 + 0 * rho, B)
     got, ref, _ = _steps(ader, op, gp, U, 2)
-    assert rel_l1(got, ref) <= 1e-11
+    check_parity(got, ref)
 
 
 def test_mhd_mixed_precision_error_is_stated(ader):
@@ -75,8 +75,10 @@ def test_mhd_mixed_precision_error_is_stated(ader):
     U = wl.orszag_tang(24, seed=3)
     got, ref, s = _steps(ader, op, gp, U, 3, same_dt=False)
     err = rel_l1(got, ref)
-    print(f"fp32-predictor MHD relative L1 vs fp64 oracle: {err:.3e}")
-    assert err <= 1e-5
+    print(f"fp32-predictor MHD relative L1 vs fp64 oracle: {err:.3e}, "
+          f"element-wise {max_rel(got, ref):.3e}")
+    # about ten times the measured 5.1e-8
+    assert err <= 5e-7
     assert s.read_status()[0] == 0
 
 

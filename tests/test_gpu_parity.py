@@ -26,10 +26,12 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-11
 # fp32-predictor bars, about ten times the measured errors against the fp64
 # oracle (3 steps of the smooth test state; one step of the 3D blast sample)
-MIXED_STEP_L1 = {2: 1e-5, 3: 1e-5}
-MIXED_STEP_MAX = {2: 1e-4, 3: 1e-4}
-MIXED_BLAST_L1 = 1e-5
-MIXED_BLAST_MAX = 1e-4
+# (measured: 2D 6.7e-8 / 6.2e-7, 3D 1.6e-8 / 5.6e-8, blast 3.1e-9 / 1.4e-8,
+# pooled / element-wise; traces up to 1.2e-5 on rough data)
+MIXED_STEP_L1 = {2: 7e-7, 3: 2e-7}
+MIXED_STEP_MAX = {2: 6e-6, 3: 6e-7}
+MIXED_BLAST_L1 = 3e-8
+MIXED_BLAST_MAX = 1.5e-7
 MIXED_TRACE_MAX = 1e-4
 
 
@@ -82,9 +84,13 @@ def test_reconstruction_parity(ader, dim, M, n, bc):
     wh = s.reconstruct(to_device(U)).cpu().numpy()
     w = oracle_reconstruct(U, all_cells(op), M, op.bc[:dim])
     ref = oracle_wh_to_gpu_layout(w, dim)
-    # the nonlinear weights (exponent 8) make w_h sensitive to rounding: the
-    # oracle itself moves by up to ~2e-12 under 1-ulp input perturbations
-    np.testing.assert_allclose(wh, ref, rtol=0, atol=2e-11 * np.abs(ref).max())
+    # the nonlinear weights (exponent 8) make w_h sensitive to rounding; with
+    # constant tables accurate to fp64 both sides sit within 1e-13 of a
+    # long-double evaluation on this data (M = 3: kernels 4e-15, oracle 5e-14)
+    err = float(np.abs(wh - ref).max() / np.abs(ref).max())
+    print(f"reconstruction: element-wise {err:.3e} of max|w_h|, pooled "
+          f"{np.abs(wh - ref).sum() / np.abs(ref).sum():.3e}")
+    assert err <= 1e-12
     assert np.abs(wh - ref).sum() / np.abs(ref).sum() <= 1e-13
 
 
@@ -122,11 +128,45 @@ def test_predictor_parity(ader, dim, M, system, ncells):
     np.testing.assert_allclose(got, q, rtol=0, atol=1e-12 * max(1.0, np.abs(q).max()))
     flags, iters = s.read_status()
     assert flags == 0
-    # per-cell stopping rule as the oracle: total iterations agree closely
-    assert abs(iters - int(it.sum())) <= max(2, 0.02 * it.sum())
+    # per-cell stopping rule as the oracle: total iterations agree closely.
+    # The threshold is about a hundred ulps of the state, so rounding moves a
+    # few cells by a few sweeps (the oracle alone, on the rough 2D M = 3
+    # linear-advection state: 91 cells stop at 7 sweeps, 5 at 8, 4 at 11)
+    assert abs(iters - int(it.sum())) <= max(2, 0.05 * it.sum())
 
 
 # ------------------------------------------------------------ cell kernel traces
+# Bars of the production cell kernel's traces (element-wise, relative to
+# max(1, |oracle|)).  On general data the traces inherit the reconstruction's
+# sensitivity to rounding (the weights' exponent 8; measured up to 4.5e-13);
+# on polynomial data every stencil reproduces the data, the weights drop out
+# and the bar isolates the predictor and the trace contraction (measured up
+# to 7e-14).
+TRACE_MAX_GENERAL = 5e-12
+TRACE_MAX_POLY = 1e-12
+MIXED_TRACE_MAX_POLY = 2e-5
+
+
+def _cell_kernel_traces(ader, M, n, bc, system, precision, U):
+    """(gpu traces [f][v, C, s, b], oracle traces, gpu sweeps, oracle sweeps)."""
+    import torch
+    from oracle.scheme import _predict_cells, traces as oracle_traces
+    op, gp = make_pair(ader, 2, M, n, (0, 0), (1.0, 1.5), bc, system=system,
+                       precision=precision, tol=1e-14 if precision == 0 else 1e-6)
+    op64, _ = make_pair(ader, 2, M, n, (0, 0), (1.0, 1.5), bc, system=system)
+    dt = 0.9 * oracle.cfl_dt(op64, U)
+    q, it = _predict_cells(op64, U, all_cells(op64), dt)
+    s = ader.Solver(gp)
+    s.clear_status()
+    dtd = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    tr = s.traces(to_device(U), dt=dtd).cpu().numpy()       # [f, C, v, s, b]
+    got = [np.transpose(tr[f], (1, 0, 2, 3)) for f in range(4)]
+    ref = [oracle_traces(q, op64, f // 2, f % 2) for f in range(4)]   # [v, C, s, b]
+    flags, iters = s.read_status()
+    assert flags == 0
+    return got, ref, iters, int(it.sum())
+
+
 @pytest.mark.parametrize("M,n,bc,system,precision", [
     (3, (37, 29), "periodic", "euler", 0), (2, (21, 18), "transmissive", "euler", 0),
     (1, (13, 9), "periodic", "euler", 0), (0, (9, 7), "periodic", "euler", 0),
@@ -139,36 +179,42 @@ def test_cell_kernel_traces_parity(ader, M, n, bc, system, precision):
     all four faces of every cell, element by element (Section 2.3, eq.
     stdg.final; the operands of eqs. flux:F and flux:G)."""
     say(f"cell-kernel traces M={M} n={n} bc={bc} {system} precision={precision}")
-    import torch
-    from oracle.scheme import _predict_cells, traces as oracle_traces
     if system == "euler":
         U = _euler_random(n, 60 + M, 2)
     elif system == "mhd":
         U = wl.orszag_tang(n[0], seed=3)[:, :, :n[1]]
     else:
         U = wl.random_field((1,) + n, 61)
-    op, gp = make_pair(ader, 2, M, n, (0, 0), (1.0, 1.5), bc, system=system,
-                       precision=precision, tol=1e-14 if precision == 0 else 1e-6)
-    op64, _ = make_pair(ader, 2, M, n, (0, 0), (1.0, 1.5), bc, system=system)
-    dt = 0.9 * oracle.cfl_dt(op64, U)
-    q, it = _predict_cells(op64, U, all_cells(op64), dt)
-    s = ader.Solver(gp)
-    s.clear_status()
-    dtd = torch.tensor([dt], dtype=torch.float64, device="cuda")
-    tr = s.traces(to_device(U), dt=dtd).cpu().numpy()       # [f, C, v, s, b]
-    worst = 0.0
-    for f in range(4):
-        ref = oracle_traces(q, op64, f // 2, f % 2)          # [v, C, s, b]
-        got = np.transpose(tr[f], (1, 0, 2, 3))
-        worst = max(worst, max_rel(got, ref))
-    flags, iters = s.read_status()
+    got, ref, iters, it = _cell_kernel_traces(ader, M, n, bc, system, precision, U)
+    worst = max(max_rel(g, r) for g, r in zip(got, ref))
     print(f"traces: element-wise max |gpu - oracle| / max(1, |oracle|) = {worst:.3e}")
-    assert flags == 0
     if precision == 0:
-        assert worst <= 1e-12
-        assert abs(iters - int(it.sum())) <= max(2, 0.02 * it.sum())
+        assert worst <= TRACE_MAX_GENERAL
+        assert abs(iters - it) <= max(2, 0.05 * it)
     else:
         assert worst <= MIXED_TRACE_MAX
+
+
+@pytest.mark.parametrize("M,n,system,precision", [
+    (3, (23, 19), "euler", 0), (2, (21, 18), "euler", 0), (1, (13, 9), "euler", 0),
+    (3, (24, 13), "linadv", 0),
+    (3, (23, 19), "euler", 1), (2, (21, 18), "euler", 1), (1, (13, 9), "euler", 1)])
+def test_cell_kernel_traces_polynomial_data(ader, M, n, system, precision):
+    """Stage test of the cell kernel's predictor and traces: on polynomial data
+    of degree <= M every stencil reproduces the data (Section 2.2), so w_h does
+    not depend on the nonlinear weights and the traces of the cells whose
+    stencils stay inside the transmissive mesh isolate the Picard iteration
+    (matrix cores in fp64, DPP lane exchanges in fp32) and the contraction
+    with psi(0), psi(1)."""
+    say(f"cell-kernel traces, polynomial data M={M} n={n} {system} precision={precision}")
+    nv = 4 if system == "euler" else 1
+    U = wl.polynomial_state(n, M, nv, (0.0, 0.0), (1.0, 1.5), seed=70 + M)
+    got, ref, iters, it = _cell_kernel_traces(ader, M, n, "transmissive", system,
+                                              precision, U)
+    inner = np.array([i + n[0] * j for j in range(M, n[1] - M) for i in range(M, n[0] - M)])
+    worst = max(max_rel(g[:, inner], r[:, inner]) for g, r in zip(got, ref))
+    print(f"traces (interior cells, polynomial data): element-wise {worst:.3e}")
+    assert worst <= (TRACE_MAX_POLY if precision == 0 else MIXED_TRACE_MAX_POLY)
 
 
 # ------------------------------------------------------------ full step
@@ -406,7 +452,7 @@ def test_explosion_900_sampled(ader):
 def test_blast_3d_64_sampled(ader, precision):
     """Spherical blast on [-1,1]^3, 64^3, M = 2, transmissive: one step,
     sampled cells against the fp64 oracle (fp64: 1e-11; fp32 predictor:
-    stated, < 1e-5)."""
+    stated, about ten times the measured error)."""
     say(f"3D blast 64^3 M=2 sampled precision={precision}")
     N = 64
     U0 = wl.blast_3d(N)

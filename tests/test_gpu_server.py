@@ -8,7 +8,7 @@ import pytest
 import oracle
 from paper_1212_3585_amd import workloads as wl
 
-from gpu_helpers import make_pair, rel_l1, say, to_device, from_device
+from gpu_helpers import check_parity, from_device, make_pair, say, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -86,7 +86,7 @@ def test_server_vortex_matches_oracle(ader):
     Uo, t, steps, _ = oracle.run(op, U0, 1.0)
     info = srv.info(rid)
     assert info["steps"] == steps and info["t"] == t
-    assert rel_l1(srv.result(rid), Uo) <= 1e-11
+    check_parity(srv.result(rid), Uo)
     srv.close()
 
 
