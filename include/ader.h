@@ -143,6 +143,31 @@ ader_status ader_compute_dt(ader_plan plan, const double* u, int64_t ld,
 ader_status ader_step(ader_plan plan, const double* u_in, double* u_out,
                       int64_t ld, const double* dt_dev, void* ws, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): ader_step
+ * with its workspace taken from a device array inside the library instead of
+ * a caller-allocated one.  The array holds ADER_STATIC_SCRATCH_BYTES; each GPU
+ * the library runs on holds its own copy until the process ends.  Same
+ * arguments, layouts and results as ader_step (the same kernels, bit for
+ * bit), minus 'ws':
+ *   status  NULL, or caller-owned device memory for two uint32 written at the
+ *           end of the call: [0] the status bits of this call (ADER_FLAG_*),
+ *           [1] its Picard sweeps summed over the cells (saturated at
+ *           2^32 - 1).  Each call starts from a zero status.
+ * The call makes no hipMalloc, hipFree or other allocating call; its first
+ * call on a device looks the array up there (hipGetSymbolAddress).
+ * Errors: as ader_step; EWORKSPACE (before any launch) when the plan's step
+ * needs more than ADER_STATIC_SCRATCH_BYTES (2D Euler, M = 3, fp64: 2 KiB per
+ * cell, so up to about 32,000 cells; ader_workspace_bytes gives the whole
+ * workspace, of which the step uses the leading part).
+ * All calls on one GPU share that GPU's array and it keeps the last call's
+ * contents: calls that overlap in time on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller. */
+#define ADER_STATIC_SCRATCH_BYTES (64ull << 20)
+ader_status ader_step_static(ader_plan plan, const double* u_in, double* u_out,
+                             int64_t ld, const double* dt_dev, uint32_t* status,
+                             void* stream);
+
 /* Stage entry points (for stage-by-stage checks):
  *
  * ader_debug_reconstruct: WENO polynomial of every cell (Section 2.2),

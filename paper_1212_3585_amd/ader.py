@@ -26,6 +26,7 @@ FLAG_NAN, FLAG_NONPHYSICAL, FLAG_NOCONV, FLAG_BADINDEX = 1, 2, 4, 8
 EXPORTS = [
     "ader_plan_create", "ader_plan_destroy", "ader_plan_nvar",
     "ader_workspace_bytes", "ader_clear_status", "ader_compute_dt", "ader_step",
+    "ader_step_static",
     "ader_debug_reconstruct", "ader_debug_predict", "ader_debug_traces", "ader_read_status",
     "ader_debug_constants", "ader_profile_begin", "ader_profile_end", "ader_tune",
     "ader_set_tile_rows",
@@ -118,6 +119,7 @@ def load_library():
         "ader_clear_status": [vp, vp, vp],
         "ader_compute_dt": [vp, vp, i64, dbl, dbl, vp, vp, vp],
         "ader_step": [vp, vp, vp, i64, vp, vp, vp],
+        "ader_step_static": [vp, vp, vp, i64, vp, vp, vp],
         "ader_debug_reconstruct": [vp, vp, i64, vp, vp, vp],
         "ader_debug_predict": [vp, vp, i64, vp, vp, vp, vp],
         "ader_debug_traces": [vp, vp, i64, vp, vp, vp, vp],
@@ -288,6 +290,16 @@ class Solver:
         dt = self.dt if dt is None else dt
         _check(self.lib.ader_step(self._plan, _ptr(u_in), _ptr(u_out), u_in.shape[1],
                                   _ptr(dt), _ptr(self.ws), _stream(stream)), "ader_step")
+        return u_out
+
+    def step_static(self, u_in, u_out, dt=None, status=None, stream=None):
+        """ader_step_static: the step on the library's static device workspace
+        (no workspace argument); status: None or a device int32/uint32 tensor
+        of two entries (status bits, Picard sweeps of this call)."""
+        dt = self.dt if dt is None else dt
+        _check(self.lib.ader_step_static(self._plan, _ptr(u_in), _ptr(u_out), u_in.shape[1],
+                                         _ptr(dt), None if status is None else _ptr(status),
+                                         _stream(stream)), "ader_step_static")
         return u_out
 
     def reconstruct(self, u, stream=None):

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -279,6 +280,84 @@ ader_status ader_step(ader_plan plan, const double* u_in, double* u_out, int64_t
   return hip_status(plan->impl->step(plan->data, u_in, u_out, ld, dt_dev, (char*)ws,
                                      (hipStream_t)stream),
                     "ader_step");
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free step: the workspace is a file-scope device array of
+// ADER_STATIC_SCRATCH_BYTES that every GPU the library runs on holds until
+// the process ends.  Host code never passes the array's name to a kernel (on
+// the host it is only a stand-in for the symbol): each device's address comes
+// from hipGetSymbolAddress, taken once per device with that device current on
+// the first call there, and is kept in g_scratch_dev.
+namespace {
+
+static __device__ __align__(256) unsigned char scratch[ADER_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_dev[kMaxDevices] = {};
+
+ader_status static_scratch(char** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_status(e, "ader_step_static: hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(ADER_EUNSUPPORTED, "ader_step_static: device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_status(e, "ader_step_static: hipGetSymbolAddress");
+    if (!ptr || reinterpret_cast<uintptr_t>(ptr) % 256 != 0)
+      return fail(ADER_EHIP, "ader_step_static: static workspace address is not 256-byte aligned");
+    g_scratch_dev[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_dev[dev];
+  return ADER_OK;
+}
+
+// status[0] = the header's status bits, status[1] = its Picard sweeps summed
+// over the counter slots (saturated to 32 bits).
+__global__ void k_static_status(const ader::WsHeader* __restrict__ hdr, uint32_t* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  unsigned long long total = 0;
+  for (int i = 0; i < ader::kCounterSlots; ++i) total += hdr->iters[i];
+  out[0] = hdr->status;
+  out[1] = total > 0xffffffffull ? 0xffffffffu : (uint32_t)total;
+}
+
+}  // namespace
+
+extern "C" {
+
+ader_status ader_step_static(ader_plan plan, const double* u_in, double* u_out, int64_t ld,
+                             const double* dt_dev, uint32_t* status, void* stream) {
+  if (!plan || !dt_dev) return fail(ADER_EINVAL, "null argument");
+  if (ader_status s = check_state(plan, u_in, ld)) return s;
+  if (ader_status s = check_state(plan, u_out, ld)) return s;
+  const uintptr_t a0 = (uintptr_t)u_in, b0 = (uintptr_t)u_out;
+  const uintptr_t len = sizeof(double) * (uintptr_t)plan->data.nv * (uintptr_t)ld;
+  if (a0 < b0 + len && b0 < a0 + len) return fail(ADER_EINVAL, "u_in and u_out overlap");
+  if (plan->data.step_bytes > (size_t)ADER_STATIC_SCRATCH_BYTES)
+    return fail(ADER_EWORKSPACE,
+                "ader_step_static: this plan's step needs " +
+                    std::to_string(plan->data.step_bytes) + " bytes of workspace, the static "
+                    "workspace holds " + std::to_string((size_t)ADER_STATIC_SCRATCH_BYTES) +
+                    "; use ader_step with a caller-allocated workspace");
+  char* ws = nullptr;
+  if (ader_status s = static_scratch(&ws)) return s;
+  const hipStream_t st = (hipStream_t)stream;
+  // the array keeps the previous call's contents: start from a zero header
+  hipError_t e = plan->impl->clear_status(ws, st);
+  if (e == hipSuccess) e = plan->impl->step(plan->data, u_in, u_out, ld, dt_dev, ws, st);
+  if (e == hipSuccess && status) {
+    hipLaunchKernelGGL(k_static_status, dim3(1), dim3(64), 0, st,
+                       reinterpret_cast<const ader::WsHeader*>(ws), status);
+    e = hipGetLastError();
+  }
+  return hip_status(e, "ader_step_static");
 }
 
 ader_status ader_debug_reconstruct(ader_plan plan, const double* u, int64_t ld, double* w_h,

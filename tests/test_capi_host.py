@@ -103,6 +103,30 @@ def test_compute_calls_validate_before_launching(ader_mod):
     lib.ader_plan_destroy(plan)
 
 
+def test_static_step_validates_before_launching(ader_mod):
+    """ader_step_static checks its arguments and the static workspace's size
+    before any HIP call."""
+    lib = ader_mod.load_library()
+    st, plan = _create(ader_mod, dim=2, M=2, n=(8, 8, 1))
+    assert st == 0
+    fake = ctypes.c_void_p(0x10000)
+    dt = ctypes.c_void_p(0x30000)
+    assert lib.ader_step_static(plan, fake, fake, 64, dt, None, None) == -1
+    assert lib.ader_step_static(plan, fake, ctypes.c_void_p(0x10000 + 8), 64, dt, None,
+                                None) == -1
+    assert lib.ader_step_static(plan, fake, ctypes.c_void_p(0x90000), 63, dt, None, None) == -1
+    assert lib.ader_step_static(plan, fake, ctypes.c_void_p(0x90000), 64, None, None,
+                                None) == -1
+    lib.ader_plan_destroy(plan)
+    # 512^2 at M = 3 needs 512 MiB of traces: more than the static 64 MiB
+    st, plan = _create(ader_mod, dim=2, M=3, n=(512, 512, 1))
+    assert st == 0
+    big = ctypes.c_void_p(0x100000000)
+    assert lib.ader_step_static(plan, fake, big, 512 * 512, dt, None, None) == -4
+    assert b"static workspace" in lib.ader_last_error()
+    lib.ader_plan_destroy(plan)
+
+
 @pytest.mark.parametrize("M", [0, 1, 2, 3])
 def test_device_path_constants_agree_with_oracle(ader_mod, M):
     """The library's long-double generator and the oracle's exact polynomial
