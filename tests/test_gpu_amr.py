@@ -136,6 +136,91 @@ def test_amr_3d_parity(ader):
     _compare(H, A)
 
 
+_ORACLE_AFTER = {}
+
+
+def _oracle_steps(key, H, steps):
+    """The oracle hierarchy after 'steps' level-0 steps, computed once per
+    case and shared by the fp64 and fp32-predictor variants of a test."""
+    if key not in _ORACLE_AFTER:
+        for _ in range(steps):
+            amr_step(H, 0.0, 1.0)
+        _ORACLE_AFTER[key] = H
+    return _ORACLE_AFTER[key]
+
+
+# fp32-predictor AMR bars (pooled, element-wise), about ten times the measured
+# errors against the fp64 oracle: 3D r = 3 patch 2.3e-8 / 1.4e-7, blast
+# 4.4e-9 / 3.2e-8, full-size explosion 3.0e-8 / 2.8e-7
+MIXED_AMR = {"3d_r3": (2e-7, 1.5e-6), "blast": (5e-8, 3e-7), "explosion": (3e-7, 3e-6)}
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_amr_3d_r3_parity(ader, precision):
+    """3D at the blast workload's refinement factor r = 3: a refined block
+    of 2 x 2 x 2 level-0 cells, two level-0 steps (three level-1 substeps
+    each), so that the projection at sub-cell offsets 0..2 and the face
+    memories summed over r^2 children meet (Section 3.1.3, eq. memory.sum)."""
+    say(f"AMR 3D 6^3 r=3 L=1 M=2 precision={precision}: 2 level-0 steps vs oracle")
+    n0, r = 6, 3
+    Us = _levels_from_fine(wl.perturbed_smooth_euler((n0 * r,) * 3, 14), r, 1)
+    F0 = np.zeros((n0,) * 3, bool)
+    F0[2:4, 2:4, 1:3] = True
+    H, A = _make(ader, 3, 2, n0, r, 1, Us, flags=[F0], precision=precision)
+    for c_gpu, c_or in zip([A.counts(l) for l in range(2)], H.counts()):
+        assert c_gpu == c_or
+    H = _oracle_steps("3d_r3", H, 2)
+    for _ in range(2):
+        A.step(1.0)
+    if precision == 0:
+        _compare(H, A)
+    else:
+        _compare(H, A, *MIXED_AMR["3d_r3"])
+    assert A.stats()["flags"] == 0
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_amr_blast_indicator_mesh_r3(ader, precision):
+    """The blast workload at a reduced level-0 mesh (8^3, r = 3, one level,
+    M = 2, transmissive, CFL 0.5): mesh from the Loehner indicator on the
+    energy, two level-0 steps."""
+    say(f"AMR 3D blast 8^3 r=3 L=1 M=2 precision={precision}: 2 level-0 steps vs oracle")
+    n0, r = 8, 3
+    Us = [wl.blast_3d(n0 * r ** l, seed=3, nq=2) for l in range(2)]
+    H, A = _make(ader, 3, 2, n0, r, 1, Us, bc="transmissive", lo=-1.0, hi=1.0,
+                 indicator_var=4, cfl=0.5, precision=precision)
+    assert H.counts()[1]["active"] > 0
+    H = _oracle_steps("blast", H, 2)
+    for _ in range(2):
+        A.step(1.0)
+    if precision == 0:
+        _compare(H, A)
+    else:
+        _compare(H, A, *MIXED_AMR["blast"])
+    assert A.stats()["flags"] == 0
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_amr_explosion_full_size_step(ader, precision):
+    """The 2D explosion workload at its full size (level 0 100^2, r = 3, two
+    levels, M = 2, transmissive, CFL 0.5, indicator on the energy): one
+    level-0 step (three level-1 and nine level-2 substeps) against the
+    oracle's AMR."""
+    say(f"AMR explosion 100^2 r=3 L=2 M=2 precision={precision}: 1 level-0 step vs oracle")
+    n0, r = 100, 3
+    Us = [wl.explosion_2d(n0 * r ** l, seed=2) for l in range(3)]
+    H, A = _make(ader, 2, 2, n0, r, 2, Us, bc="transmissive", lo=-1.0, hi=1.0,
+                 indicator_var=3, cfl=0.5, precision=precision)
+    assert H.counts()[2]["active"] > 20000
+    H = _oracle_steps("explosion", H, 1)
+    A.step(1.0)
+    if precision == 0:
+        _compare(H, A)
+    else:
+        _compare(H, A, *MIXED_AMR["explosion"])
+    assert A.stats()["flags"] == 0
+
+
 def test_amr_conservation_and_graph(ader):
     say("AMR conservation over 3 steps; graph replay equals direct launches")
     n0, r = 6, 3
