@@ -83,8 +83,9 @@ struct ader_amr_s {
   std::vector<std::vector<uint8_t>> h_flags;
   std::vector<std::vector<int8_t>> h_status;  // during the build only
   std::vector<void*> dev_allocs;
-  // per-level scratch of the active cells (wa, wh, qh, fbuf), grown on demand
-  std::vector<std::array<DevBuf, 4>> lvl_bufs;
+  // per-level scratch of the active cells (wa, wh, qh, fbuf), grown on demand,
+  // and the level's dense pass buffers (3D; sized by the index space)
+  std::vector<std::array<DevBuf, 5>> lvl_bufs;
   // per-level dense regrid arrays: flags, dilation scratch, previous status,
   // mother slots (list capacity = the level's cells)
   struct RegridLevel {
@@ -378,8 +379,15 @@ ader_status set_level_lists(ader_amr a, int l) {
   if (e == hipSuccess) e = select_count(a, ader::kSelVMother, v.st, nullptr, N, v.vm, &v.nvm);
   if (e == hipSuccess) e = ader::rg_positions(v.pos, N, v.act, v.nact, a->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
-  std::array<DevBuf, 4>& B = a->lvl_bufs[l];
+  std::array<DevBuf, 5>& B = a->lvl_bufs[l];
   const size_t na = (size_t)v.nact;
+  const size_t dense = sizeof(double) * a->impl->dense_weno_per_cell() * (size_t)N;
+  if (e == hipSuccess && dense > 0 && !v.dwx) {
+    // allocated once (the index space is fixed) and zeroed, so that lines no
+    // reconstruction reads never hold uninitialised memory
+    e = fill_buf(B[4], &v.dwx, nullptr, dense);
+    if (e == hipSuccess) e = hipMemsetAsync(v.dwx, 0, dense, a->stream);
+  }
   if (e == hipSuccess)
     e = fill_buf(B[0], &v.wa, nullptr, sizeof(double) * a->impl->weno_scratch_per_cell() * na);
   if (e == hipSuccess)

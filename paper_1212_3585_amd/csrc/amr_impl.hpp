@@ -7,6 +7,7 @@
 #include "amr.hpp"
 #include "predict_mfma.hpp"
 #include "predict_wave.hpp"
+#include "weno3d.hpp"
 
 namespace ader {
 
@@ -27,6 +28,7 @@ class AmrImpl final : public AmrImplBase {
     return (size_t)NV * (n * Pow<S, DIM - 1>::v + (DIM == 3 ? n * n * S : 0));
   }
   size_t wh_per_cell() const override { return (size_t)NV * Pow<n, DIM>::v; }
+  size_t dense_weno_per_cell() const override { return DIM == 3 ? (size_t)NV * (n + n * n) : 0; }
   size_t fbuf_per_cell() const override { return (size_t)2 * DIM * NV; }
 
   hipError_t cfl(const AmrLevel& lv, double* partial, int nb, hipStream_t st) const override {
@@ -131,23 +133,29 @@ class AmrImpl final : public AmrImplBase {
     unsigned int* flags = &lv.hdr->status;
     double* pass0 = lv.wa;
     double* pass1 = DIM == 2 ? lv.wh : lv.wb;
-    if constexpr (DIM == 2) {
-      // 2D: the predictor kernels reconstruct their own cells (fused)
-      (void)flags;
-      (void)pass0;
-      (void)pass1;
-    } else {
-    hipLaunchKernelGGL((k_amr_weno_x<DIM, M, NV>), dim3(amr_blocks(np * NV * Pow<S, DIM - 1>::v)),
-                       dim3(kBlock), 0, st, lv.u, lv.ncells, lv.act, np, lv.mp, pass0, c);
-    hipLaunchKernelGGL((k_level_weno_pass<DIM, M, NV, 1>),
-                       dim3(amr_blocks(np * NV * n * Pow<S, DIM - 2>::v)), dim3(kBlock), 0, st,
-                       (const double*)nullptr, (int64_t)0, (const int32_t*)nullptr,
-                       (const double*)pass0, pass1, np, c, flags);
-    }
+    (void)flags;
+    (void)pass0;
+    (void)pass1;
     if constexpr (DIM == 3) {
-      hipLaunchKernelGGL((k_level_weno_pass<DIM, M, NV, 2>), dim3(amr_blocks(np * NV * n * n)),
-                         dim3(kBlock), 0, st, (const double*)nullptr, (int64_t)0,
-                         (const int32_t*)nullptr, (const double*)lv.wb, lv.wh, np, c, flags);
+      // x and y lines once per non-absent cell of the level into its dense
+      // pass buffers, then the z pass of the active cells into w_h
+      CellLists cl;
+      cl.l[0] = lv.act;
+      cl.n[0] = np;
+      cl.l[1] = lv.vc;
+      cl.n[1] = lv.nvc;
+      cl.l[2] = lv.vm;
+      cl.n[2] = lv.nvm;
+      const int64_t E = cl.total();
+      double* dwxy = lv.dwx + (size_t)NV * n * lv.ncells;
+      hipLaunchKernelGGL((k_dense_weno_x<M, NV>), dim3(amr_blocks(E * NV)), dim3(kBlock), 0, st,
+                         lv.u, lv.ncells, cl, lv.mp, lv.dwx, lv.ncells, c);
+      hipLaunchKernelGGL((k_dense_weno_y<M, NV>), dim3(amr_blocks(E * NV * n)), dim3(kBlock), 0,
+                         st, (const double*)lv.dwx, cl, lv.mp, dwxy, lv.ncells, c);
+      constexpr int ZC = ZPassCells<M>::v;
+      hipLaunchKernelGGL((k_weno_z_aos<M, NV>), dim3((unsigned)((np + ZC - 1) / ZC)),
+                         dim3(kBlock), 0, st, (const double*)dwxy, lv.ncells, lv.act, np, lv.mp,
+                         lv.wh, c);
     }
     R* qh = static_cast<R*>(lv.qh);
     if constexpr (DIM == 2 && std::is_same<R, double>::value) {

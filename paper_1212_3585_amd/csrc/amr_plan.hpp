@@ -51,6 +51,7 @@ struct AmrLevel {
   double* wa = nullptr;       // WENO pass buffers of the active cells
   double* wb = nullptr;
   double* wh = nullptr;       // reconstruction w_h of the active cells
+  double* dwx = nullptr;      // 3D: dense x- and y-pass lines [nv][n + n^2][ncells]
   void* qh = nullptr;         // predictor of the active cells (predictor precision)
   double* fbuf = nullptr;     // face fluxes of the active cells [cell][2 dim][nv]
   WsHeader* hdr = nullptr;    // status bits and Picard counters of the level
@@ -73,6 +74,8 @@ class AmrImplBase {
   // WENO scratch doubles per active cell (two pass buffers) and w_h doubles
   virtual size_t weno_scratch_per_cell() const = 0;
   virtual size_t wh_per_cell() const = 0;
+  // doubles per cell of the level's index space of the dense pass buffers
+  virtual size_t dense_weno_per_cell() const = 0;
   // face-flux doubles per active cell
   virtual size_t fbuf_per_cell() const = 0;
   // block maxima of sum_k speed_k / dx_k over the active cells -> partial[0..nb)

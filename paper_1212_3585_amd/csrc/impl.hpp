@@ -9,6 +9,7 @@
 #include "level.hpp"
 #include "predict_mfma.hpp"
 #include "predict_wave.hpp"
+#include "weno3d.hpp"
 
 namespace ader {
 
@@ -76,9 +77,10 @@ struct Impl final : ImplBase {
       double* wxy = reinterpret_cast<double*>(ws + p.off_wxy);
       hipLaunchKernelGGL((k_weno_pass<DIM, M, NV, 1, false>), dim3(blocks_for(C * NV * n)),
                          dim3(kBlock), 0, st, (const double*)wx, C, n, wxy, mp, p.dc);
-      hipLaunchKernelGGL((k_weno_pass<DIM, M, NV, 2, true>),
-                         dim3(blocks_for(C * NV * n * n)), dim3(kBlock), 0, st,
-                         (const double*)wxy, C, n * n, wh, mp, p.dc);
+      // z pass through LDS: each block writes its cells' w_h contiguously
+      hipLaunchKernelGGL((k_weno_z_aos<M, NV>), dim3(blocks_for(C, ZPassCells<M>::v)),
+                         dim3(kBlock), 0, st, (const double*)wxy, C, (const int32_t*)nullptr,
+                         C, mp, wh, p.dc);
     }
     return hipGetLastError();
   }
