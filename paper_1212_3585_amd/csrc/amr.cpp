@@ -83,9 +83,10 @@ struct ader_amr_s {
   std::vector<std::vector<uint8_t>> h_flags;
   std::vector<std::vector<int8_t>> h_status;  // during the build only
   std::vector<void*> dev_allocs;
-  // per-level scratch of the active cells (wa, wh, qh, fbuf), grown on demand,
-  // and the level's dense pass buffers (3D; sized by the index space)
-  std::vector<std::array<DevBuf, 5>> lvl_bufs;
+  // per-level scratch of the active cells (wa, wh, qh, fbuf, coarse-fine
+  // face list), grown on demand, and the level's dense pass buffers (3D;
+  // sized by the index space)
+  std::vector<std::array<DevBuf, 6>> lvl_bufs;
   // per-level dense regrid arrays: flags, dilation scratch, previous status,
   // mother slots (list capacity = the level's cells)
   struct RegridLevel {
@@ -369,6 +370,26 @@ hipError_t select_count(ader_amr a, int mode, const int8_t* st, const int8_t* ol
   return e;
 }
 
+// The coarse-fine face lists of every level (after all levels' lists are
+// set: a level's faces depend on its neighbours in level l - 1 and l + 1).
+ader_status set_cf_lists(ader_amr a) {
+  hipError_t e = hipSuccess;
+  for (int l = 0; l <= a->L && e == hipSuccess; ++l) {
+    ader::AmrLevel& v = a->lv[l];
+    int c = 0;
+    e = hipMemsetAsync(a->d_count, 0, sizeof(int), a->stream);
+    if (e == hipSuccess)
+      e = a->impl->cf_faces(v, l > 0 ? &a->lv[l - 1] : nullptr,
+                            l < a->L ? &a->lv[l + 1] : nullptr, a->ac, a->d_count, a->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&c, a->d_count, sizeof(int), hipMemcpyDeviceToHost, a->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
+    v.ncf = c;
+  }
+  if (e != hipSuccess) return hip_status(e, "AMR coarse-fine face lists");
+  return ADER_OK;
+}
+
 // Lists, positions and scratch of level l from its device status.
 ader_status set_level_lists(ader_amr a, int l) {
   ader::AmrLevel& v = a->lv[l];
@@ -379,7 +400,7 @@ ader_status set_level_lists(ader_amr a, int l) {
   if (e == hipSuccess) e = select_count(a, ader::kSelVMother, v.st, nullptr, N, v.vm, &v.nvm);
   if (e == hipSuccess) e = ader::rg_positions(v.pos, N, v.act, v.nact, a->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
-  std::array<DevBuf, 5>& B = a->lvl_bufs[l];
+  std::array<DevBuf, 6>& B = a->lvl_bufs[l];
   const size_t na = (size_t)v.nact;
   const size_t dense = sizeof(double) * a->impl->dense_weno_per_cell() * (size_t)N;
   if (e == hipSuccess && dense > 0 && !v.dwx) {
@@ -396,6 +417,7 @@ ader_status set_level_lists(ader_amr a, int l) {
     e = fill_buf(B[2], &v.qh, nullptr, a->impl->qh_elem_size() * a->nv * ipow(M + 1, d + 1) * na);
   if (e == hipSuccess)
     e = fill_buf(B[3], &v.fbuf, nullptr, sizeof(double) * a->impl->fbuf_per_cell() * na);
+  if (e == hipSuccess) e = fill_buf(B[5], &v.cf, nullptr, sizeof(int32_t) * 2 * d * na);
   if (e != hipSuccess) return hip_status(e, "AMR level lists");
   v.wb = v.wa + (size_t)a->nv * (M + 1) * ipow(2 * M + 1, d - 1) * na;
   a->dtargs.nb[l] = v.nact == 0 ? 0
@@ -646,6 +668,7 @@ ader_status ader_amr_build(ader_amr a) {
   }
   for (int l = 0; l <= L; ++l)
     if (ader_status st = set_level_lists(a, l)) return st;
+  if (ader_status st = set_cf_lists(a)) return st;
   a->h_status.clear();
   a->h_status.shrink_to_fit();
   a->dtargs.nlev = L + 1;
@@ -770,6 +793,7 @@ ader_status ader_amr_regrid(ader_amr a, int* changed) {
   //    fine (a new cell's mother may be new itself); removed cells NaN
   for (int l = 0; l <= L; ++l)
     if (ader_status s = set_level_lists(a, l)) return s;
+  if (ader_status s = set_cf_lists(a)) return s;
   for (int l = 1; l <= L && e == hipSuccess; ++l) {
     const int64_t Nc = g[l - 1].N, Nf = g[l].N;
     auto& Rc = a->rg[l - 1];

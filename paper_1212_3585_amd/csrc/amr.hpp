@@ -16,6 +16,9 @@
 //                   the mother's reconstruction w_h over the child's sub-cell
 //   k_fill_list     one value into listed cells of every variable (the
 //                   memory of the virtual children before a level's substeps)
+//   k_amr_cf_faces  the list of a level's coarse-fine faces (when the lists
+//                   change)
+//   k_amr_flux_cf   fluxes of those faces, one group of lanes per face
 //   k_amr_flux      face fluxes of the active cells, one group of lanes per
 //                   (cell, axis), one lane per space-time point of the face;
 //                   each face once (a cell's high faces, and its low faces
@@ -400,23 +403,127 @@ __device__ __forceinline__ int amr_face_kind(const AmrUpdArgs& a, const MeshPara
   return -1;
 }
 
+// Flux of one face of active cell i (axis k, side) of the given kind (see
+// amr_face_kind), by a group of G lanes, lane g owning space-time point
+// (s = g / NT, tb = g % NT); the face average goes to
+// fbuf[(i * 2 DIM + 2 k + side) * NV + v].  A face to a virtual child also
+// adds its flux to the child's memory.  The group takes one path.
+template <int DIM, int M, int SYS, typename R, int G, int FLUX>
+__device__ __forceinline__ void amr_face_flux(const AmrUpdArgs& a, const MeshParams& mp,
+                                              const DevConsts& c, const AmrConsts& ac,
+                                              double* __restrict__ fbuf, int64_t i,
+                                              const int (&cc)[3], int k, int side, int type,
+                                              int64_t nb, int32_t pn, const int (&off)[3],
+                                              int g) {
+  constexpr int n = M + 1;
+  constexpr int NV = NVars<SYS, DIM>::v;
+  constexpr int NST = Pow<n, DIM + 1>::v;
+  constexpr int NT = Pow<n, DIM - 1>::v;
+  constexpr int NPT = n * NT;
+  constexpr int FS = 2 * DIM;
+  double F[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) F[v] = 0.0;
+  if (type == 3) {
+    // this lane's share of the memory of the cell's virtual children on the face
+    const int nsub = DIM == 2 ? a.r : a.r * a.r;
+    for (int j = g; j < nsub; j += G) {
+      int ch[3] = {0, 0, 0};
+      int t = 0;
+      for (int ax = 0; ax < DIM; ++ax) {
+        if (ax == k) {
+          ch[ax] = cc[ax] * a.r + (side ? a.r - 1 : 0);
+        } else {
+          const int aj = DIM == 2 ? j : (t == 0 ? j / a.r : j % a.r);
+          ch[ax] = cc[ax] * a.r + aj;
+          ++t;
+        }
+      }
+      const int64_t chd = dense_index<DIM>(ch, a.nf);
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        F[v] += a.mem_f[((int64_t)(k * 2 + side) * NV + v) * a.ldf + chd];
+    }
+  } else if (g < NPT) {
+    const int s = g / NT, tb = g % NT;
+    double qm[NV], qp[NV];
+    cell_trace<DIM, M, NV, R>(static_cast<const R*>(a.qh) + i * NV * NST, k, side, tb, s, c,
+                              qm);
+    if (type == 0) {
+      cell_trace<DIM, M, NV, R>(static_cast<const R*>(a.qh) + (int64_t)pn * NV * NST, k,
+                                1 - side, tb, s, c, qp);
+    } else if (type == 1) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) qp[v] = qm[v];
+    } else {
+      // coarse predictor at this face point and time node
+      const int tt[2] = {tb % n, tb / n};
+      double wt[4], wax[3][4];
+      int ti = 0;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) wt[p] = p < n ? ac.at_nodes[a.sub][s][p] : 0.0;
+      for (int ax = 0; ax < 3; ++ax) {
+        for (int p = 0; p < 4; ++p) {
+          double w = 0.0;
+          if (p < n && ax < DIM)
+            w = ax == k ? ac.at_face[off[ax]][1 - side][p] : ac.at_nodes[off[ax]][tt[ti]][p];
+          wax[ax][p] = w;
+        }
+        if (ax < DIM && ax != k) ++ti;
+      }
+      eval_predictor<DIM, M, NV, R>(static_cast<const R*>(a.qh_c) + (int64_t)pn * NV * NST, wt,
+                                    wax, qp);
+    }
+    double Fpt[NV];
+    if (side)
+      numerical_flux<SYS, DIM, FLUX>(qm, qp, k, mp, c, Fpt);
+    else
+      numerical_flux<SYS, DIM, FLUX>(qp, qm, k, mp, c, Fpt);
+    double wtp = c.w[s];
+    {
+      const int tt[2] = {tb % n, tb / n};
+      for (int dd = 0; dd < DIM - 1; ++dd) wtp *= c.w[tt[dd]];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = wtp * Fpt[v];
+  }
+  // group sum by a fixed butterfly
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] += __shfl_xor(F[v], o, 64);
+  if (g == 0) {
+    if (type == 3) {
+      const double inv = 1.0 / (DIM == 2 ? (double)(a.r * a.r) : (double)(a.r * a.r * a.r));
+#pragma unroll
+      for (int v = 0; v < NV; ++v) F[v] *= inv;
+    }
+    double* fo = fbuf + (i * FS + 2 * k + side) * NV;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fo[v] = F[v];
+    if (type == 2) {  // the face flux also goes to the coarse cell's memory
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        a.mem[((int64_t)(k * 2 + (1 - side)) * NV + v) * mp.ld + nb] += F[v];
+    }
+  }
+}
+
 // Face fluxes of the active cells: each cell computes its high face on every
 // axis, and its low face where the low neighbour is not an active cell of
 // the same level (that face is the neighbour's high face), so every face is
-// evaluated once.  Face-averaged fluxes go to
-// fbuf[(i * 2 DIM + 2 k + side) * NV + v].  A face to a virtual child also
-// adds its flux to the child's memory.
+// evaluated once.  This kernel takes the faces to active cells of the level
+// and through the boundary, a group of lanes per (cell, axis); the
+// coarse-fine faces (virtual children and virtual mothers) are listed once
+// per mesh (k_amr_cf_faces) and done by k_amr_flux_cf.  Keeping their paths
+// out of this kernel keeps its registers low (78 instead of 167 VGPRs at 3D
+// M = 2 fp64), so more wavefronts hide the latency of its gathers.
 template <int DIM, int M, int SYS, typename R, int TB = kBlock, int FLUX = -1>
 __global__ void __launch_bounds__((AmrFluxShape<DIM, M, TB>::BLOCK))
 k_amr_flux(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, double* __restrict__ fbuf,
            WsHeader* hdr) {
   using Sh = AmrFluxShape<DIM, M, TB>;
-  constexpr int n = M + 1;
-  constexpr int NV = NVars<SYS, DIM>::v;
-  constexpr int NST = Pow<n, DIM + 1>::v;
-  constexpr int NT = Sh::NT;
   constexpr int G = Sh::G;
-  constexpr int FS = 2 * DIM;
   const int tid = threadIdx.x;
   const int cs = tid / Sh::LPC;
   const int k = (tid % Sh::LPC) / G;
@@ -430,101 +537,62 @@ k_amr_flux(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, double* __res
   unsigned int flags = 0;
   int cc[3] = {0, 0, 0};
   if (valid) dense_coords<DIM>(a.act[i], mp.n, cc);
-  const R* qme = static_cast<const R*>(a.qh) + (valid ? i : 0) * NV * NST;
   for (int side = 1; side >= 0; --side) {
     int64_t nb = 0;
     int32_t pn = -1;
     int off[3] = {0, 0, 0};
     const int type = valid ? amr_face_kind<DIM>(a, mp, cc, k, side, &nb, &pn, off) : -2;
-    if (side == 0 && (type == 0 || type == -2)) continue;  // uniform in the group
     if (type == -1) flags |= kFlagBadIndex;
-    double F[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) F[v] = 0.0;
-    if (type == 3) {
-      // this lane's share of the memory of the cell's virtual children on the face
-      const int nsub = DIM == 2 ? a.r : a.r * a.r;
-      for (int j = g; j < nsub; j += G) {
-        int ch[3] = {0, 0, 0};
-        int t = 0;
-        for (int ax = 0; ax < DIM; ++ax) {
-          if (ax == k) {
-            ch[ax] = cc[ax] * a.r + (side ? a.r - 1 : 0);
-          } else {
-            const int aj = DIM == 2 ? j : (t == 0 ? j / a.r : j % a.r);
-            ch[ax] = cc[ax] * a.r + aj;
-            ++t;
-          }
-        }
-        const int64_t chd = dense_index<DIM>(ch, a.nf);
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-          F[v] += a.mem_f[((int64_t)(k * 2 + side) * NV + v) * a.ldf + chd];
-      }
-    } else if (type >= 0 && g < Sh::NPT) {
-      const int s = g / NT, tb = g % NT;
-      double qm[NV], qp[NV];
-      cell_trace<DIM, M, NV, R>(qme, k, side, tb, s, c, qm);
-      if (type == 0) {
-        cell_trace<DIM, M, NV, R>(static_cast<const R*>(a.qh) + (int64_t)pn * NV * NST, k,
-                                  1 - side, tb, s, c, qp);
-      } else if (type == 1) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) qp[v] = qm[v];
-      } else {
-        // coarse predictor at this face point and time node
-        const int tt[2] = {tb % n, tb / n};
-        double wt[4], wax[3][4];
-        int ti = 0;
-#pragma unroll
-        for (int p = 0; p < 4; ++p) wt[p] = p < n ? ac.at_nodes[a.sub][s][p] : 0.0;
-        for (int ax = 0; ax < 3; ++ax) {
-          for (int p = 0; p < 4; ++p) {
-            double w = 0.0;
-            if (p < n && ax < DIM)
-              w = ax == k ? ac.at_face[off[ax]][1 - side][p] : ac.at_nodes[off[ax]][tt[ti]][p];
-            wax[ax][p] = w;
-          }
-          if (ax < DIM && ax != k) ++ti;
-        }
-        eval_predictor<DIM, M, NV, R>(static_cast<const R*>(a.qh_c) + (int64_t)pn * NV * NST, wt,
-                                      wax, qp);
-      }
-      double Fpt[NV];
-      if (side)
-        numerical_flux<SYS, DIM, FLUX>(qm, qp, k, mp, c, Fpt);
-      else
-        numerical_flux<SYS, DIM, FLUX>(qp, qm, k, mp, c, Fpt);
-      double wtp = c.w[s];
-      {
-        const int tt[2] = {tb % n, tb / n};
-        for (int dd = 0; dd < DIM - 1; ++dd) wtp *= c.w[tt[dd]];
-      }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) F[v] = wtp * Fpt[v];
-    }
-    // group sum by a fixed butterfly (the group takes one path: no divergence)
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1)
-#pragma unroll
-      for (int v = 0; v < NV; ++v) F[v] += __shfl_xor(F[v], o, 64);
-    if (g == 0 && type >= 0) {
-      if (type == 3) {
-        const double inv = 1.0 / (DIM == 2 ? (double)(a.r * a.r) : (double)(a.r * a.r * a.r));
-#pragma unroll
-        for (int v = 0; v < NV; ++v) F[v] *= inv;
-      }
-      double* fo = fbuf + (i * FS + 2 * k + side) * NV;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) fo[v] = F[v];
-      if (type == 2) {  // the face flux also goes to the coarse cell's memory
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-          a.mem[((int64_t)(k * 2 + (1 - side)) * NV + v) * mp.ld + nb] += F[v];
-      }
-    }
+    // uniform in the group: the low face of an active neighbour is its high
+    // face; coarse-fine faces are the other kernel's
+    if (type < 0 || type >= 2 || (side == 0 && type == 0)) continue;
+    amr_face_flux<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, fbuf, i, cc, k, side, type, nb, pn,
+                                           off, g);
   }
   block_report(0u, flags, hdr);
+}
+
+// The coarse-fine faces of a level's active cells (kinds 2 and 3 of
+// amr_face_kind) as entries i * 2 DIM + 2 k + side; built when the level's
+// lists change.  The order of the entries does not matter: each face's flux
+// is computed on its own and written to its own slots.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_amr_cf_faces(AmrUpdArgs a, MeshParams mp, int32_t* __restrict__ list, int* __restrict__ count) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= a.nact * 2 * DIM) return;
+  const int64_t i = t / (2 * DIM);
+  const int f = (int)(t % (2 * DIM));
+  int cc[3] = {0, 0, 0};
+  dense_coords<DIM>(a.act[i], mp.n, cc);
+  int64_t nb = 0;
+  int32_t pn = -1;
+  int off[3] = {0, 0, 0};
+  const int type = amr_face_kind<DIM>(a, mp, cc, f >> 1, f & 1, &nb, &pn, off);
+  if (type >= 2) list[atomicAdd(count, 1)] = (int32_t)t;
+}
+
+// Fluxes of the listed coarse-fine faces: one group of lanes per entry.
+template <int DIM, int M, int SYS, typename R, int FLUX = -1>
+__global__ void __launch_bounds__(kBlock)
+k_amr_flux_cf(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac,
+              const int32_t* __restrict__ list, int64_t nlist, double* __restrict__ fbuf) {
+  constexpr int G = AmrFluxShape<DIM, M>::G;
+  const int64_t e = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  if (e >= nlist) return;  // uniform in the group
+  const int g = threadIdx.x % G;
+  const int32_t t = list[e];
+  const int64_t i = t / (2 * DIM);
+  const int k = (t % (2 * DIM)) >> 1, side = t & 1;
+  int cc[3] = {0, 0, 0};
+  dense_coords<DIM>(a.act[i], mp.n, cc);
+  int64_t nb = 0;
+  int32_t pn = -1;
+  int off[3] = {0, 0, 0};
+  const int type = amr_face_kind<DIM>(a, mp, cc, k, side, &nb, &pn, off);
+  if (type < 2) return;
+  amr_face_flux<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, fbuf, i, cc, k, side, type, nb, pn, off,
+                                         g);
 }
 
 // Conservative update of the active cells (eq. finite_vol) from the face

@@ -233,13 +233,32 @@ class AmrImpl final : public AmrImplBase {
                                 const AmrConsts& ac, hipStream_t st) {
     using Sh = AmrFluxShape<DIM, M, TB>;
     const unsigned nb = (unsigned)((lv.nact + Sh::CPB - 1) / Sh::CPB);
-    // one instantiation per flux (only Euler has the Osher-type flux)
-    if (SYS == 1 && lv.mp.flux == 1)
+    // one instantiation per flux (only Euler has the Osher-type flux); the
+    // listed coarse-fine faces in their own kernel
+    constexpr int GPB = kBlock / AmrFluxShape<DIM, M>::G;  // faces per block
+    const unsigned ncb = (unsigned)((lv.ncf + GPB - 1) / GPB);
+    if (SYS == 1 && lv.mp.flux == 1) {
       hipLaunchKernelGGL((k_amr_flux<DIM, M, SYS, R, TB, 1>), dim3(nb), dim3(Sh::BLOCK), 0, st,
                          a, lv.mp, c, ac, lv.fbuf, lv.hdr);
-    else
+      if (lv.ncf > 0)
+        hipLaunchKernelGGL((k_amr_flux_cf<DIM, M, SYS, R, 1>), dim3(ncb), dim3(kBlock), 0, st, a,
+                           lv.mp, c, ac, (const int32_t*)lv.cf, lv.ncf, lv.fbuf);
+    } else {
       hipLaunchKernelGGL((k_amr_flux<DIM, M, SYS, R, TB, 0>), dim3(nb), dim3(Sh::BLOCK), 0, st,
                          a, lv.mp, c, ac, lv.fbuf, lv.hdr);
+      if (lv.ncf > 0)
+        hipLaunchKernelGGL((k_amr_flux_cf<DIM, M, SYS, R, 0>), dim3(ncb), dim3(kBlock), 0, st, a,
+                           lv.mp, c, ac, (const int32_t*)lv.cf, lv.ncf, lv.fbuf);
+    }
+    return hipGetLastError();
+  }
+
+  hipError_t cf_faces(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
+                      const AmrConsts& ac, int* count, hipStream_t st) const override {
+    if (lv.nact == 0) return hipSuccess;
+    const AmrUpdArgs a = upd_args(lv, coarse, fine, nullptr, 0, ac);
+    hipLaunchKernelGGL((k_amr_cf_faces<DIM>), dim3(amr_blocks(lv.nact * 2 * DIM)), dim3(kBlock),
+                       0, st, a, lv.mp, lv.cf, count);
     return hipGetLastError();
   }
 

@@ -54,6 +54,8 @@ struct AmrLevel {
   double* dwx = nullptr;      // 3D: dense x- and y-pass lines [nv][n + n^2][ncells]
   void* qh = nullptr;         // predictor of the active cells (predictor precision)
   double* fbuf = nullptr;     // face fluxes of the active cells [cell][2 dim][nv]
+  int32_t* cf = nullptr;      // coarse-fine faces of the active cells (k_amr_cf_faces)
+  int64_t ncf = 0;
   WsHeader* hdr = nullptr;    // status bits and Picard counters of the level
   MeshParams mp{};            // the level's mesh (n, dx, ld = ncells)
 };
@@ -100,6 +102,10 @@ class AmrImplBase {
   virtual hipError_t update(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
                             const double* dt, int sub, const DevConsts& c, const AmrConsts& ac,
                             const AmrShape& sh, hipStream_t st) const = 0;
+  // the list of the level's coarse-fine faces into lv.cf; *count (device)
+  // must be zero on entry and holds the count on exit
+  virtual hipError_t cf_faces(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
+                              const AmrConsts& ac, int* count, hipStream_t st) const = 0;
   // the face-flux kernel alone (for tuning; its fluxes go to the scratch)
   virtual hipError_t flux_only(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
                                const double* dt, int sub, const DevConsts& c,
