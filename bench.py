@@ -211,7 +211,8 @@ def cpu_oracle_all_cores(U0, dt, rows_per_task=16):
 # the sources the uniform 2D cell and face kernels are compiled from (their
 # launcher, kernels, constants and the header they include)
 CELL_KERNEL_SOURCES = ("impl2d.hip", "impl.hpp", "plan.hpp", "fused2d.hpp", "level.hpp",
-                       "predict_mfma.hpp", "predict_wave.hpp", "kernels.hpp", "consts.hpp",
+                       "predict_mfma.hpp", "predict_wave.hpp", "weno3d.hpp", "kernels.hpp",
+                       "consts.hpp",
                        "consts.cpp",
                        "cell2d_launch.hpp", "cell2d_rows.hpp", "cell2d_rows2.hip",
                        "cell2d_rows4.hip", "cell2d_rows8.hip", "cell2d_rows16.hip")
