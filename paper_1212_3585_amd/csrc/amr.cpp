@@ -86,7 +86,7 @@ struct ader_amr_s {
   // per-level scratch of the active cells (wa, wh, qh, fbuf, coarse-fine
   // face list), grown on demand, and the level's dense pass buffers (3D;
   // sized by the index space)
-  std::vector<std::array<DevBuf, 6>> lvl_bufs;
+  std::vector<std::array<DevBuf, 7>> lvl_bufs;
   // per-level dense regrid arrays: flags, dilation scratch, previous status,
   // mother slots (list capacity = the level's cells)
   struct RegridLevel {
@@ -400,7 +400,7 @@ ader_status set_level_lists(ader_amr a, int l) {
   if (e == hipSuccess) e = select_count(a, ader::kSelVMother, v.st, nullptr, N, v.vm, &v.nvm);
   if (e == hipSuccess) e = ader::rg_positions(v.pos, N, v.act, v.nact, a->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
-  std::array<DevBuf, 6>& B = a->lvl_bufs[l];
+  std::array<DevBuf, 7>& B = a->lvl_bufs[l];
   const size_t na = (size_t)v.nact;
   const size_t dense = sizeof(double) * a->impl->dense_weno_per_cell() * (size_t)N;
   if (e == hipSuccess && dense > 0 && !v.dwx) {
@@ -418,6 +418,7 @@ ader_status set_level_lists(ader_amr a, int l) {
   if (e == hipSuccess)
     e = fill_buf(B[3], &v.fbuf, nullptr, sizeof(double) * a->impl->fbuf_per_cell() * na);
   if (e == hipSuccess) e = fill_buf(B[5], &v.cf, nullptr, sizeof(int32_t) * 2 * d * na);
+  if (e == hipSuccess) e = fill_buf(B[6], &v.fc, nullptr, sizeof(int32_t) * 2 * d * na);
   if (e != hipSuccess) return hip_status(e, "AMR level lists");
   v.wb = v.wa + (size_t)a->nv * (M + 1) * ipow(2 * M + 1, d - 1) * na;
   a->dtargs.nb[l] = v.nact == 0 ? 0

@@ -16,8 +16,8 @@
 //                   the mother's reconstruction w_h over the child's sub-cell
 //   k_fill_list     one value into listed cells of every variable (the
 //                   memory of the virtual children before a level's substeps)
-//   k_amr_cf_faces  the list of a level's coarse-fine faces (when the lists
-//                   change)
+//   k_amr_cf_faces  the list of a level's coarse-fine faces and the kind of
+//                   every face of its active cells (when the lists change)
 //   k_amr_flux_cf   fluxes of those faces, one group of lanes per face
 //   k_amr_flux      face fluxes of the active cells, one group of lanes per
 //                   (cell, axis), one lane per space-time point of the face;
@@ -355,7 +355,14 @@ struct AmrUpdArgs {
   const double* dt;
   int sub;
   int r;
+  // kind of each face of the active cells, fc[(2 k + side) nact + i]
+  // (k_amr_cf_faces): >= 0 the list position of the same-level active
+  // neighbour, kFaceOut a transmissive boundary, kFaceCoarseFine a face of
+  // k_amr_flux_cf, kFaceBad no flux (an index outside the lists)
+  const int32_t* fc;
 };
+
+constexpr int32_t kFaceOut = -1, kFaceCoarseFine = -2, kFaceBad = -3;
 
 // Shape of the face-flux kernel: a group of G lanes per (cell, axis k); lane
 // g < NPT of a group owns space-time point (s = g / NT, tb = g % NT) of the
@@ -535,19 +542,17 @@ k_amr_flux(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, double* __res
   const int64_t i = blk * Sh::CPB + cs;
   const bool valid = i < a.nact;
   unsigned int flags = 0;
-  int cc[3] = {0, 0, 0};
-  if (valid) dense_coords<DIM>(a.act[i], mp.n, cc);
+  const int cc[3] = {0, 0, 0};  // not read for same-level and boundary faces
+  const int off[3] = {0, 0, 0};
   for (int side = 1; side >= 0; --side) {
-    int64_t nb = 0;
-    int32_t pn = -1;
-    int off[3] = {0, 0, 0};
-    const int type = valid ? amr_face_kind<DIM>(a, mp, cc, k, side, &nb, &pn, off) : -2;
-    if (type == -1) flags |= kFlagBadIndex;
+    const int32_t code = valid ? a.fc[(2 * k + side) * a.nact + i] : kFaceCoarseFine;
+    if (code == kFaceBad) flags |= kFlagBadIndex;
     // uniform in the group: the low face of an active neighbour is its high
     // face; coarse-fine faces are the other kernel's
-    if (type < 0 || type >= 2 || (side == 0 && type == 0)) continue;
-    amr_face_flux<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, fbuf, i, cc, k, side, type, nb, pn,
-                                           off, g);
+    if (code == kFaceCoarseFine || code == kFaceBad || (side == 0 && code >= 0)) continue;
+    const int type = code >= 0 ? 0 : 1;
+    amr_face_flux<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, fbuf, i, cc, k, side, type, 0,
+                                           code >= 0 ? code : -1, off, g);
   }
   block_report(0u, flags, hdr);
 }
@@ -556,9 +561,13 @@ k_amr_flux(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, double* __res
 // amr_face_kind) as entries i * 2 DIM + 2 k + side; built when the level's
 // lists change.  The order of the entries does not matter: each face's flux
 // is computed on its own and written to its own slots.
+// The same pass also writes every face's kind for the per-step kernels
+// (AmrUpdArgs::fc), so that they read one code instead of gathering the
+// neighbour's status and list position.
 template <int DIM>
 __global__ void __launch_bounds__(kBlock)
-k_amr_cf_faces(AmrUpdArgs a, MeshParams mp, int32_t* __restrict__ list, int* __restrict__ count) {
+k_amr_cf_faces(AmrUpdArgs a, MeshParams mp, int32_t* __restrict__ list, int* __restrict__ count,
+               int32_t* __restrict__ fc) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= a.nact * 2 * DIM) return;
   const int64_t i = t / (2 * DIM);
@@ -570,6 +579,8 @@ k_amr_cf_faces(AmrUpdArgs a, MeshParams mp, int32_t* __restrict__ list, int* __r
   int off[3] = {0, 0, 0};
   const int type = amr_face_kind<DIM>(a, mp, cc, f >> 1, f & 1, &nb, &pn, off);
   if (type >= 2) list[atomicAdd(count, 1)] = (int32_t)t;
+  fc[f * a.nact + i] = type == 0 ? pn : (type == 1 ? kFaceOut : (type >= 2 ? kFaceCoarseFine
+                                                                           : kFaceBad));
 }
 
 // Fluxes of the listed coarse-fine faces: one group of lanes per entry.
@@ -608,25 +619,20 @@ k_amr_apply(AmrUpdArgs a, MeshParams mp, const double* __restrict__ fbuf, WsHead
   if (i < a.nact) {
     const int64_t ld = mp.ld;
     const int64_t cell = a.act[i];
-    int cc[3];
-    dense_coords<DIM>(cell, mp.n, cc);
     const double dt = *a.dt;
     double q[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) q[v] = a.u[v * ld + cell];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      int64_t nb = 0;
-      int32_t pn = -1;
-      int off[3];
-      const int type = amr_face_kind<DIM>(a, mp, cc, k, 0, &nb, &pn, off);
+      const int32_t code = a.fc[(2 * k) * a.nact + i];  // the low face
       const double* fhi = fbuf + (i * FS + 2 * k + 1) * NV;
-      const double* flo = type == 0 ? fbuf + ((int64_t)pn * FS + 2 * k + 1) * NV
+      const double* flo = code >= 0 ? fbuf + ((int64_t)code * FS + 2 * k + 1) * NV
                                     : fbuf + (i * FS + 2 * k) * NV;
-      if (type == -1) flags |= kFlagBadIndex;
+      if (code == kFaceBad) flags |= kFlagBadIndex;
 #pragma unroll
       for (int v = 0; v < NV; ++v)
-        q[v] -= (dt / mp.dx[k]) * (fhi[v] - (type == -1 ? 0.0 : flo[v]));
+        q[v] -= (dt / mp.dx[k]) * (fhi[v] - (code == kFaceBad ? 0.0 : flo[v]));
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {

@@ -211,6 +211,7 @@ class AmrImpl final : public AmrImplBase {
     a.act = lv.act;
     a.nact = lv.nact;
     a.qh = lv.qh;
+    a.fc = lv.fc;
     if (coarse) {
       a.pos_c = coarse->pos;
       a.qh_c = coarse->qh;
@@ -258,7 +259,7 @@ class AmrImpl final : public AmrImplBase {
     if (lv.nact == 0) return hipSuccess;
     const AmrUpdArgs a = upd_args(lv, coarse, fine, nullptr, 0, ac);
     hipLaunchKernelGGL((k_amr_cf_faces<DIM>), dim3(amr_blocks(lv.nact * 2 * DIM)), dim3(kBlock),
-                       0, st, a, lv.mp, lv.cf, count);
+                       0, st, a, lv.mp, lv.cf, count, lv.fc);
     return hipGetLastError();
   }
 

@@ -55,6 +55,7 @@ struct AmrLevel {
   void* qh = nullptr;         // predictor of the active cells (predictor precision)
   double* fbuf = nullptr;     // face fluxes of the active cells [cell][2 dim][nv]
   int32_t* cf = nullptr;      // coarse-fine faces of the active cells (k_amr_cf_faces)
+  int32_t* fc = nullptr;      // kind of every face of the active cells (k_amr_cf_faces)
   int64_t ncf = 0;
   WsHeader* hdr = nullptr;    // status bits and Picard counters of the level
   MeshParams mp{};            // the level's mesh (n, dx, ld = ncells)
