@@ -172,7 +172,8 @@ def _cell_kernel_traces(ader, M, n, bc, system, precision, U):
     (1, (13, 9), "periodic", "euler", 0), (0, (9, 7), "periodic", "euler", 0),
     (3, (19, 17), "periodic", "mhd", 0), (3, (24, 13), "transmissive", "linadv", 0),
     (3, (37, 29), "periodic", "euler", 1), (2, (21, 18), "transmissive", "euler", 1),
-    (1, (13, 9), "periodic", "euler", 1), (3, (19, 17), "periodic", "mhd", 1)])
+    (1, (13, 9), "periodic", "euler", 1), (3, (19, 17), "periodic", "mhd", 1),
+    (3, (24, 13), "transmissive", "linadv", 1)])
 def test_cell_kernel_traces_parity(ader, M, n, bc, system, precision):
     """The production 2D cell kernel (LDS WENO, matrix-core fp64 or DPP fp32
     predictor, trace contraction) against the oracle's predictor traces on
