@@ -114,6 +114,17 @@ __device__ __forceinline__ float ror_line_b1(float x, const float (&coef)[4]) {
   acc = fmac_row_ror12(acc, coef[3], x);
   return acc;
 }
+// xor_line_b0(fx, cx) + ror_line_b1(fy, cy) as one chain of fused
+// multiply-adds (the x terms, then the y terms)
+__device__ __forceinline__ float line_sum_xy(float fx, const float (&cx)[4], float fy,
+                                             const float (&cy)[4]) {
+  float acc = xor_line_b0(fx, cx);
+  acc = fmaf(cy[0], fy, acc);
+  acc = fmac_row_ror4(acc, cy[1], fy);
+  acc = fmac_row_ror8(acc, cy[2], fy);
+  acc = fmac_row_ror12(acc, cy[3], fy);
+  return acc;
+}
 // coef[m] = scale * D[p][(p - m) mod 4] (zero where that node is padding)
 template <int n>
 __device__ __forceinline__ void ror_row(const DevConsts& c, int p, double scale, float (&coef)[4]) {
@@ -276,7 +287,7 @@ __device__ __forceinline__ void cell2d_tile(int tile_x, int tile_y, const double
           const double gt = lane_transpose(F[1][v], taddr);
           Rs[v][s] = __builtin_amdgcn_mfma_f64_4x4x4f64(gt, my, rx, 0, 0, 0);
         } else {
-          Rs[v][s] = xor_line_b0(F[0][v], cxm) + ror_line_b1(F[1][v], cyr);
+          Rs[v][s] = line_sum_xy(F[0][v], cxm, F[1][v], cyr);
         }
       }
     }
@@ -316,7 +327,7 @@ __device__ __forceinline__ void cell2d_tile(int tile_x, int tile_y, const double
         const double gt = lane_transpose(F[1][v], taddr);
         r = __builtin_amdgcn_mfma_f64_4x4x4f64(gt, my, rx, 0, 0, 0);
       } else {
-        r = xor_line_b0(F[0][v], cxm) + ror_line_b1(F[1][v], cyr);
+        r = line_sum_xy(F[0][v], cxm, F[1][v], cyr);
       }
 #pragma unroll
       for (int s = 0; s < n; ++s) {
