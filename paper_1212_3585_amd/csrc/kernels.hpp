@@ -452,50 +452,53 @@ struct FuseWeno {
   const int32_t* act = nullptr;
 };
 
-// Both WENO passes of one 2D cell (cx, cy) and variable v from the dense grid
-// (boundary maps of mp): the 2M+1 x lines, then the n y lines, the same line
-// operations as the two-pass kernels.  out[px + n py].
-template <int M>
-__device__ __forceinline__ void weno2d_cell(const double* __restrict__ u, int64_t ld, int cx,
-                                            int cy, int v, const MeshParams& mp,
-                                            const DevConsts& c, double* out) {
-  constexpr int n = M + 1;
-  constexpr int S = 2 * M + 1;
-  double xo[S][n];
-#pragma unroll
-  for (int oy = 0; oy < S; ++oy) {
-    const int gy = bc_map(cy + oy - M, mp.n[1], mp.bc[1]);
-    const int64_t row = (int64_t)v * ld + (int64_t)mp.n[0] * gy;
-    double vals[S];
-#pragma unroll
-    for (int o = 0; o < S; ++o) vals[o] = u[row + bc_map(cx + o - M, mp.n[0], mp.bc[0])];
-    weno_line<M>(vals, c, xo[oy]);
-  }
-#pragma unroll
-  for (int px = 0; px < n; ++px) {
-    double vals[S], w[n];
-#pragma unroll
-    for (int o = 0; o < S; ++o) vals[o] = xo[o][px];
-    weno_line<M>(vals, c, w);
-#pragma unroll
-    for (int q = 0; q < n; ++q) out[px + n * q] = w[q];
-  }
-}
-
-// The prologue of a fused predictor block: cells first_cell + lc, lc < cpb,
-// reconstructed into sWh[(lc NV + v) n^2 + node] by the block's threads.
-template <int M, int NV>
-__device__ __forceinline__ void weno2d_block(const FuseWeno& fw, int64_t first_cell, int cpb,
+// The prologue of a fused predictor block: cells first_cell + lc, lc < CPB,
+// reconstructed into sWh[(lc NV + v) n^2 + px + n py] by all the block's
+// threads in two passes (the same line operations as the two-pass kernels):
+// the 2M+1 x lines of every (cell, variable) from the dense grid (boundary
+// maps of mp) into LDS, then the n y lines.
+template <int M, int NV, int CPB>
+__device__ __forceinline__ void weno2d_block(const FuseWeno& fw, int64_t first_cell,
                                              int64_t ncells, const MeshParams& mp,
                                              const DevConsts& c, double* sWh) {
-  constexpr int NS = (M + 1) * (M + 1);
-  for (int item = threadIdx.x; item < cpb * NV; item += blockDim.x) {
-    const int lc = item / NV, v = item % NV;
+  constexpr int n = M + 1;
+  constexpr int S = 2 * M + 1;
+  constexpr int NS = n * n;
+  __shared__ double sX[CPB * NV * S * n];  // x lines [(lc NV + v) S + row][px]
+  // x lines: item = lc + CPB (row + S v), neighbouring threads on
+  // neighbouring cells of the list
+  for (int item = threadIdx.x; item < CPB * NV * S; item += blockDim.x) {
+    const int lc = item % CPB;
+    const int oy = (item / CPB) % S;
+    const int v = item / (CPB * S);
     const int64_t cell = first_cell + lc;
     if (cell >= ncells) continue;
     const int32_t idx = fw.act[cell];
     const int cx = (int)(idx % mp.n[0]), cy = (int)(idx / mp.n[0]);
-    weno2d_cell<M>(fw.u, fw.ld, cx, cy, v, mp, c, sWh + (lc * NV + v) * NS);
+    const int gy = bc_map(cy + oy - M, mp.n[1], mp.bc[1]);
+    const int64_t row = (int64_t)v * fw.ld + (int64_t)mp.n[0] * gy;
+    double vals[S];
+#pragma unroll
+    for (int o = 0; o < S; ++o) vals[o] = fw.u[row + bc_map(cx + o - M, mp.n[0], mp.bc[0])];
+    double w[n];
+    weno_line<M>(vals, c, w);
+#pragma unroll
+    for (int px = 0; px < n; ++px) sX[((lc * NV + v) * S + oy) * n + px] = w[px];
+  }
+  __syncthreads();
+  // y lines: item = lc + CPB (px + n v)
+  for (int item = threadIdx.x; item < CPB * NV * n; item += blockDim.x) {
+    const int lc = item % CPB;
+    const int px = (item / CPB) % n;
+    const int v = item / (CPB * n);
+    if (first_cell + lc >= ncells) continue;
+    double vals[S];
+#pragma unroll
+    for (int o = 0; o < S; ++o) vals[o] = sX[((lc * NV + v) * S + o) * n + px];
+    double w[n];
+    weno_line<M>(vals, c, w);
+#pragma unroll
+    for (int q = 0; q < n; ++q) sWh[(lc * NV + v) * NS + px + n * q] = w[q];
   }
   __syncthreads();
 }
@@ -649,7 +652,7 @@ k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
   if constexpr (FUSE) {
     static_assert(DIM == 2, "fused reconstruction in 2D only");
     __shared__ double sWh[CPB * NV * NS];
-    weno2d_block<M, NV>(fw, (int64_t)blockIdx.x * CPB, CPB, ncells, mp, c, sWh);
+    weno2d_block<M, NV, CPB>(fw, (int64_t)blockIdx.x * CPB, ncells, mp, c, sWh);
     wsrc = sWh;
     wcell = lc;
   }

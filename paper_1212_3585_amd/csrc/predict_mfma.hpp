@@ -99,7 +99,7 @@ k_predict_mfma2d(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t nc
   if constexpr (FUSE) {
     constexpr int CPB = 4 * (kBlock / 64);
     __shared__ double sWh[CPB * NV * NS];
-    weno2d_block<M, NV>(fw, (int64_t)blockIdx.x * CPB, CPB, ncells, mp, c, sWh);
+    weno2d_block<M, NV, CPB>(fw, (int64_t)blockIdx.x * CPB, ncells, mp, c, sWh);
     wsrc = sWh;
     wcell = wave * 4 + b1;
   }
