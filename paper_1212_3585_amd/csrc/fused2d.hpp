@@ -53,7 +53,7 @@ template <int CTRL>
 __device__ __forceinline__ float dpp_f(float x) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
 }
-constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kQuadXor3 = 0x1B;  // [1032] [2301] [3210]
+constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E;  // quad_perm [1,0,3,2], [2,3,0,1]
 
 // Lane-local coefficients of the quad exchange (fp32 predictor): the node
 // p ^ m of the same line is fetched from lane ^ m (b0 axis);
@@ -104,7 +104,7 @@ template <int CTRL>
 __device__ __forceinline__ float ror_f(float x) {
   return dpp_f<CTRL>(x);
 }
-constexpr int kRowRor4 = 0x124, kRowRor8 = 0x128, kRowRor12 = 0x12C;
+constexpr int kRowRor4 = 0x124, kRowRor8 = 0x128;
 
 // sum_m coef[m] * x(b1 index (p - m) mod 4), m = 0..3 in order
 __device__ __forceinline__ float ror_line_b1(float x, const float (&coef)[4]) {
