@@ -417,7 +417,8 @@ ader_status set_level_lists(ader_amr a, int l) {
     e = fill_buf(B[2], &v.qh, nullptr, a->impl->qh_elem_size() * a->nv * ipow(M + 1, d + 1) * na);
   if (e == hipSuccess)
     e = fill_buf(B[3], &v.fbuf, nullptr, sizeof(double) * a->impl->fbuf_per_cell() * na);
-  if (e == hipSuccess) e = fill_buf(B[5], &v.cf, nullptr, sizeof(int32_t) * 2 * d * na);
+  if (e == hipSuccess)
+    e = fill_buf(B[5], &v.cf, nullptr, sizeof(int32_t) * ader::kAmrCfRecord * 2 * d * na);
   if (e == hipSuccess) e = fill_buf(B[6], &v.fc, nullptr, sizeof(int32_t) * 2 * d * na);
   if (e != hipSuccess) return hip_status(e, "AMR level lists");
   v.wb = v.wa + (size_t)a->nv * (M + 1) * ipow(2 * M + 1, d - 1) * na;

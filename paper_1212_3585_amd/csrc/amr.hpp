@@ -558,9 +558,12 @@ k_amr_flux(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, double* __res
 }
 
 // The coarse-fine faces of a level's active cells (kinds 2 and 3 of
-// amr_face_kind) as entries i * 2 DIM + 2 k + side; built when the level's
-// lists change.  The order of the entries does not matter: each face's flux
-// is computed on its own and written to its own slots.
+// amr_face_kind), built when the level's lists change, as records of four
+// int32 (kAmrCfRecord): the entry i * 2 DIM + 2 k + side, the kind with the
+// child's sub-cell offsets (kind | off_x << 8 | off_y << 16 | off_z << 24),
+// the neighbour's dense index and its list position.  The order of the
+// records does not matter: each face's flux is computed on its own and
+// written to its own slots.
 // The same pass also writes every face's kind for the per-step kernels
 // (AmrUpdArgs::fc), so that they read one code instead of gathering the
 // neighbour's status and list position.
@@ -578,7 +581,13 @@ k_amr_cf_faces(AmrUpdArgs a, MeshParams mp, int32_t* __restrict__ list, int* __r
   int32_t pn = -1;
   int off[3] = {0, 0, 0};
   const int type = amr_face_kind<DIM>(a, mp, cc, f >> 1, f & 1, &nb, &pn, off);
-  if (type >= 2) list[atomicAdd(count, 1)] = (int32_t)t;
+  if (type >= 2) {
+    int32_t* rec = list + (int64_t)atomicAdd(count, 1) * kAmrCfRecord;
+    rec[0] = (int32_t)t;
+    rec[1] = type | (off[0] << 8) | (off[1] << 16) | (off[2] << 24);
+    rec[2] = (int32_t)nb;
+    rec[3] = pn;
+  }
   fc[f * a.nact + i] = type == 0 ? pn : (type == 1 ? kFaceOut : (type >= 2 ? kFaceCoarseFine
                                                                            : kFaceBad));
 }
@@ -592,18 +601,16 @@ k_amr_flux_cf(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac,
   const int64_t e = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G;
   if (e >= nlist) return;  // uniform in the group
   const int g = threadIdx.x % G;
-  const int32_t t = list[e];
+  const int4 rec = reinterpret_cast<const int4*>(list)[e];
+  const int32_t t = rec.x;
   const int64_t i = t / (2 * DIM);
   const int k = (t % (2 * DIM)) >> 1, side = t & 1;
+  const int type = rec.y & 0xFF;
+  const int off[3] = {(rec.y >> 8) & 0xFF, (rec.y >> 16) & 0xFF, (rec.y >> 24) & 0xFF};
   int cc[3] = {0, 0, 0};
-  dense_coords<DIM>(a.act[i], mp.n, cc);
-  int64_t nb = 0;
-  int32_t pn = -1;
-  int off[3] = {0, 0, 0};
-  const int type = amr_face_kind<DIM>(a, mp, cc, k, side, &nb, &pn, off);
-  if (type < 2) return;
-  amr_face_flux<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, fbuf, i, cc, k, side, type, nb, pn, off,
-                                         g);
+  if (type == 3) dense_coords<DIM>(a.act[i], mp.n, cc);  // the face's fine children
+  amr_face_flux<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, fbuf, i, cc, k, side, type, rec.z, rec.w,
+                                         off, g);
 }
 
 // Conservative update of the active cells (eq. finite_vol) from the face

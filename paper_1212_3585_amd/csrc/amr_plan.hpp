@@ -33,6 +33,9 @@ struct AmrClock {
   unsigned long long steps;
 };
 
+// int32 per coarse-fine face record (k_amr_cf_faces)
+constexpr int kAmrCfRecord = 4;
+
 // One level of the dense per-level representation.
 struct AmrLevel {
   int n[3] = {1, 1, 1};  // cells per axis of the level's index space
@@ -54,7 +57,7 @@ struct AmrLevel {
   double* dwx = nullptr;      // 3D: dense x- and y-pass lines [nv][n + n^2][ncells]
   void* qh = nullptr;         // predictor of the active cells (predictor precision)
   double* fbuf = nullptr;     // face fluxes of the active cells [cell][2 dim][nv]
-  int32_t* cf = nullptr;      // coarse-fine faces of the active cells (k_amr_cf_faces)
+  int32_t* cf = nullptr;      // coarse-fine face records of the active cells (k_amr_cf_faces)
   int32_t* fc = nullptr;      // kind of every face of the active cells (k_amr_cf_faces)
   int64_t ncf = 0;
   WsHeader* hdr = nullptr;    // status bits and Picard counters of the level
