@@ -787,7 +787,13 @@ k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
 // ------------------------------------------------------------- face fluxes
 // Faces along axis K are indexed on the mesh extended by one along K:
 // f = i + Ex * (j + Ey * k) with E = n except E_K = n_K + 1.  Face index i_K
-// separates cells i_K - 1 and i_K.  F[v * nf + f].
+// separates cells i_K - 1 and i_K.  F[v * nf + f].  The blocks walk the
+// faces of fp64 predictors with i_K fastest, so that the faces of a block
+// are consecutive along K and read each cell's q_h about once (in the
+// natural order a cell's two z faces are a plane of faces apart): 3D
+// face fluxes at 192^3 18.4 -> 16.6 ms per step.  With fp32 q_h (half the
+// bytes) the natural order, whose blocks read contiguous runs of cells,
+// measured faster (11.7 against 12.0-12.3 ms).
 template <int DIM, int M, int SYS, typename R, int K>
 __global__ void __launch_bounds__(kBlock)
 k_face_flux(const R* __restrict__ qh, double* __restrict__ F, int64_t nfaces, MeshParams mp,
@@ -804,17 +810,27 @@ k_face_flux(const R* __restrict__ qh, double* __restrict__ F, int64_t nfaces, Me
   const int tid = threadIdx.x;
   const int lf = tid / G;
   const int l = tid - lf * G;
-  const int64_t f = (int64_t)blockIdx.x * FPB + lf;
-  const bool active = lf < FPB && f < nfaces;
+  const int64_t fw = (int64_t)blockIdx.x * FPB + lf;  // position in the walk order
+  constexpr bool kWalk = std::is_same<R, double>::value;
+  const bool active = lf < FPB && fw < nfaces;
+  int e[3] = {mp.n[0], mp.n[1], DIM == 3 ? mp.n[2] : 1};
+  e[K] += 1;
+  // the other two axes, in increasing order
+  constexpr int A1 = K == 0 ? 1 : 0, A2 = K == 2 ? 1 : 2;
+  int fi[3];
+  if constexpr (kWalk) {
+    fi[K] = (int)(fw % e[K]);
+    fi[A1] = (int)((fw / e[K]) % e[A1]);
+    fi[A2] = (int)(fw / ((int64_t)e[K] * e[A1]));
+  } else {
+    fi[0] = (int)(fw % e[0]);
+    fi[1] = (int)((fw / e[0]) % e[1]);
+    fi[2] = (int)(fw / ((int64_t)e[0] * e[1]));
+  }
+  const int64_t f = fi[0] + (int64_t)e[0] * (fi[1] + (int64_t)e[1] * fi[2]);
 
   double wpt = 0.0;
   if (active) {
-    int e[3] = {mp.n[0], mp.n[1], DIM == 3 ? mp.n[2] : 1};
-    e[K] += 1;
-    int fi[3];
-    fi[0] = (int)(f % e[0]);
-    fi[1] = (int)((f / e[0]) % e[1]);
-    fi[2] = (int)(f / ((int64_t)e[0] * e[1]));
     // neighbouring cells along K
     const int iL = fi[K] - 1, iR = fi[K];
     const bool outL = iL < 0, outR = iR >= mp.n[K];
