@@ -605,12 +605,26 @@ k_amr_flux_cf(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac,
   const int32_t t = rec.x;
   const int64_t i = t / (2 * DIM);
   const int k = (t % (2 * DIM)) >> 1, side = t & 1;
-  const int type = rec.y & 0xFF;
-  const int off[3] = {(rec.y >> 8) & 0xFF, (rec.y >> 16) & 0xFF, (rec.y >> 24) & 0xFF};
   int cc[3] = {0, 0, 0};
-  if (type == 3) dense_coords<DIM>(a.act[i], mp.n, cc);  // the face's fine children
-  amr_face_flux<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, fbuf, i, cc, k, side, type, rec.z, rec.w,
-                                         off, g);
+  if constexpr (DIM == 2) {
+    const int type = rec.y & 0xFF;
+    const int off[3] = {(rec.y >> 8) & 0xFF, (rec.y >> 16) & 0xFF, (rec.y >> 24) & 0xFF};
+    if (type == 3) dense_coords<DIM>(a.act[i], mp.n, cc);  // the face's fine children
+    amr_face_flux<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, fbuf, i, cc, k, side, type, rec.z,
+                                           rec.w, off, g);
+  } else {
+    // 3D: deriving the kind again from the lists measured faster with the
+    // fp64 predictor (93.5 against 118.5 us per launch on the 3D blast;
+    // 65 against 60 us with the fp32 one)
+    dense_coords<DIM>(a.act[i], mp.n, cc);
+    int64_t nb = 0;
+    int32_t pn = -1;
+    int off[3] = {0, 0, 0};
+    const int type = amr_face_kind<DIM>(a, mp, cc, k, side, &nb, &pn, off);
+    if (type < 2) return;
+    amr_face_flux<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, fbuf, i, cc, k, side, type, nb, pn,
+                                           off, g);
+  }
 }
 
 // Conservative update of the active cells (eq. finite_vol) from the face
