@@ -5,9 +5,20 @@
 // per time node; in 3D that moves more LDS bytes per cell and sweep than the
 // arithmetic needs cycles.  Here a cell owns a power-of-two group of G >= n^d
 // lanes inside one wavefront (G = 8, 32, 64 for n^3 = 8, 27, 64), so the
-// derivative along axis k fetches the n - 1 other nodes of the lane's line
-// with ds_bpermute: no LDS memory, no barriers, and the stopping test is a
-// ballot over the cell's lanes.
+// derivative along axis k takes the n - 1 other nodes of the lane's line
+// from lanes of the same wavefront: no block barriers, and the stopping test
+// is a ballot over the cell's lanes.
+//
+// fp64: each lane publishes its nodal fluxes of one time node as one record
+// per axis in wavefront-private LDS (NV values padded to whole 16-byte
+// vectors) and reads its line partners' records with 16-byte loads.  A
+// lane-to-lane fetch (ds_bpermute) moves 4 bytes per instruction, and with at
+// most 15 LDS operations in flight per wavefront the sweep waited on its
+// exchanges (86 waits per sweep against 33 with the records).  The LDS of one
+// wavefront is read and written in issue order, so a compiler-only fence (no
+// wait, no barrier) orders the records between its lanes.
+// fp32: ds_bpermute.  The records raised its registers from 66 to 95 per lane
+// (seven to five wavefronts per SIMD) and made it slower.
 //
 // One Picard sweep of eq. stdg.final per loop trip, dimension by dimension:
 //   * nodal fluxes f_k at the lane's node and time node sp;
@@ -34,14 +45,22 @@ template <int NS> struct WaveGroup {
   static_assert(NS <= 64, "a cell must fit one wavefront");
 };
 
-template <typename R> __device__ __forceinline__ R lane_fetch(R x, int addr);
-template <> __device__ __forceinline__ double lane_fetch<double>(double x, int addr) {
-  const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(x));
-  const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(x));
-  return __hiloint2double(hi, lo);
+template <typename R> __device__ __forceinline__ R lane_fetch(R x, int lane);
+template <> __device__ __forceinline__ float lane_fetch<float>(float x, int lane) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(lane << 2, __float_as_int(x)));
 }
-template <> __device__ __forceinline__ float lane_fetch<float>(float x, int addr) {
-  return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x)));
+
+// 16-byte vector of R (two doubles or four floats)
+template <typename R> struct Vec16;
+template <> struct Vec16<double> { typedef double __attribute__((ext_vector_type(2))) T; };
+template <> struct Vec16<float> { typedef float __attribute__((ext_vector_type(4))) T; };
+
+// orders this wavefront's LDS accesses in the compiler only: the hardware
+// already performs one wavefront's LDS operations in issue order
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // maximum over the G lanes of this lane's group (G a power of two <= 64)
@@ -79,10 +98,10 @@ k_predict_wave(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncel
 
   int ak[3] = {a % n, (a / n) % n, a / (n * n)};
   const double dt = *dt_dev;
-  // coef[k][m]: (dt/dx_k) D[p_k][(p_k + m) mod n]; addr[k][m]: byte address
-  // of the lane holding that node of this lane's line (m = 0 is the lane)
+  // coef[k][m]: (dt/dx_k) D[p_k][(p_k + m) mod n]; pl[k][m]: the lane holding
+  // that node of this lane's line (m = 0 is the lane)
   R coef[DIM][n];
-  int addr[DIM][n];
+  int pl[DIM][n];
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     const int stride = k == 0 ? 1 : (k == 1 ? n : n * n);
@@ -91,7 +110,7 @@ k_predict_wave(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncel
     for (int m = 0; m < n; ++m) {
       const int b = (ak[k] + m) % n;
       coef[k][m] = (R)((dt / mp.dx[k]) * pick_entry<n>(c.dmat, ak[k], b));
-      addr[k][m] = (base + b * stride) << 2;
+      pl[k][m] = base + b * stride;
     }
   }
   const R gamma = (R)mp.gamma;
@@ -109,18 +128,68 @@ k_predict_wave(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncel
   for (int v = 0; v < NV; ++v) wmax = fmax(wmax, fabs(w[v]));
   const R thr = (R)mp.tol * fmax(R(1), group_max<G>(node_ok ? wmax : R(0)));
 
+  // fp64 exchange: wavefront-private flux records [axis][lane][NV values,
+  // padded to whole 16-byte vectors]; the full vectors move as 16-byte
+  // accesses, the NV mod VPV values after them one by one
+  constexpr bool kRec = sizeof(R) == 8;
+  typedef typename Vec16<R>::T V;
+  constexpr int VPV = 16 / (int)sizeof(R);       // values per 16-byte vector
+  constexpr int NFULL = NV / VPV;                 // full vectors per record
+  constexpr int RV = (NV + VPV - 1) / VPV * VPV;  // record length
+  __shared__ __attribute__((aligned(16))) R xrec[kRec ? BLK / 64 : 1][DIM][kRec ? 64 : 1][RV];
+
   // sum_k (dt/dx_k) D^(k) f_k at this lane's node
   auto derivative = [&](const R (&F)[DIM][NV], R (&out)[NV]) {
+    if constexpr (kRec) {
+      // the lane's own terms first, so that its fluxes are dead once published
+      R (&rec)[DIM][64][RV] = xrec[wave];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      R acc = R(0);
+      for (int v = 0; v < NV; ++v) {
+        R acc = R(0);
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) acc += coef[k][0] * F[k][v];
+        out[v] = acc;
+      }
+      wave_lds_order();  // the partners' reads of the previous records are issued
 #pragma unroll
       for (int k = 0; k < DIM; ++k) {
-        acc += coef[k][0] * F[k][v];
 #pragma unroll
-        for (int m = 1; m < n; ++m) acc += coef[k][m] * lane_fetch<R>(F[k][v], addr[k][m]);
+        for (int j = 0; j < NFULL; ++j) {
+          V x;
+#pragma unroll
+          for (int e = 0; e < VPV; ++e) x[e] = F[k][VPV * j + e];
+          reinterpret_cast<V*>(rec[k][lane])[j] = x;
+        }
+#pragma unroll
+        for (int v = VPV * NFULL; v < NV; ++v) rec[k][lane][v] = F[k][v];
       }
-      out[v] = acc;
+      wave_lds_order();
+#pragma unroll
+      for (int k = 0; k < DIM; ++k)
+#pragma unroll
+        for (int m = 1; m < n; ++m) {
+          const R* pr = rec[k][pl[k][m]];
+#pragma unroll
+          for (int j = 0; j < NFULL; ++j) {
+            const V x = reinterpret_cast<const V*>(pr)[j];
+#pragma unroll
+            for (int e = 0; e < VPV; ++e) out[VPV * j + e] += coef[k][m] * x[e];
+          }
+#pragma unroll
+          for (int v = VPV * NFULL; v < NV; ++v) out[v] += coef[k][m] * pr[v];
+        }
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        R acc = R(0);
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          acc += coef[k][0] * F[k][v];
+#pragma unroll
+          for (int m = 1; m < n; ++m) acc += coef[k][m] * lane_fetch<R>(F[k][v], pl[k][m]);
+        }
+        out[v] = acc;
+      }
     }
   };
   bool done = !cell_ok;
