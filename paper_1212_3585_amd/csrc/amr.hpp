@@ -34,6 +34,7 @@
 
 #include "amr_plan.hpp"
 #include "level.hpp"
+#include "predict_wave.hpp"
 
 namespace ader {
 
@@ -415,16 +416,19 @@ __device__ __forceinline__ int amr_face_kind(const AmrUpdArgs& a, const MeshPara
 // (s = g / NT, tb = g % NT); the face average goes to
 // fbuf[(i * 2 DIM + 2 k + side) * NV + v].  A face to a virtual child also
 // adds its flux to the child's memory.  The group takes one path.
+// trc: the group's NV n NT doubles of LDS for a face to a virtual child
+// (unused by the other kinds).
 template <int DIM, int M, int SYS, typename R, int G, int FLUX>
 __device__ __forceinline__ void amr_face_flux(const AmrUpdArgs& a, const MeshParams& mp,
                                               const DevConsts& c, const AmrConsts& ac,
                                               double* __restrict__ fbuf, int64_t i,
                                               const int (&cc)[3], int k, int side, int type,
                                               int64_t nb, int32_t pn, const int (&off)[3],
-                                              int g) {
+                                              int g, double* __restrict__ trc) {
   constexpr int n = M + 1;
   constexpr int NV = NVars<SYS, DIM>::v;
-  constexpr int NST = Pow<n, DIM + 1>::v;
+  constexpr int NS = Pow<n, DIM>::v;
+  constexpr int NST = NS * n;
   constexpr int NT = Pow<n, DIM - 1>::v;
   constexpr int NPT = n * NT;
   constexpr int FS = 2 * DIM;
@@ -451,48 +455,82 @@ __device__ __forceinline__ void amr_face_flux(const AmrUpdArgs& a, const MeshPar
       for (int v = 0; v < NV; ++v)
         F[v] += a.mem_f[((int64_t)(k * 2 + side) * NV + v) * a.ldf + chd];
     }
-  } else if (g < NPT) {
-    const int s = g / NT, tb = g % NT;
-    double qm[NV], qp[NV];
-    cell_trace<DIM, M, NV, R>(static_cast<const R*>(a.qh) + i * NV * NST, k, side, tb, s, c,
-                              qm);
-    if (type == 0) {
-      cell_trace<DIM, M, NV, R>(static_cast<const R*>(a.qh) + (int64_t)pn * NV * NST, k,
-                                1 - side, tb, s, c, qp);
-    } else if (type == 1) {
+  } else {
+    // tangential axes of the face, in increasing order
+    const int ta0 = k == 0 ? 1 : 0, ta1 = k == 2 ? 1 : 2;
+    if (type == 2) {
+      // The coarse predictor on the face: contracted along the normal (coarse
+      // basis at the virtual child's face) and in time (coarse basis at this
+      // substep's time nodes) once per face, the group's lanes sharing the
+      // NV n NT values [v][s][tangential nodes] through LDS; each lane then
+      // contracts the tangential axes at its own Gauss point.
+      const R* qc = static_cast<const R*>(a.qh_c) + (int64_t)pn * NV * NST;
+      const int sk = k == 0 ? 1 : (k == 1 ? n : n * n);
+      const int s0 = ta0 == 0 ? 1 : (ta0 == 1 ? n : n * n);
+      const int s1 = ta1 == 1 ? n : n * n;
+      for (int idx = g; idx < NV * NPT; idx += G) {
+        const int v = idx / NPT, s = (idx / NT) % n, tb = idx % NT;
+        const int base = (tb % n) * s0 + (DIM == 3 ? (tb / n) * s1 : 0);
+        double acc = 0.0;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) qp[v] = qm[v];
-    } else {
-      // coarse predictor at this face point and time node
-      const int tt[2] = {tb % n, tb / n};
-      double wt[4], wax[3][4];
-      int ti = 0;
+        for (int pt = 0; pt < n; ++pt) {
+          double sp = 0.0;
 #pragma unroll
-      for (int p = 0; p < 4; ++p) wt[p] = p < n ? ac.at_nodes[a.sub][s][p] : 0.0;
-      for (int ax = 0; ax < 3; ++ax) {
-        for (int p = 0; p < 4; ++p) {
-          double w = 0.0;
-          if (p < n && ax < DIM)
-            w = ax == k ? ac.at_face[off[ax]][1 - side][p] : ac.at_nodes[off[ax]][tt[ti]][p];
-          wax[ax][p] = w;
+          for (int pn = 0; pn < n; ++pn)
+            sp += ac.at_face[off[k]][1 - side][pn] *
+                  (double)qc[v * NST + NS * pt + base + pn * sk];
+          acc += ac.at_nodes[a.sub][s][pt] * sp;
         }
-        if (ax < DIM && ax != k) ++ti;
+        trc[idx] = acc;
       }
-      eval_predictor<DIM, M, NV, R>(static_cast<const R*>(a.qh_c) + (int64_t)pn * NV * NST, wt,
-                                    wax, qp);
+      wave_lds_order();
     }
-    double Fpt[NV];
-    if (side)
-      numerical_flux<SYS, DIM, FLUX>(qm, qp, k, mp, c, Fpt);
-    else
-      numerical_flux<SYS, DIM, FLUX>(qp, qm, k, mp, c, Fpt);
-    double wtp = c.w[s];
-    {
-      const int tt[2] = {tb % n, tb / n};
-      for (int dd = 0; dd < DIM - 1; ++dd) wtp *= c.w[tt[dd]];
-    }
+    if (g < NPT) {
+      const int s = g / NT, tb = g % NT;
+      double qm[NV], qp[NV];
+      cell_trace<DIM, M, NV, R>(static_cast<const R*>(a.qh) + i * NV * NST, k, side, tb, s, c,
+                                qm);
+      if (type == 0) {
+        cell_trace<DIM, M, NV, R>(static_cast<const R*>(a.qh) + (int64_t)pn * NV * NST, k,
+                                  1 - side, tb, s, c, qp);
+      } else if (type == 1) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) F[v] = wtp * Fpt[v];
+        for (int v = 0; v < NV; ++v) qp[v] = qm[v];
+      } else {
+        // coarse predictor at this face point and time node
+        double w0[4], w1[4];
+#pragma unroll
+        for (int p = 0; p < n; ++p) {
+          w0[p] = ac.at_nodes[off[ta0]][tb % n][p];
+          w1[p] = DIM == 3 ? ac.at_nodes[off[ta1]][tb / n][p] : 1.0;
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const double* tv = trc + v * NPT + s * NT;
+          double acc = 0.0;
+#pragma unroll
+          for (int p1 = 0; p1 < (DIM == 3 ? n : 1); ++p1) {
+            double sp = 0.0;
+#pragma unroll
+            for (int p0 = 0; p0 < n; ++p0) sp += w0[p0] * tv[p0 + n * p1];
+            acc += w1[p1] * sp;
+          }
+          qp[v] = acc;
+        }
+      }
+      double Fpt[NV];
+      if (side)
+        numerical_flux<SYS, DIM, FLUX>(qm, qp, k, mp, c, Fpt);
+      else
+        numerical_flux<SYS, DIM, FLUX>(qp, qm, k, mp, c, Fpt);
+      double wtp = c.w[s];
+      {
+        const int tt[2] = {tb % n, tb / n};
+        for (int dd = 0; dd < DIM - 1; ++dd) wtp *= c.w[tt[dd]];
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) F[v] = wtp * Fpt[v];
+    }
   }
   // group sum by a fixed butterfly
 #pragma unroll
@@ -552,7 +590,7 @@ k_amr_flux(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, double* __res
     if (code == kFaceCoarseFine || code == kFaceBad || (side == 0 && code >= 0)) continue;
     const int type = code >= 0 ? 0 : 1;
     amr_face_flux<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, fbuf, i, cc, k, side, type, 0,
-                                           code >= 0 ? code : -1, off, g);
+                                           code >= 0 ? code : -1, off, g, nullptr);
   }
   block_report(0u, flags, hdr);
 }
@@ -598,6 +636,10 @@ __global__ void __launch_bounds__(kBlock)
 k_amr_flux_cf(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac,
               const int32_t* __restrict__ list, int64_t nlist, double* __restrict__ fbuf) {
   constexpr int G = AmrFluxShape<DIM, M>::G;
+  constexpr int NV = NVars<SYS, DIM>::v;
+  constexpr int NPT = Pow<M + 1, DIM>::v;  // space-time points of a face
+  __shared__ double s_trc[kBlock / G][NV * NPT];
+  double* trc = s_trc[threadIdx.x / G];
   const int64_t e = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G;
   if (e >= nlist) return;  // uniform in the group
   const int g = threadIdx.x % G;
@@ -611,7 +653,7 @@ k_amr_flux_cf(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac,
     const int off[3] = {(rec.y >> 8) & 0xFF, (rec.y >> 16) & 0xFF, (rec.y >> 24) & 0xFF};
     if (type == 3) dense_coords<DIM>(a.act[i], mp.n, cc);  // the face's fine children
     amr_face_flux<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, fbuf, i, cc, k, side, type, rec.z,
-                                           rec.w, off, g);
+                                           rec.w, off, g, trc);
   } else {
     // 3D: deriving the kind again from the lists measured faster with the
     // fp64 predictor (93.5 against 118.5 us per launch on the 3D blast;
@@ -623,7 +665,7 @@ k_amr_flux_cf(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac,
     const int type = amr_face_kind<DIM>(a, mp, cc, k, side, &nb, &pn, off);
     if (type < 2) return;
     amr_face_flux<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, fbuf, i, cc, k, side, type, nb, pn,
-                                           off, g);
+                                           off, g, trc);
   }
 }
 
