@@ -18,12 +18,12 @@
 //                   memory of the virtual children before a level's substeps)
 //   k_amr_cf_faces  the list of a level's coarse-fine faces and the kind of
 //                   every face of its active cells (when the lists change)
-//   k_amr_flux_cf   fluxes of those faces, one group of lanes per face
 //   k_amr_flux      face fluxes of the active cells, one group of lanes per
 //                   (cell, axis), one lane per space-time point of the face;
 //                   each face once (a cell's high faces, and its low faces
 //                   not shared with an active cell of the level): same-level
-//                   faces as on a uniform mesh; a face to a virtual child
+//                   faces as on a uniform mesh; its first blocks take the
+//                   listed coarse-fine faces, a group per face: a face to a virtual child
 //                   (coarser neighbour) takes the coarse predictor at this
 //                   face's Gauss points and this substep's time nodes and
 //                   stores the flux in the virtual child's memory; a face to
@@ -358,8 +358,9 @@ struct AmrUpdArgs {
   int r;
   // kind of each face of the active cells, fc[(2 k + side) nact + i]
   // (k_amr_cf_faces): >= 0 the list position of the same-level active
-  // neighbour, kFaceOut a transmissive boundary, kFaceCoarseFine a face of
-  // k_amr_flux_cf, kFaceBad no flux (an index outside the lists)
+  // neighbour, kFaceOut a transmissive boundary, kFaceCoarseFine a listed
+  // coarse-fine face (the first blocks of k_amr_flux), kFaceBad no flux (an
+  // index outside the lists)
   const int32_t* fc;
 };
 
@@ -554,29 +555,75 @@ __device__ __forceinline__ void amr_face_flux(const AmrUpdArgs& a, const MeshPar
   }
 }
 
+// Flux of listed coarse-fine face e (a record of k_amr_cf_faces) by a group
+// of G lanes; trc is the group's LDS (see amr_face_flux).
+template <int DIM, int M, int SYS, typename R, int G, int FLUX>
+__device__ __forceinline__ void amr_cf_entry(const AmrUpdArgs& a, const MeshParams& mp,
+                                             const DevConsts& c, const AmrConsts& ac,
+                                             const int32_t* __restrict__ list, int64_t e,
+                                             double* __restrict__ fbuf, int g,
+                                             double* __restrict__ trc) {
+  const int4 rec = reinterpret_cast<const int4*>(list)[e];
+  const int32_t t = rec.x;
+  const int64_t i = t / (2 * DIM);
+  const int k = (t % (2 * DIM)) >> 1, side = t & 1;
+  int cc[3] = {0, 0, 0};
+  if constexpr (DIM == 2) {
+    const int type = rec.y & 0xFF;
+    const int off[3] = {(rec.y >> 8) & 0xFF, (rec.y >> 16) & 0xFF, (rec.y >> 24) & 0xFF};
+    if (type == 3) dense_coords<DIM>(a.act[i], mp.n, cc);  // the face's fine children
+    amr_face_flux<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, fbuf, i, cc, k, side, type, rec.z,
+                                           rec.w, off, g, trc);
+  } else {
+    // 3D: deriving the kind again from the lists measured faster with the
+    // fp64 predictor (93.5 against 118.5 us per launch on the 3D blast;
+    // 65 against 60 us with the fp32 one)
+    dense_coords<DIM>(a.act[i], mp.n, cc);
+    int64_t nb = 0;
+    int32_t pn = -1;
+    int off[3] = {0, 0, 0};
+    const int type = amr_face_kind<DIM>(a, mp, cc, k, side, &nb, &pn, off);
+    if (type < 2) return;
+    amr_face_flux<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, fbuf, i, cc, k, side, type, nb, pn,
+                                           off, g, trc);
+  }
+}
+
 // Face fluxes of the active cells: each cell computes its high face on every
 // axis, and its low face where the low neighbour is not an active cell of
 // the same level (that face is the neighbour's high face), so every face is
 // evaluated once.  This kernel takes the faces to active cells of the level
 // and through the boundary, a group of lanes per (cell, axis); the
 // coarse-fine faces (virtual children and virtual mothers) are listed once
-// per mesh (k_amr_cf_faces) and done by k_amr_flux_cf.  Keeping their paths
-// out of this kernel keeps its registers low (78 instead of 167 VGPRs at 3D
-// M = 2 fp64), so more wavefronts hide the latency of its gathers.
+// per mesh (k_amr_cf_faces) and done by the first ncb blocks of the same
+// launch, a group of G lanes per listed face (amr_cf_entry), so that their
+// gathers overlap the bulk of the same-level faces and the level substep
+// needs no launch of its own for them.  Deriving their kinds in the
+// same-level path instead took 167 instead of 78 VGPRs at 3D M = 2 fp64.
 template <int DIM, int M, int SYS, typename R, int TB = kBlock, int FLUX = -1>
 __global__ void __launch_bounds__((AmrFluxShape<DIM, M, TB>::BLOCK))
 k_amr_flux(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, double* __restrict__ fbuf,
-           WsHeader* hdr) {
+           WsHeader* hdr, const int32_t* __restrict__ cfl, int64_t ncf, unsigned ncb) {
   using Sh = AmrFluxShape<DIM, M, TB>;
   constexpr int G = Sh::G;
+  constexpr int NV = NVars<SYS, DIM>::v;
   const int tid = threadIdx.x;
+  if (blockIdx.x < ncb) {  // coarse-fine faces (uniform in the block)
+    __shared__ double s_trc[Sh::BLOCK / G][NV * Sh::NPT];
+    const int64_t e = (int64_t)blockIdx.x * (Sh::BLOCK / G) + tid / G;
+    if (e < ncf)  // uniform in the group
+      amr_cf_entry<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, cfl, e, fbuf, tid % G,
+                                            s_trc[tid / G]);
+    return;
+  }
   const int cs = tid / Sh::LPC;
   const int k = (tid % Sh::LPC) / G;
   const int g = tid % G;
   // groups in the reverse of the predictor's order (2D: predictor forward;
   // 3D: predictor reversed): the q_h written last are read first, while
   // still cached
-  const int64_t blk = DIM == 2 ? (int64_t)(gridDim.x - 1 - blockIdx.x) : (int64_t)blockIdx.x;
+  const int64_t bm = (int64_t)blockIdx.x - ncb, nbm = (int64_t)gridDim.x - ncb;
+  const int64_t blk = DIM == 2 ? nbm - 1 - bm : bm;
   const int64_t i = blk * Sh::CPB + cs;
   const bool valid = i < a.nact;
   unsigned int flags = 0;
@@ -586,7 +633,7 @@ k_amr_flux(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, double* __res
     const int32_t code = valid ? a.fc[(2 * k + side) * a.nact + i] : kFaceCoarseFine;
     if (code == kFaceBad) flags |= kFlagBadIndex;
     // uniform in the group: the low face of an active neighbour is its high
-    // face; coarse-fine faces are the other kernel's
+    // face; coarse-fine faces are the listed ones of the first blocks
     if (code == kFaceCoarseFine || code == kFaceBad || (side == 0 && code >= 0)) continue;
     const int type = code >= 0 ? 0 : 1;
     amr_face_flux<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, fbuf, i, cc, k, side, type, 0,
@@ -628,45 +675,6 @@ k_amr_cf_faces(AmrUpdArgs a, MeshParams mp, int32_t* __restrict__ list, int* __r
   }
   fc[f * a.nact + i] = type == 0 ? pn : (type == 1 ? kFaceOut : (type >= 2 ? kFaceCoarseFine
                                                                            : kFaceBad));
-}
-
-// Fluxes of the listed coarse-fine faces: one group of lanes per entry.
-template <int DIM, int M, int SYS, typename R, int FLUX = -1>
-__global__ void __launch_bounds__(kBlock)
-k_amr_flux_cf(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac,
-              const int32_t* __restrict__ list, int64_t nlist, double* __restrict__ fbuf) {
-  constexpr int G = AmrFluxShape<DIM, M>::G;
-  constexpr int NV = NVars<SYS, DIM>::v;
-  constexpr int NPT = Pow<M + 1, DIM>::v;  // space-time points of a face
-  __shared__ double s_trc[kBlock / G][NV * NPT];
-  double* trc = s_trc[threadIdx.x / G];
-  const int64_t e = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G;
-  if (e >= nlist) return;  // uniform in the group
-  const int g = threadIdx.x % G;
-  const int4 rec = reinterpret_cast<const int4*>(list)[e];
-  const int32_t t = rec.x;
-  const int64_t i = t / (2 * DIM);
-  const int k = (t % (2 * DIM)) >> 1, side = t & 1;
-  int cc[3] = {0, 0, 0};
-  if constexpr (DIM == 2) {
-    const int type = rec.y & 0xFF;
-    const int off[3] = {(rec.y >> 8) & 0xFF, (rec.y >> 16) & 0xFF, (rec.y >> 24) & 0xFF};
-    if (type == 3) dense_coords<DIM>(a.act[i], mp.n, cc);  // the face's fine children
-    amr_face_flux<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, fbuf, i, cc, k, side, type, rec.z,
-                                           rec.w, off, g, trc);
-  } else {
-    // 3D: deriving the kind again from the lists measured faster with the
-    // fp64 predictor (93.5 against 118.5 us per launch on the 3D blast;
-    // 65 against 60 us with the fp32 one)
-    dense_coords<DIM>(a.act[i], mp.n, cc);
-    int64_t nb = 0;
-    int32_t pn = -1;
-    int off[3] = {0, 0, 0};
-    const int type = amr_face_kind<DIM>(a, mp, cc, k, side, &nb, &pn, off);
-    if (type < 2) return;
-    amr_face_flux<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, fbuf, i, cc, k, side, type, nb, pn,
-                                           off, g, trc);
-  }
 }
 
 // Conservative update of the active cells (eq. finite_vol) from the face

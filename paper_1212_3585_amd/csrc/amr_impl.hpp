@@ -235,22 +235,16 @@ class AmrImpl final : public AmrImplBase {
     using Sh = AmrFluxShape<DIM, M, TB>;
     const unsigned nb = (unsigned)((lv.nact + Sh::CPB - 1) / Sh::CPB);
     // one instantiation per flux (only Euler has the Osher-type flux); the
-    // listed coarse-fine faces in their own kernel
-    constexpr int GPB = kBlock / AmrFluxShape<DIM, M>::G;  // faces per block
+    // listed coarse-fine faces in the first ncb blocks of the same launch
+    constexpr int GPB = Sh::BLOCK / Sh::G;  // coarse-fine faces per block
     const unsigned ncb = (unsigned)((lv.ncf + GPB - 1) / GPB);
-    if (SYS == 1 && lv.mp.flux == 1) {
-      hipLaunchKernelGGL((k_amr_flux<DIM, M, SYS, R, TB, 1>), dim3(nb), dim3(Sh::BLOCK), 0, st,
-                         a, lv.mp, c, ac, lv.fbuf, lv.hdr);
-      if (lv.ncf > 0)
-        hipLaunchKernelGGL((k_amr_flux_cf<DIM, M, SYS, R, 1>), dim3(ncb), dim3(kBlock), 0, st, a,
-                           lv.mp, c, ac, (const int32_t*)lv.cf, lv.ncf, lv.fbuf);
-    } else {
-      hipLaunchKernelGGL((k_amr_flux<DIM, M, SYS, R, TB, 0>), dim3(nb), dim3(Sh::BLOCK), 0, st,
-                         a, lv.mp, c, ac, lv.fbuf, lv.hdr);
-      if (lv.ncf > 0)
-        hipLaunchKernelGGL((k_amr_flux_cf<DIM, M, SYS, R, 0>), dim3(ncb), dim3(kBlock), 0, st, a,
-                           lv.mp, c, ac, (const int32_t*)lv.cf, lv.ncf, lv.fbuf);
-    }
+    const int32_t* cfl = (const int32_t*)lv.cf;
+    if (SYS == 1 && lv.mp.flux == 1)
+      hipLaunchKernelGGL((k_amr_flux<DIM, M, SYS, R, TB, 1>), dim3(ncb + nb), dim3(Sh::BLOCK), 0,
+                         st, a, lv.mp, c, ac, lv.fbuf, lv.hdr, cfl, (int64_t)lv.ncf, ncb);
+    else
+      hipLaunchKernelGGL((k_amr_flux<DIM, M, SYS, R, TB, 0>), dim3(ncb + nb), dim3(Sh::BLOCK), 0,
+                         st, a, lv.mp, c, ac, lv.fbuf, lv.hdr, cfl, (int64_t)lv.ncf, ncb);
     return hipGetLastError();
   }
 
