@@ -446,23 +446,32 @@ hipError_t children_from(ader_amr a, int l, const int32_t* moth, int64_t nm, con
   return e;
 }
 
-ader_status record_advance(ader_amr a, int l, int sub, hipStream_t st) {
+// Records level l's substep 'sub': the finer levels' substeps recursively
+// between its predictor and its update.  A substep that is not the last of
+// its level's run (defer_apply) computes its face fluxes and leaves the
+// update of its cells to the next substep's preparation launch (prepare
+// with apply_dt): the two touch disjoint cells.
+ader_status record_advance(ader_amr a, int l, int sub, bool defer_apply, bool pending_apply,
+                           hipStream_t st) {
   const ader::AmrImplBase* im = a->impl;
   hipError_t e = hipSuccess;
-  // virtual mothers of the finer levels, finest first; then this level's
-  // averaging, projection and the finer level's memory in one launch
+  // virtual mothers of the finer levels, finest first (they read finer
+  // levels only, so they may precede the pending update); then this level's
+  // averaging, projection, the finer level's memory and the pending update
+  // in one launch
   for (int lev = a->L - 1; lev > l && e == hipSuccess; --lev)
     e = im->average(a->lv[lev], a->lv[lev + 1], a->r, st);
   if (e == hipSuccess)
     e = im->prepare(a->lv[l], l > 0 ? &a->lv[l - 1] : nullptr,
-                    l < a->L ? &a->lv[l + 1] : nullptr, a->ac, sub, st);
+                    l < a->L ? &a->lv[l + 1] : nullptr, a->ac, sub,
+                    pending_apply ? &a->clock->dt[l] : nullptr, st);
   if (e == hipSuccess) e = im->predict(a->lv[l], &a->clock->dt[l], a->dc, a->shape, st);
   if (e != hipSuccess) return hip_status(e, "ader_amr_step");
   if (l < a->L)
     for (int s = 0; s < a->r; ++s)
-      if (ader_status stt = record_advance(a, l + 1, s, st)) return stt;
+      if (ader_status stt = record_advance(a, l + 1, s, s + 1 < a->r, s > 0, st)) return stt;
   e = im->update(a->lv[l], l > 0 ? &a->lv[l - 1] : nullptr, l < a->L ? &a->lv[l + 1] : nullptr,
-                 &a->clock->dt[l], sub, a->dc, a->ac, a->shape, st);
+                 &a->clock->dt[l], sub, a->dc, a->ac, a->shape, !defer_apply, st);
   return hip_status(e, "ader_amr_step");
 }
 
@@ -473,7 +482,7 @@ ader_status record_step(ader_amr a, hipStream_t st) {
       e = a->impl->cfl(a->lv[l], a->partial + (size_t)l * ader::kDtMaxBlocks, a->dtargs.nb[l], st);
   if (e == hipSuccess) e = ader::launch_amr_dt(a->partial, a->dtargs, a->clock, a->lv[0].hdr, st);
   if (e != hipSuccess) return hip_status(e, "ader_amr_step");
-  if (ader_status s = record_advance(a, 0, 0, st)) return s;
+  if (ader_status s = record_advance(a, 0, 0, false, false, st)) return s;
   for (int lev = a->L - 1; lev >= 0 && e == hipSuccess; --lev)
     e = a->impl->average(a->lv[lev], a->lv[lev + 1], a->r, st);
   return hip_status(e, "ader_amr_step");

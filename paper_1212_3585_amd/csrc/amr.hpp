@@ -219,6 +219,12 @@ __device__ __forceinline__ void eval_predictor(const R* __restrict__ q, const do
 }
 
 // The work of one level substep before its reconstruction, in one launch:
+//   blocks [0, nab)             the level's conservative update of its
+//                               previous substep (amr_apply_cell), when the
+//                               caller defers it to this launch: it writes
+//                               the active cells, which nothing below reads
+//                               or writes;
+//   then, counting threads from block nab:
 //   threads [0, nvm)            virtual mothers of the level = mean of their
 //                               children (eq. average);
 //   threads [nvm, nvm + nvc)    virtual children of the level = sub-cell
@@ -226,7 +232,7 @@ __device__ __forceinline__ void eval_predictor(const R* __restrict__ q, const do
 //                               substep's mother-local time (Section 3.1.3);
 //   the rest                    the finer level's memory at its virtual
 //                               children cleared (its r substeps follow).
-// The three sets are disjoint; nothing reads what another writes.
+// The sets are disjoint; nothing reads what another writes.
 struct AmrPrepArgs {
   double* u;
   int64_t ld;
@@ -246,64 +252,6 @@ struct AmrPrepArgs {
   int64_t nvcf;
   int sub;
 };
-
-template <int DIM, int M, int NV, typename R>
-__global__ void __launch_bounds__(kBlock)
-k_amr_prepare(AmrPrepArgs a, AmrConsts ac, WsHeader* hdr) {
-  constexpr int n = M + 1;
-  constexpr int NST = Pow<n, DIM + 1>::v;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  unsigned int flags = 0;
-  const int r = ac.r;
-  if (i < a.nvm) {
-    const int64_t cell = a.vm[i];
-    int c[3];
-    dense_coords<DIM>(cell, a.n, c);
-    const int nchild = DIM == 2 ? r * r : r * r * r;
-    double sum[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) sum[v] = 0.0;
-    for (int b = 0; b < nchild; ++b) {
-      int f[3] = {c[0] * r + b % r, DIM > 1 ? c[1] * r + (b / r) % r : 0,
-                  DIM > 2 ? c[2] * r + b / (r * r) : 0};
-      const int64_t child = dense_index<DIM>(f, a.nf);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) sum[v] += a.uf[v * a.ldf + child];
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) a.u[v * a.ld + cell] = sum[v] / nchild;
-  } else if (i < a.nvm + a.nvc) {
-    const int64_t cell = a.vc[i - a.nvm];
-    int c[3], m[3], o[3];
-    dense_coords<DIM>(cell, a.n, c);
-    for (int k = 0; k < 3; ++k) {
-      m[k] = c[k] / r;
-      o[k] = c[k] % r;
-    }
-    const int32_t mp = a.pos_c[dense_index<DIM>(m, a.nc)];
-    if (mp < 0) {
-      flags |= kFlagBadIndex;  // a virtual child whose mother is not active
-    } else {
-      double wt[4], wax[3][4];
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        wt[p] = p < n ? ac.at_sub[a.sub][p] : 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) wax[k][p] = p < n ? ac.sub_avg[o[k]][p] : 0.0;
-      }
-      double val[NV];
-      eval_predictor<DIM, M, NV, R>(static_cast<const R*>(a.qh_c) + (int64_t)mp * NV * NST, wt,
-                                    wax, val);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) a.u[v * a.ld + cell] = val[v];
-    }
-  } else {
-    const int64_t j = i - a.nvm - a.nvc;
-    constexpr int E = 2 * DIM * NV;  // memory entries per cell
-    if (j < a.nvcf * E) a.mem_f[(j / a.nvcf) * a.ldf + a.vcf[j % a.nvcf]] = 0.0;
-  }
-  block_report(0u, flags, hdr);
-}
 
 // First WENO pass (along x) of the active cells; the (2M+1)^d stencil is
 // addressed on the dense grid with the boundary maps.  Output layout as
@@ -677,40 +625,112 @@ k_amr_cf_faces(AmrUpdArgs a, MeshParams mp, int32_t* __restrict__ list, int* __r
                                                                            : kFaceBad));
 }
 
-// Conservative update of the active cells (eq. finite_vol) from the face
+// Conservative update of active cell i (eq. finite_vol) from the face
 // fluxes of k_amr_flux: the low face on axis k is the low neighbour's high
 // face when that neighbour is an active cell of the same level.
 template <int DIM, int SYS>
-__global__ void __launch_bounds__(kBlock)
-k_amr_apply(AmrUpdArgs a, MeshParams mp, const double* __restrict__ fbuf, WsHeader* hdr) {
+__device__ __forceinline__ void amr_apply_cell(const AmrUpdArgs& a, const MeshParams& mp,
+                                               const double* __restrict__ fbuf, int64_t i,
+                                               unsigned int& flags) {
   constexpr int NV = NVars<SYS, DIM>::v;
   constexpr int FS = 2 * DIM;
+  const int64_t ld = mp.ld;
+  const int64_t cell = a.act[i];
+  const double dt = *a.dt;
+  double q[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) q[v] = a.u[v * ld + cell];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    const int32_t code = a.fc[(2 * k) * a.nact + i];  // the low face
+    const double* fhi = fbuf + (i * FS + 2 * k + 1) * NV;
+    const double* flo = code >= 0 ? fbuf + ((int64_t)code * FS + 2 * k + 1) * NV
+                                  : fbuf + (i * FS + 2 * k) * NV;
+    if (code == kFaceBad) flags |= kFlagBadIndex;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      q[v] -= (dt / mp.dx[k]) * (fhi[v] - (code == kFaceBad ? 0.0 : flo[v]));
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    a.u[v * ld + cell] = q[v];
+    if (q[v] != q[v]) flags |= kFlagNan;
+  }
+  if (!state_physical<SYS, DIM>(q, mp.gamma)) flags |= kFlagNonPhysical;
+}
+
+template <int DIM, int SYS>
+__global__ void __launch_bounds__(kBlock)
+k_amr_apply(AmrUpdArgs a, MeshParams mp, const double* __restrict__ fbuf, WsHeader* hdr) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   unsigned int flags = 0;
-  if (i < a.nact) {
-    const int64_t ld = mp.ld;
-    const int64_t cell = a.act[i];
-    const double dt = *a.dt;
-    double q[NV];
+  if (i < a.nact) amr_apply_cell<DIM, SYS>(a, mp, fbuf, i, flags);
+  block_report(0u, flags, hdr);
+}
+
+// The launch of one level substep before its reconstruction (AmrPrepArgs).
+template <int DIM, int M, int SYS, typename R>
+__global__ void __launch_bounds__(kBlock)
+k_amr_prepare(AmrPrepArgs a, AmrConsts ac, WsHeader* hdr, AmrUpdArgs ua, MeshParams ump,
+              const double* __restrict__ fbuf, unsigned nab) {
+  constexpr int n = M + 1;
+  constexpr int NV = NVars<SYS, DIM>::v;
+  constexpr int NST = Pow<n, DIM + 1>::v;
+  unsigned int flags = 0;
+  if (blockIdx.x < nab) {  // the level's update of its previous substep (uniform in the block)
+    const int64_t ia = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (ia < ua.nact) amr_apply_cell<DIM, SYS>(ua, ump, fbuf, ia, flags);
+    block_report(0u, flags, hdr);
+    return;
+  }
+  const int64_t i = (int64_t)(blockIdx.x - nab) * kBlock + threadIdx.x;
+  const int r = ac.r;
+  if (i < a.nvm) {
+    const int64_t cell = a.vm[i];
+    int c[3];
+    dense_coords<DIM>(cell, a.n, c);
+    const int nchild = DIM == 2 ? r * r : r * r * r;
+    double sum[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) q[v] = a.u[v * ld + cell];
+    for (int v = 0; v < NV; ++v) sum[v] = 0.0;
+    for (int b = 0; b < nchild; ++b) {
+      int f[3] = {c[0] * r + b % r, DIM > 1 ? c[1] * r + (b / r) % r : 0,
+                  DIM > 2 ? c[2] * r + b / (r * r) : 0};
+      const int64_t child = dense_index<DIM>(f, a.nf);
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      const int32_t code = a.fc[(2 * k) * a.nact + i];  // the low face
-      const double* fhi = fbuf + (i * FS + 2 * k + 1) * NV;
-      const double* flo = code >= 0 ? fbuf + ((int64_t)code * FS + 2 * k + 1) * NV
-                                    : fbuf + (i * FS + 2 * k) * NV;
-      if (code == kFaceBad) flags |= kFlagBadIndex;
-#pragma unroll
-      for (int v = 0; v < NV; ++v)
-        q[v] -= (dt / mp.dx[k]) * (fhi[v] - (code == kFaceBad ? 0.0 : flo[v]));
+      for (int v = 0; v < NV; ++v) sum[v] += a.uf[v * a.ldf + child];
     }
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      a.u[v * ld + cell] = q[v];
-      if (q[v] != q[v]) flags |= kFlagNan;
+    for (int v = 0; v < NV; ++v) a.u[v * a.ld + cell] = sum[v] / nchild;
+  } else if (i < a.nvm + a.nvc) {
+    const int64_t cell = a.vc[i - a.nvm];
+    int c[3], m[3], o[3];
+    dense_coords<DIM>(cell, a.n, c);
+    for (int k = 0; k < 3; ++k) {
+      m[k] = c[k] / r;
+      o[k] = c[k] % r;
     }
-    if (!state_physical<SYS, DIM>(q, mp.gamma)) flags |= kFlagNonPhysical;
+    const int32_t mp = a.pos_c[dense_index<DIM>(m, a.nc)];
+    if (mp < 0) {
+      flags |= kFlagBadIndex;  // a virtual child whose mother is not active
+    } else {
+      double wt[4], wax[3][4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        wt[p] = p < n ? ac.at_sub[a.sub][p] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) wax[k][p] = p < n ? ac.sub_avg[o[k]][p] : 0.0;
+      }
+      double val[NV];
+      eval_predictor<DIM, M, NV, R>(static_cast<const R*>(a.qh_c) + (int64_t)mp * NV * NST, wt,
+                                    wax, val);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) a.u[v * a.ld + cell] = val[v];
+    }
+  } else {
+    const int64_t j = i - a.nvm - a.nvc;
+    constexpr int E = 2 * DIM * NV;  // memory entries per cell
+    if (j < a.nvcf * E) a.mem_f[(j / a.nvcf) * a.ldf + a.vcf[j % a.nvcf]] = 0.0;
   }
   block_report(0u, flags, hdr);
 }

@@ -47,7 +47,8 @@ class AmrImpl final : public AmrImplBase {
   }
 
   hipError_t prepare(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
-                     const AmrConsts& ac, int sub, hipStream_t st) const override {
+                     const AmrConsts& ac, int sub, const double* apply_dt,
+                     hipStream_t st) const override {
     AmrPrepArgs a{};
     a.u = lv.u;
     a.ld = lv.ncells;
@@ -71,9 +72,13 @@ class AmrImpl final : public AmrImplBase {
     }
     a.sub = sub;
     const int64_t total = a.nvm + a.nvc + a.nvcf * 2 * DIM * NV;
-    if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_amr_prepare<DIM, M, NV, R>), dim3(amr_blocks(total)), dim3(kBlock), 0,
-                       st, a, ac, lv.hdr);
+    // the level's deferred update of its previous substep in the first blocks
+    const AmrUpdArgs ua = upd_args(lv, coarse, fine, apply_dt, sub, ac);
+    const unsigned nab = apply_dt && lv.nact > 0 ? amr_blocks(lv.nact) : 0u;
+    const unsigned npb = (unsigned)((total + kBlock - 1) / kBlock);
+    if (nab + npb == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_amr_prepare<DIM, M, SYS, R>), dim3(nab + npb), dim3(kBlock), 0, st, a,
+                       ac, lv.hdr, ua, lv.mp, (const double*)lv.fbuf, nab);
     return hipGetLastError();
   }
 
@@ -271,10 +276,10 @@ class AmrImpl final : public AmrImplBase {
 
   hipError_t update(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
                     const double* dt, int sub, const DevConsts& c, const AmrConsts& ac,
-                    const AmrShape& sh, hipStream_t st) const override {
+                    const AmrShape& sh, bool apply, hipStream_t st) const override {
     if (lv.nact == 0) return hipSuccess;
     hipError_t e = flux_only(lv, coarse, fine, dt, sub, c, ac, sh.flux_block, st);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || !apply) return e;
     const AmrUpdArgs a = upd_args(lv, coarse, fine, dt, sub, ac);
     hipLaunchKernelGGL((k_amr_apply<DIM, SYS>), dim3(amr_blocks(lv.nact)), dim3(kBlock), 0, st,
                        a, lv.mp, (const double*)lv.fbuf, lv.hdr);

@@ -91,9 +91,12 @@ class AmrImplBase {
                              hipStream_t st) const = 0;
   // one level substep's averaging (from 'fine'), projection (from 'coarse'
   // at substep 'sub') and the clearing of fine's memory at its virtual
-  // children; coarse / fine may be null at the ends
+  // children; coarse / fine may be null at the ends.  With apply_dt, the
+  // same launch also applies the level's update of its previous substep
+  // (deferred by update(..., apply = false)) with step *apply_dt.
   virtual hipError_t prepare(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
-                             const AmrConsts& ac, int sub, hipStream_t st) const = 0;
+                             const AmrConsts& ac, int sub, const double* apply_dt,
+                             hipStream_t st) const = 0;
   // reconstruction + predictor of the active cells of 'lv' with step *dt
   virtual hipError_t predict(const AmrLevel& lv, const double* dt, const DevConsts& c,
                              const AmrShape& sh, hipStream_t st) const = 0;
@@ -102,10 +105,12 @@ class AmrImplBase {
   // fits (LDS)
   virtual bool pred_block_ok(int block) const = 0;
   // finite-volume update of the active cells of 'lv' (substep 'sub' of the
-  // coarser level's step); coarse / fine may be null at the ends
+  // coarser level's step); coarse / fine may be null at the ends.  With
+  // apply false only the face fluxes are computed, and the update is left
+  // to the level's next prepare (its apply_dt)
   virtual hipError_t update(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
                             const double* dt, int sub, const DevConsts& c, const AmrConsts& ac,
-                            const AmrShape& sh, hipStream_t st) const = 0;
+                            const AmrShape& sh, bool apply, hipStream_t st) const = 0;
   // the list of the level's coarse-fine faces into lv.cf; *count (device)
   // must be zero on entry and holds the count on exit
   virtual hipError_t cf_faces(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
