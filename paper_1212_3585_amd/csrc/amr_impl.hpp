@@ -82,14 +82,24 @@ class AmrImpl final : public AmrImplBase {
     return hipGetLastError();
   }
 
+  // 2D fp64: the matrix-core predictor with the fused reconstruction (fixed
+  // 256-thread blocks).  The dense wave-local predictor (seven cells of nine
+  // lanes per wavefront at M = 2) made the 2D explosion step 5% slower in
+  // fp64 and 4.5% faster with the fp32 predictor, which uses it.
   static constexpr bool kMfmaPredictor = DIM == 2 && std::is_same<R, double>::value;
 
-  // the generic predictor's LDS: DIM NV block values of R (at most 64 KiB)
+  // the wave-local predictor's LDS for a block of BLK threads: the fp64 flux
+  // records, the stopping thresholds' scratch and (2D) the fused
+  // reconstruction's x lines and w_h, within the 160 KiB of a CU
   template <int BLK>
   static constexpr bool pred_fits() {
-    // fluxes of the block, plus (2D) the block's fused reconstruction
-    constexpr size_t wsh = DIM == 2 ? (size_t)(BLK / Pow<n, DIM>::v) * NV * Pow<n, DIM>::v * 8 : 0;
-    return (size_t)DIM * NV * BLK * sizeof(R) + wsh + 2048 <= 65536;
+    constexpr int NS = Pow<n, DIM>::v;
+    constexpr int CPB = WaveCells<DIM, NS>::CPW * (BLK / 64);
+    constexpr size_t VPV = 16 / sizeof(R);
+    constexpr size_t RV = (NV + VPV - 1) / VPV * VPV;
+    constexpr size_t rec = std::is_same<R, double>::value ? (size_t)(BLK / 64) * DIM * 64 * RV * 8 : 0;
+    constexpr size_t fuse = DIM == 2 ? (size_t)CPB * NV * (NS + S * n) * 8 : 0;
+    return rec + fuse + (size_t)(BLK / 64) * 64 * sizeof(R) + 1024 <= 163840;
   }
 
   bool pred_block_ok(int block) const override {
@@ -110,22 +120,21 @@ class AmrImpl final : public AmrImplBase {
     } else {
       constexpr int NS = Pow<n, DIM>::v;
       const int64_t np = lv.nact;
-      const dim3 grid((unsigned)((np + BLK / NS - 1) / (BLK / NS)));
+      // wavefront-local exchanges (no block barriers in the sweeps)
+      constexpr int WCPB = WaveCells<DIM, NS>::CPW * (BLK / 64);
+      const dim3 wgrid((unsigned)((np + WCPB - 1) / WCPB));
       if constexpr (DIM == 2) {  // reconstruction fused into the predictor
         FuseWeno fw;
         fw.u = lv.u;
         fw.ld = lv.ncells;
         fw.act = lv.act;
-        hipLaunchKernelGGL((k_predict<DIM, M, SYS, R, R, BLK, true>), grid, dim3(BLK), 0, st,
-                           (const double*)nullptr, static_cast<R*>(lv.qh), np, dt, lv.mp, c,
+        hipLaunchKernelGGL((k_predict_wave<DIM, M, SYS, R, R, BLK, true>), wgrid, dim3(BLK), 0,
+                           st, (const double*)nullptr, static_cast<R*>(lv.qh), np, dt, lv.mp, c,
                            lv.hdr, fw);
       } else {
-        // wavefront-local exchanges (no LDS round trips, no block barriers)
-        constexpr int WCPB = (64 / WaveGroup<NS>::G) * (BLK / 64);
-        const dim3 wgrid((unsigned)((np + WCPB - 1) / WCPB));
         hipLaunchKernelGGL((k_predict_wave<DIM, M, SYS, R, R, BLK>), wgrid, dim3(BLK), 0, st,
                            (const double*)lv.wh, static_cast<R*>(lv.qh), np, dt, lv.mp, c,
-                           lv.hdr);
+                           lv.hdr, FuseWeno{});
       }
       return hipGetLastError();
     }
@@ -162,25 +171,23 @@ class AmrImpl final : public AmrImplBase {
                          dim3(kBlock), 0, st, (const double*)dwxy, lv.ncells, lv.act, np, lv.mp,
                          lv.wh, c);
     }
-    R* qh = static_cast<R*>(lv.qh);
-    if constexpr (DIM == 2 && std::is_same<R, double>::value) {
+    if constexpr (kMfmaPredictor) {
       FuseWeno fw;
       fw.u = lv.u;
       fw.ld = lv.ncells;
       fw.act = lv.act;
       hipLaunchKernelGGL((k_predict_mfma2d<M, SYS, R, true>),
                          dim3((unsigned)((np + 4 * (kBlock / 64) - 1) / (4 * (kBlock / 64)))),
-                         dim3(kBlock), 0, st, (const double*)nullptr, qh, np, dt, lv.mp, c,
-                         lv.hdr, fw);
+                         dim3(kBlock), 0, st, (const double*)nullptr, static_cast<R*>(lv.qh), np,
+                         dt, lv.mp, c, lv.hdr, fw);
+      return hipGetLastError();
     } else {
-      (void)qh;
       switch (sh.pred_block) {
         case 128: return launch_predict<128>(lv, dt, c, st);
         case 512: return launch_predict<512>(lv, dt, c, st);
         default: return launch_predict<256>(lv, dt, c, st);
       }
     }
-    return hipGetLastError();
   }
 
   hipError_t children(const AmrLevel& cl, const int32_t* moth, int64_t nm, double* wa,

@@ -606,12 +606,10 @@ __device__ __forceinline__ void pick_row(const DevConsts& c, int a, R (&row)[n])
 // Space-time predictor of 'ncells' cells whose nodal reconstructions are
 // wh[(cell * NV + v) * NS + a].  Output qh[(cell * NV + v) * NST + a + NS * s]
 // in type OUT.  One lane per spatial node a; CPB cells per BLK-thread block.
-template <int DIM, int M, int SYS, typename R, typename OUT, int BLK = kBlock,
-          bool FUSE = false>
+template <int DIM, int M, int SYS, typename R, typename OUT, int BLK = kBlock>
 __global__ void __launch_bounds__(BLK)
 k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
-          const double* __restrict__ dt_dev, MeshParams mp, DevConsts c, WsHeader* hdr,
-          FuseWeno fw = FuseWeno()) {
+          const double* __restrict__ dt_dev, MeshParams mp, DevConsts c, WsHeader* hdr) {
   constexpr int n = M + 1;
   constexpr int NS = Pow<n, DIM>::v;
   constexpr int NST = NS * n;
@@ -645,21 +643,10 @@ k_predict(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
 #pragma unroll
   for (int k = 0; k < DIM; ++k) pick_row<n, R>(c, ak[k], drow[k]);
 
-  // w_hat: from the global reconstruction, or (FUSE, 2D) from the block's own
-  // reconstruction in LDS
-  const double* wsrc = wh;
-  int64_t wcell = cell;
-  if constexpr (FUSE) {
-    static_assert(DIM == 2, "fused reconstruction in 2D only");
-    __shared__ double sWh[CPB * NV * NS];
-    weno2d_block<M, NV, CPB>(fw, (int64_t)blockIdx.x * CPB, ncells, mp, c, sWh);
-    wsrc = sWh;
-    wcell = lc;
-  }
   R w[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v)
-    w[v] = active ? (R)wsrc[(wcell * NV + v) * NS + a] : (v == 0 || v == NV - 1 ? R(1) : R(0));
+    w[v] = active ? (R)wh[(cell * NV + v) * NS + a] : (v == 0 || v == NV - 1 ? R(1) : R(0));
   R q[NV][n];
 #pragma unroll
   for (int v = 0; v < NV; ++v)

@@ -45,6 +45,15 @@ template <int NS> struct WaveGroup {
   static_assert(NS <= 64, "a cell must fit one wavefront");
 };
 
+// Lanes of the wave-local predictor: in 3D a power-of-two group per cell
+// (WaveGroup); in 2D exactly n^2 lanes per cell, packed (M = 2: seven cells
+// of nine lanes per wavefront, where a power-of-two group holds four), the
+// lanes after the last whole cell idle.
+template <int DIM, int NS> struct WaveCells {
+  static constexpr int G = DIM == 2 ? NS : WaveGroup<NS>::G;
+  static constexpr int CPW = 64 / G;  // cells per wavefront
+};
+
 template <typename R> __device__ __forceinline__ R lane_fetch(R x, int lane);
 template <> __device__ __forceinline__ float lane_fetch<float>(float x, int lane) {
   return __int_as_float(__builtin_amdgcn_ds_bpermute(lane << 2, __float_as_int(x)));
@@ -71,30 +80,40 @@ __device__ __forceinline__ R group_max(R x) {
   return x;
 }
 
-template <int DIM, int M, int SYS, typename R, typename OUT, int BLK = kBlock>
+// FUSE (2D): the block reconstructs its own cells first (weno2d_block, from
+// the averages fw.u of the listed cells fw.act) instead of reading w_h.
+template <int DIM, int M, int SYS, typename R, typename OUT, int BLK = kBlock, bool FUSE = false>
 __global__ void __launch_bounds__(BLK)
 k_predict_wave(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncells,
-               const double* __restrict__ dt_dev, MeshParams mp, DevConsts c, WsHeader* hdr) {
+               const double* __restrict__ dt_dev, MeshParams mp, DevConsts c, WsHeader* hdr,
+               FuseWeno fw = FuseWeno{}) {
   constexpr int n = M + 1;
   constexpr int NS = Pow<n, DIM>::v;
   constexpr int NST = NS * n;
   constexpr int NV = NVars<SYS, DIM>::v;
-  constexpr int G = WaveGroup<NS>::G;
-  constexpr int CPW = 64 / G;            // cells per wavefront
-  constexpr int CPB = CPW * (BLK / 64);  // cells per block
+  constexpr int G = WaveCells<DIM, NS>::G;
+  constexpr int CPW = WaveCells<DIM, NS>::CPW;  // cells per wavefront
+  constexpr int CPB = CPW * (BLK / 64);         // cells per block
+  static_assert(!FUSE || DIM == 2, "fused reconstruction in 2D only");
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int slot = lane / G;
+  const int slot_raw = lane / G;
+  const bool slot_ok = slot_raw < CPW;     // lanes after the last whole cell idle
+  const int slot = slot_ok ? slot_raw : 0;  // ... and address cell 0's lanes
   const int a_raw = lane % G;
-  const bool node_ok = a_raw < NS;
-  const int a = node_ok ? a_raw : 0;  // padding lanes mirror node 0 (never written out)
-  // reverse block order: the reconstructions written last by the preceding
-  // pass are read first, while still cached (the face kernel then runs forward)
-  const int64_t cell = (int64_t)(gridDim.x - 1 - blockIdx.x) * CPB + wave * CPW + slot;
-  const bool cell_ok = cell < ncells;
+  const bool node_ok = slot_ok && a_raw < NS;
+  const int a = a_raw < NS ? a_raw : 0;  // padding lanes mirror node 0 (never written out)
+  // 3D: reverse block order, so that the reconstructions written last by the
+  // preceding pass are read first, while still cached (the face kernel then
+  // runs forward); 2D (fused reconstruction): forward, the face kernel reverse
+  const int64_t blk = FUSE ? (int64_t)blockIdx.x : (int64_t)(gridDim.x - 1 - blockIdx.x);
+  const int lc = wave * CPW + slot;  // the cell's place in the block
+  const int64_t cell = blk * CPB + lc;
+  const bool cell_ok = slot_ok && cell < ncells;
   const bool active = cell_ok && node_ok;
-  const uint64_t cell_lanes = (G == 64 ? ~0ULL : ((1ULL << G) - 1ULL)) << (slot * G);
+  const uint64_t cell_lanes =
+      slot_ok ? (G == 64 ? ~0ULL : ((1ULL << G) - 1ULL)) << (slot * G) : 0ULL;
 
   int ak[3] = {a % n, (a / n) % n, a / (n * n)};
   const double dt = *dt_dev;
@@ -117,16 +136,35 @@ k_predict_wave(const double* __restrict__ wh, OUT* __restrict__ qh, int64_t ncel
   const R ch = (R)mp.ch;
   const R adv[3] = {(R)mp.adv[0], (R)mp.adv[1], (R)mp.adv[2]};
 
+  const double* wsrc = wh + cell * NV * NS;
+  if constexpr (FUSE) {
+    __shared__ double sWh[CPB * NV * NS];
+    weno2d_block<M, NV, CPB>(fw, blk * CPB, ncells, mp, c, sWh);
+    wsrc = sWh + lc * NV * NS;
+  }
   R w[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v)
-    w[v] = active ? (R)wh[(cell * NV + v) * NS + a] : (v == 0 || v == NV - 1 ? R(1) : R(0));
+    w[v] = active ? (R)wsrc[v * NS + a] : (v == 0 || v == NV - 1 ? R(1) : R(0));
 
   // stopping threshold of the cell: tol * max(1, max |w_hat|) over its nodes
   R wmax = R(0);
 #pragma unroll
   for (int v = 0; v < NV; ++v) wmax = fmax(wmax, fabs(w[v]));
-  const R thr = (R)mp.tol * fmax(R(1), group_max<G>(node_ok ? wmax : R(0)));
+  wmax = node_ok ? wmax : R(0);
+  R cmax;
+  if constexpr ((G & (G - 1)) == 0) {
+    cmax = group_max<G>(wmax);
+  } else {
+    // a group that is not a power of two: through wavefront-private LDS
+    __shared__ R smax[BLK / 64][64];
+    smax[wave][lane] = wmax;
+    wave_lds_order();
+    cmax = R(0);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) cmax = fmax(cmax, smax[wave][slot * G + j]);
+  }
+  const R thr = (R)mp.tol * fmax(R(1), cmax);
 
   // fp64 exchange: wavefront-private flux records [axis][lane][NV values,
   // padded to whole 16-byte vectors]; the full vectors move as 16-byte
