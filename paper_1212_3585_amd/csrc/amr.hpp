@@ -8,7 +8,9 @@
 //   k_amr_dt        level-0 step from all levels' maxima, level steps, clock
 //   k_amr_average   virtual mothers = mean of their r^d children (eq. average)
 //   k_amr_prepare   one launch per level substep for the averaging, the
-//                   projection and the clearing of the finer level's memory
+//                   projection and the clearing of the finer level's memory,
+//                   and the level's update of its previous substep (all but
+//                   the last substep of a run defer it to this launch)
 //   k_amr_weno_x    first WENO pass of the active cells, stencil indices from
 //                   the dense grid; later passes and the predictor are the
 //                   level-list kernels (level.hpp, predictor kernels)
@@ -23,13 +25,15 @@
 //                   each face once (a cell's high faces, and its low faces
 //                   not shared with an active cell of the level): same-level
 //                   faces as on a uniform mesh; its first blocks take the
-//                   listed coarse-fine faces, a group per face: a face to a virtual child
-//                   (coarser neighbour) takes the coarse predictor at this
-//                   face's Gauss points and this substep's time nodes and
-//                   stores the flux in the virtual child's memory; a face to
-//                   a virtual mother (finer neighbour) averages the memory of
-//                   this cell's virtual children on that face (eq. memory.sum)
+//                   listed coarse-fine faces, a group per face: a face to a
+//                   virtual child (coarser neighbour) takes the coarse
+//                   predictor at this face's Gauss points and this
+//                   substep's time nodes and stores the flux in the virtual
+//                   child's memory; a face to a virtual mother (finer
+//                   neighbour) averages the memory of this cell's virtual
+//                   children on that face (eq. memory.sum)
 //   k_amr_apply     conservative update of the active cells from those fluxes
+//                   (after the last substep of a run; amr_apply_cell)
 #pragma once
 
 #include "amr_plan.hpp"

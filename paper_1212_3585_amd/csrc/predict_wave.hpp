@@ -1,13 +1,16 @@
-// Space-time predictor with wavefront-local exchanges (used in 3D).
+// Space-time predictor with wavefront-local exchanges (3D, and the 2D AMR
+// levels of the fp32-predictor form).
 //
 // The generic predictor (k_predict) gives every spatial node of a cell one
 // lane and exchanges the nodal fluxes through LDS, with two block barriers
 // per time node; in 3D that moves more LDS bytes per cell and sweep than the
-// arithmetic needs cycles.  Here a cell owns a power-of-two group of G >= n^d
-// lanes inside one wavefront (G = 8, 32, 64 for n^3 = 8, 27, 64), so the
+// arithmetic needs cycles.  Here a cell owns a group of G >= n^d lanes inside
+// one wavefront (WaveCells: in 3D a power of two, G = 8, 32, 64 for n^3 = 8,
+// 27, 64; in 2D exactly n^2, seven cells of nine lanes at M = 2), so the
 // derivative along axis k takes the n - 1 other nodes of the lane's line
-// from lanes of the same wavefront: no block barriers, and the stopping test
-// is a ballot over the cell's lanes.
+// from lanes of the same wavefront: no block barriers in the sweeps, and the
+// stopping test is a ballot over the cell's lanes.  With FUSE (2D) the block
+// first reconstructs its own cells (weno2d_block).
 //
 // fp64: each lane publishes its nodal fluxes of one time node as one record
 // per axis in wavefront-private LDS (NV values padded to whole 16-byte
