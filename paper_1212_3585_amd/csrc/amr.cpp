@@ -477,9 +477,7 @@ ader_status record_advance(ader_amr a, int l, int sub, bool defer_apply, bool pe
 
 ader_status record_step(ader_amr a, hipStream_t st) {
   hipError_t e = hipSuccess;
-  for (int l = 0; l <= a->L && e == hipSuccess; ++l)
-    if (a->dtargs.nb[l] > 0)
-      e = a->impl->cfl(a->lv[l], a->partial + (size_t)l * ader::kDtMaxBlocks, a->dtargs.nb[l], st);
+  e = a->impl->cfl(a->lv.data(), a->L + 1, a->partial, a->dtargs.nb, st);
   if (e == hipSuccess) e = ader::launch_amr_dt(a->partial, a->dtargs, a->clock, a->lv[0].hdr, st);
   if (e != hipSuccess) return hip_status(e, "ader_amr_step");
   if (ader_status s = record_advance(a, 0, 0, false, false, st)) return s;

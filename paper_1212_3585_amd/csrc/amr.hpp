@@ -3,8 +3,9 @@
 // its whole index space with a status per cell; the work runs over per-level
 // lists (active cells, virtual children, virtual mothers).
 //
-//   k_amr_cfl       block maxima of sum_k speed_k / dx_k over a level's
-//                   active cells (the CFL rule, reading R1, per level)
+//   k_amr_cfl       block maxima of sum_k speed_k / dx_k over each level's
+//                   active cells (the CFL rule, reading R1), all levels in
+//                   one launch
 //   k_amr_dt        level-0 step from all levels' maxima, level steps, clock
 //   k_amr_average   virtual mothers = mean of their r^d children (eq. average)
 //   k_amr_prepare   one launch per level substep for the averaging, the
@@ -58,16 +59,38 @@ __device__ __forceinline__ double nan_max_d(double a, double b) {
   return (b != b || b > a) ? b : a;  // a NaN wins, so it reaches dt
 }
 
+// The CFL block maxima of every level in one launch: level l takes nb
+// blocks from block 'first' of the grid, and block lb of it writes
+// partial[l kDtMaxBlocks + lb].
+struct AmrCflLevel {
+  const double* u = nullptr;
+  const int32_t* act = nullptr;
+  int64_t nact = 0;
+  MeshParams mp{};
+  int nb = 0;
+  int first = 0;
+};
+struct AmrCflArgs {
+  AmrCflLevel lv[kAmrMaxLevels];
+  int nlev = 0;
+};
+
 template <int DIM, int SYS>
 __global__ void __launch_bounds__(kBlock)
-k_amr_cfl(const double* __restrict__ u, const int32_t* __restrict__ act, int64_t nact,
-          MeshParams mp, double* __restrict__ partial) {
+k_amr_cfl(AmrCflArgs args, double* __restrict__ partial) {
   constexpr int NV = NVars<SYS, DIM>::v;
   __shared__ double sw[kBlock / 64];
+  int l = 0;  // the block's level (uniform in the block)
+  while (l + 1 < args.nlev && (int)blockIdx.x >= args.lv[l + 1].first) ++l;
+  const AmrCflLevel& L = args.lv[l];
+  const int lb = (int)blockIdx.x - L.first;
+  const double* __restrict__ u = L.u;
+  const int32_t* __restrict__ act = L.act;
+  const int64_t nact = L.nact;
+  const MeshParams& mp = L.mp;
   const double adv[3] = {mp.adv[0], mp.adv[1], mp.adv[2]};
   double m = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nact;
-       i += (int64_t)gridDim.x * kBlock) {
+  for (int64_t i = (int64_t)lb * kBlock + threadIdx.x; i < nact; i += (int64_t)L.nb * kBlock) {
     const int64_t cell = act[i];
     double q[NV];
 #pragma unroll
@@ -89,27 +112,34 @@ k_amr_cfl(const double* __restrict__ u, const int32_t* __restrict__ act, int64_t
     double b = sw[0];
 #pragma unroll
     for (int i = 1; i < kBlock / 64; ++i) b = nan_max_d(b, sw[i]);
-    partial[blockIdx.x] = b;
+    partial[l * kDtMaxBlocks + lb] = b;
   }
 }
 
-// one thread: the level-0 step of the AMR run and the level steps
-// (a template so that the header can be included by several units)
+// One wavefront (64 threads): the level-0 step of the AMR run and the level
+// steps.  The lanes read the levels' block maxima in parallel and combine
+// them with a butterfly (a maximum in any order, a NaN winning, so that it
+// reaches dt); lane 0 finishes.  (A template so that the header can be
+// included by several units.)
 template <int TAG>
 __global__ void k_amr_dt(const double* __restrict__ partial, AmrDtArgs a, AmrClock* clock,
                          WsHeader* hdr) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (blockIdx.x != 0) return;
+  const int lane = threadIdx.x;
   double best = 1.0 / 0.0;
   double rl = 1.0;  // r^l
   for (int l = 0; l < a.nlev; ++l) {
-    if (a.nb[l] > 0) {
+    if (a.nb[l] > 0) {  // uniform
       double m = 0.0;
-      for (int i = 0; i < a.nb[l]; ++i) m = nan_max_d(m, partial[l * kDtMaxBlocks + i]);
+      for (int i = lane; i < a.nb[l]; i += 64) m = nan_max_d(m, partial[l * kDtMaxBlocks + i]);
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) m = nan_max_d(m, __shfl_xor(m, o, 64));
       const double cand = rl * a.cfl / m;
       best = (cand != cand || cand < best) ? cand : best;
     }
     rl *= a.r;
   }
+  if (lane != 0) return;
   const double t = clock->t;
   const double rest = clock->t_end - t;
   double dt = rest < best ? rest : best;

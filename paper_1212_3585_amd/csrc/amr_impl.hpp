@@ -31,10 +31,23 @@ class AmrImpl final : public AmrImplBase {
   size_t dense_weno_per_cell() const override { return DIM == 3 ? (size_t)NV * (n + n * n) : 0; }
   size_t fbuf_per_cell() const override { return (size_t)2 * DIM * NV; }
 
-  hipError_t cfl(const AmrLevel& lv, double* partial, int nb, hipStream_t st) const override {
-    if (lv.nact == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_amr_cfl<DIM, SYS>), dim3(nb), dim3(kBlock), 0, st, lv.u, lv.act,
-                       lv.nact, lv.mp, partial);
+  hipError_t cfl(const AmrLevel* lv, int nlev, double* partial, const int* nb,
+                 hipStream_t st) const override {
+    AmrCflArgs args;
+    int blocks = 0;
+    for (int l = 0; l < nlev; ++l) {
+      AmrCflLevel& L = args.lv[l];
+      L.u = lv[l].u;
+      L.act = lv[l].act;
+      L.nact = lv[l].nact;
+      L.mp = lv[l].mp;
+      L.nb = lv[l].nact > 0 ? nb[l] : 0;
+      L.first = blocks;
+      blocks += L.nb;
+    }
+    args.nlev = nlev;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_amr_cfl<DIM, SYS>), dim3(blocks), dim3(kBlock), 0, st, args, partial);
     return hipGetLastError();
   }
 

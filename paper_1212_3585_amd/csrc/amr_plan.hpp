@@ -84,8 +84,10 @@ class AmrImplBase {
   virtual size_t dense_weno_per_cell() const = 0;
   // face-flux doubles per active cell
   virtual size_t fbuf_per_cell() const = 0;
-  // block maxima of sum_k speed_k / dx_k over the active cells -> partial[0..nb)
-  virtual hipError_t cfl(const AmrLevel& lv, double* partial, int nb, hipStream_t st) const = 0;
+  // block maxima of sum_k speed_k / dx_k over the active cells of levels
+  // 0..nlev-1 -> partial[l kDtMaxBlocks + 0..nb[l]), one launch
+  virtual hipError_t cfl(const AmrLevel* lv, int nlev, double* partial, const int* nb,
+                         hipStream_t st) const = 0;
   // virtual mothers of 'coarse' from their children on 'fine'
   virtual hipError_t average(const AmrLevel& coarse, const AmrLevel& fine, int r,
                              hipStream_t st) const = 0;
