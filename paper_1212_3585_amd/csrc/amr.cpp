@@ -447,10 +447,12 @@ hipError_t children_from(ader_amr a, int l, const int32_t* moth, int64_t nm, con
 }
 
 // Records level l's substep 'sub': the finer levels' substeps recursively
-// between its predictor and its update.  A substep that is not the last of
-// its level's run (defer_apply) computes its face fluxes and leaves the
-// update of its cells to the next substep's preparation launch (prepare
-// with apply_dt): the two touch disjoint cells.
+// between its predictor and its update.  A finer level's substep (defer_apply)
+// computes its face fluxes and leaves the update of its cells to the next
+// launch that can carry it: the next substep's preparation (prepare with
+// apply_dt), or after the last substep of the run the coarser level's face
+// launch (update with pend).  They write disjoint cells and read none of the
+// deferred update's.
 ader_status record_advance(ader_amr a, int l, int sub, bool defer_apply, bool pending_apply,
                            hipStream_t st) {
   const ader::AmrImplBase* im = a->impl;
@@ -469,9 +471,11 @@ ader_status record_advance(ader_amr a, int l, int sub, bool defer_apply, bool pe
   if (e != hipSuccess) return hip_status(e, "ader_amr_step");
   if (l < a->L)
     for (int s = 0; s < a->r; ++s)
-      if (ader_status stt = record_advance(a, l + 1, s, s + 1 < a->r, s > 0, st)) return stt;
+      if (ader_status stt = record_advance(a, l + 1, s, true, s > 0, st)) return stt;
   e = im->update(a->lv[l], l > 0 ? &a->lv[l - 1] : nullptr, l < a->L ? &a->lv[l + 1] : nullptr,
-                 &a->clock->dt[l], sub, a->dc, a->ac, a->shape, !defer_apply, st);
+                 &a->clock->dt[l], sub, a->dc, a->ac, a->shape, !defer_apply,
+                 l < a->L ? &a->lv[l + 1] : nullptr, l < a->L ? &a->clock->dt[l + 1] : nullptr,
+                 st);
   return hip_status(e, "ader_amr_step");
 }
 

@@ -34,7 +34,10 @@
 //                   neighbour) averages the memory of this cell's virtual
 //                   children on that face (eq. memory.sum)
 //   k_amr_apply     conservative update of the active cells from those fluxes
-//                   (after the last substep of a run; amr_apply_cell)
+//                   (amr_apply_cell) where no other launch carries it: a
+//                   finer level's updates ride in k_amr_prepare of its next
+//                   substep and, after the last substep of a run, in the
+//                   coarser level's k_amr_flux
 #pragma once
 
 #include "amr_plan.hpp"
@@ -571,6 +574,40 @@ __device__ __forceinline__ void amr_cf_entry(const AmrUpdArgs& a, const MeshPara
   }
 }
 
+// Conservative update of active cell i (eq. finite_vol) from the face
+// fluxes of k_amr_flux: the low face on axis k is the low neighbour's high
+// face when that neighbour is an active cell of the same level.
+template <int DIM, int SYS>
+__device__ __forceinline__ void amr_apply_cell(const AmrUpdArgs& a, const MeshParams& mp,
+                                               const double* __restrict__ fbuf, int64_t i,
+                                               unsigned int& flags) {
+  constexpr int NV = NVars<SYS, DIM>::v;
+  constexpr int FS = 2 * DIM;
+  const int64_t ld = mp.ld;
+  const int64_t cell = a.act[i];
+  const double dt = *a.dt;
+  double q[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) q[v] = a.u[v * ld + cell];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    const int32_t code = a.fc[(2 * k) * a.nact + i];  // the low face
+    const double* fhi = fbuf + (i * FS + 2 * k + 1) * NV;
+    const double* flo = code >= 0 ? fbuf + ((int64_t)code * FS + 2 * k + 1) * NV
+                                  : fbuf + (i * FS + 2 * k) * NV;
+    if (code == kFaceBad) flags |= kFlagBadIndex;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      q[v] -= (dt / mp.dx[k]) * (fhi[v] - (code == kFaceBad ? 0.0 : flo[v]));
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    a.u[v * ld + cell] = q[v];
+    if (q[v] != q[v]) flags |= kFlagNan;
+  }
+  if (!state_physical<SYS, DIM>(q, mp.gamma)) flags |= kFlagNonPhysical;
+}
+
 // Face fluxes of the active cells: each cell computes its high face on every
 // axis, and its low face where the low neighbour is not an active cell of
 // the same level (that face is the neighbour's high face), so every face is
@@ -580,12 +617,18 @@ __device__ __forceinline__ void amr_cf_entry(const AmrUpdArgs& a, const MeshPara
 // per mesh (k_amr_cf_faces) and done by the first ncb blocks of the same
 // launch, a group of G lanes per listed face (amr_cf_entry), so that their
 // gathers overlap the bulk of the same-level faces and the level substep
-// needs no launch of its own for them.  Deriving their kinds in the
+// needs no launch of its own for them.  In 2D the next nab blocks apply the
+// finer level's update of the last substep of its run (ua, deferred to this
+// launch): it writes that level's active cells, which this level's faces do
+// not read (they read its memory, written by its face kernel).  In 3D that
+// path held the kernel at 98 instead of 73 VGPRs, so nab is 0 there.  Deriving their kinds in the
 // same-level path instead took 167 instead of 78 VGPRs at 3D M = 2 fp64.
 template <int DIM, int M, int SYS, typename R, int TB = kBlock, int FLUX = -1>
 __global__ void __launch_bounds__((AmrFluxShape<DIM, M, TB>::BLOCK))
 k_amr_flux(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, double* __restrict__ fbuf,
-           WsHeader* hdr, const int32_t* __restrict__ cfl, int64_t ncf, unsigned ncb) {
+           WsHeader* hdr, const int32_t* __restrict__ cfl, int64_t ncf, unsigned ncb,
+           AmrUpdArgs ua, MeshParams ump, const double* __restrict__ ufbuf, WsHeader* uhdr,
+           unsigned nab) {
   using Sh = AmrFluxShape<DIM, M, TB>;
   constexpr int G = Sh::G;
   constexpr int NV = NVars<SYS, DIM>::v;
@@ -598,13 +641,22 @@ k_amr_flux(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, double* __res
                                             s_trc[tid / G]);
     return;
   }
+  if constexpr (DIM == 2) {
+    if (blockIdx.x < ncb + nab) {  // the finer level's deferred update (uniform in the block)
+      const int64_t ia = (int64_t)(blockIdx.x - ncb) * Sh::BLOCK + tid;
+      unsigned int uflags = 0;
+      if (ia < ua.nact) amr_apply_cell<DIM, SYS>(ua, ump, ufbuf, ia, uflags);
+      block_report(0u, uflags, uhdr);
+      return;
+    }
+  }
   const int cs = tid / Sh::LPC;
   const int k = (tid % Sh::LPC) / G;
   const int g = tid % G;
   // groups in the reverse of the predictor's order (2D: predictor forward;
   // 3D: predictor reversed): the q_h written last are read first, while
   // still cached
-  const int64_t bm = (int64_t)blockIdx.x - ncb, nbm = (int64_t)gridDim.x - ncb;
+  const int64_t bm = (int64_t)blockIdx.x - ncb - nab, nbm = (int64_t)gridDim.x - ncb - nab;
   const int64_t blk = DIM == 2 ? nbm - 1 - bm : bm;
   const int64_t i = blk * Sh::CPB + cs;
   const bool valid = i < a.nact;
@@ -657,40 +709,6 @@ k_amr_cf_faces(AmrUpdArgs a, MeshParams mp, int32_t* __restrict__ list, int* __r
   }
   fc[f * a.nact + i] = type == 0 ? pn : (type == 1 ? kFaceOut : (type >= 2 ? kFaceCoarseFine
                                                                            : kFaceBad));
-}
-
-// Conservative update of active cell i (eq. finite_vol) from the face
-// fluxes of k_amr_flux: the low face on axis k is the low neighbour's high
-// face when that neighbour is an active cell of the same level.
-template <int DIM, int SYS>
-__device__ __forceinline__ void amr_apply_cell(const AmrUpdArgs& a, const MeshParams& mp,
-                                               const double* __restrict__ fbuf, int64_t i,
-                                               unsigned int& flags) {
-  constexpr int NV = NVars<SYS, DIM>::v;
-  constexpr int FS = 2 * DIM;
-  const int64_t ld = mp.ld;
-  const int64_t cell = a.act[i];
-  const double dt = *a.dt;
-  double q[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) q[v] = a.u[v * ld + cell];
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) {
-    const int32_t code = a.fc[(2 * k) * a.nact + i];  // the low face
-    const double* fhi = fbuf + (i * FS + 2 * k + 1) * NV;
-    const double* flo = code >= 0 ? fbuf + ((int64_t)code * FS + 2 * k + 1) * NV
-                                  : fbuf + (i * FS + 2 * k) * NV;
-    if (code == kFaceBad) flags |= kFlagBadIndex;
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-      q[v] -= (dt / mp.dx[k]) * (fhi[v] - (code == kFaceBad ? 0.0 : flo[v]));
-  }
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    a.u[v * ld + cell] = q[v];
-    if (q[v] != q[v]) flags |= kFlagNan;
-  }
-  if (!state_physical<SYS, DIM>(q, mp.gamma)) flags |= kFlagNonPhysical;
 }
 
 template <int DIM, int SYS>

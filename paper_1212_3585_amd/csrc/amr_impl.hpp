@@ -254,22 +254,36 @@ class AmrImpl final : public AmrImplBase {
     return a;
   }
 
+  // pend / pend_dt: a finer level whose update (with step *pend_dt) rides in
+  // this launch, or null
   template <int TB>
   static hipError_t launch_flux(const AmrUpdArgs& a, const AmrLevel& lv, const DevConsts& c,
-                                const AmrConsts& ac, hipStream_t st) {
+                                const AmrConsts& ac, const AmrLevel* pend,
+                                const double* pend_dt, hipStream_t st) {
     using Sh = AmrFluxShape<DIM, M, TB>;
     const unsigned nb = (unsigned)((lv.nact + Sh::CPB - 1) / Sh::CPB);
+    const bool with_pend = DIM == 2 && pend && pend->nact > 0;
+    const AmrUpdArgs ua = with_pend ? upd_args(*pend, nullptr, nullptr, pend_dt, 0, ac)
+                                    : AmrUpdArgs{};
+    const unsigned nab =
+        with_pend ? (unsigned)((pend->nact + Sh::BLOCK - 1) / Sh::BLOCK) : 0u;
+    const MeshParams ump = with_pend ? pend->mp : lv.mp;
+    const double* ufbuf = with_pend ? (const double*)pend->fbuf : nullptr;
+    WsHeader* uhdr = with_pend ? pend->hdr : lv.hdr;
     // one instantiation per flux (only Euler has the Osher-type flux); the
     // listed coarse-fine faces in the first ncb blocks of the same launch
     constexpr int GPB = Sh::BLOCK / Sh::G;  // coarse-fine faces per block
     const unsigned ncb = (unsigned)((lv.ncf + GPB - 1) / GPB);
     const int32_t* cfl = (const int32_t*)lv.cf;
+    const dim3 grid(ncb + nab + nb);
     if (SYS == 1 && lv.mp.flux == 1)
-      hipLaunchKernelGGL((k_amr_flux<DIM, M, SYS, R, TB, 1>), dim3(ncb + nb), dim3(Sh::BLOCK), 0,
-                         st, a, lv.mp, c, ac, lv.fbuf, lv.hdr, cfl, (int64_t)lv.ncf, ncb);
+      hipLaunchKernelGGL((k_amr_flux<DIM, M, SYS, R, TB, 1>), grid, dim3(Sh::BLOCK), 0, st, a,
+                         lv.mp, c, ac, lv.fbuf, lv.hdr, cfl, (int64_t)lv.ncf, ncb, ua, ump, ufbuf,
+                         uhdr, nab);
     else
-      hipLaunchKernelGGL((k_amr_flux<DIM, M, SYS, R, TB, 0>), dim3(ncb + nb), dim3(Sh::BLOCK), 0,
-                         st, a, lv.mp, c, ac, lv.fbuf, lv.hdr, cfl, (int64_t)lv.ncf, ncb);
+      hipLaunchKernelGGL((k_amr_flux<DIM, M, SYS, R, TB, 0>), grid, dim3(Sh::BLOCK), 0, st, a,
+                         lv.mp, c, ac, lv.fbuf, lv.hdr, cfl, (int64_t)lv.ncf, ncb, ua, ump, ufbuf,
+                         uhdr, nab);
     return hipGetLastError();
   }
 
@@ -282,23 +296,40 @@ class AmrImpl final : public AmrImplBase {
     return hipGetLastError();
   }
 
+  hipError_t flux_pend(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
+                       const double* dt, int sub, const DevConsts& c, const AmrConsts& ac,
+                       int flux_block, const AmrLevel* pend, const double* pend_dt,
+                       hipStream_t st) const {
+    const AmrUpdArgs a = upd_args(lv, coarse, fine, dt, sub, ac);
+    switch (flux_block) {
+      case 128: return launch_flux<128>(a, lv, c, ac, pend, pend_dt, st);
+      case 512: return launch_flux<512>(a, lv, c, ac, pend, pend_dt, st);
+      default: return launch_flux<256>(a, lv, c, ac, pend, pend_dt, st);
+    }
+  }
+
   hipError_t flux_only(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
                        const double* dt, int sub, const DevConsts& c, const AmrConsts& ac,
                        int flux_block, hipStream_t st) const override {
     if (lv.nact == 0) return hipSuccess;
-    const AmrUpdArgs a = upd_args(lv, coarse, fine, dt, sub, ac);
-    switch (flux_block) {
-      case 128: return launch_flux<128>(a, lv, c, ac, st);
-      case 512: return launch_flux<512>(a, lv, c, ac, st);
-      default: return launch_flux<256>(a, lv, c, ac, st);
-    }
+    return flux_pend(lv, coarse, fine, dt, sub, c, ac, flux_block, nullptr, nullptr, st);
   }
 
   hipError_t update(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
                     const double* dt, int sub, const DevConsts& c, const AmrConsts& ac,
-                    const AmrShape& sh, bool apply, hipStream_t st) const override {
+                    const AmrShape& sh, bool apply, const AmrLevel* pend,
+                    const double* pend_dt, hipStream_t st) const override {
+    // the finer level's update in a launch of its own where the face launch
+    // does not carry it (3D, or no faces on this level)
+    if (pend && pend->nact > 0 && (DIM == 3 || lv.nact == 0)) {
+      const AmrUpdArgs ua = upd_args(*pend, nullptr, nullptr, pend_dt, 0, ac);
+      hipLaunchKernelGGL((k_amr_apply<DIM, SYS>), dim3(amr_blocks(pend->nact)), dim3(kBlock), 0,
+                         st, ua, pend->mp, (const double*)pend->fbuf, pend->hdr);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
     if (lv.nact == 0) return hipSuccess;
-    hipError_t e = flux_only(lv, coarse, fine, dt, sub, c, ac, sh.flux_block, st);
+    hipError_t e = flux_pend(lv, coarse, fine, dt, sub, c, ac, sh.flux_block, pend, pend_dt, st);
     if (e != hipSuccess || !apply) return e;
     const AmrUpdArgs a = upd_args(lv, coarse, fine, dt, sub, ac);
     hipLaunchKernelGGL((k_amr_apply<DIM, SYS>), dim3(amr_blocks(lv.nact)), dim3(kBlock), 0, st,

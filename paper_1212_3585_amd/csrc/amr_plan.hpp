@@ -109,10 +109,13 @@ class AmrImplBase {
   // finite-volume update of the active cells of 'lv' (substep 'sub' of the
   // coarser level's step); coarse / fine may be null at the ends.  With
   // apply false only the face fluxes are computed, and the update is left
-  // to the level's next prepare (its apply_dt)
+  // to the level's next prepare (its apply_dt) or to the coarser level's
+  // update (its pend).  pend (or null): a finer level whose deferred update,
+  // with step *pend_dt, rides in this update's face launch
   virtual hipError_t update(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
                             const double* dt, int sub, const DevConsts& c, const AmrConsts& ac,
-                            const AmrShape& sh, bool apply, hipStream_t st) const = 0;
+                            const AmrShape& sh, bool apply, const AmrLevel* pend,
+                            const double* pend_dt, hipStream_t st) const = 0;
   // the list of the level's coarse-fine faces into lv.cf; *count (device)
   // must be zero on entry and holds the count on exit
   virtual hipError_t cf_faces(const AmrLevel& lv, const AmrLevel* coarse, const AmrLevel* fine,
