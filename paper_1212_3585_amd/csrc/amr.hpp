@@ -354,15 +354,22 @@ constexpr int32_t kFaceOut = -1, kFaceCoarseFine = -2, kFaceBad = -3;
 // Shape of the face-flux kernel: a group of G lanes per (cell, axis k); lane
 // g < NPT of a group owns space-time point (s = g / NT, tb = g % NT) of the
 // face.  CPB cells per block.
+// PACK (2D M = 2): a face's nine points take nine lanes and a wavefront
+// holds three cells (54 lanes), where power-of-two groups of 16 hold two;
+// the lanes after the last whole cell (or group) idle.
 template <int DIM, int M, int TB = kBlock>
 struct AmrFluxShape {
   static constexpr int n = M + 1;
   static constexpr int NT = Pow<n, DIM - 1>::v;  // transverse nodes of a face
   static constexpr int NPT = n * NT;              // space-time points of a face
-  static constexpr int G = NPT <= 4 ? 4 : (NPT <= 8 ? 8 : (NPT <= 16 ? 16 : (NPT <= 32 ? 32 : 64)));
+  static constexpr int P2 = NPT <= 4 ? 4 : (NPT <= 8 ? 8 : (NPT <= 16 ? 16 : (NPT <= 32 ? 32 : 64)));
+  static constexpr bool PACK = DIM == 2 && P2 != NPT && NPT > 4;
+  static constexpr int G = PACK ? NPT : P2;       // lanes per face
   static constexpr int LPC = DIM * G;             // lanes per cell
-  static constexpr int CPB = LPC >= TB ? 1 : TB / LPC;  // about TB threads
-  static constexpr int BLOCK = CPB * LPC;
+  static constexpr int CPW = 64 / LPC;            // cells per wavefront (PACK)
+  static constexpr int CPB = PACK ? CPW * (TB / 64) : (LPC >= TB ? 1 : TB / LPC);
+  static constexpr int BLOCK = PACK ? TB : CPB * LPC;
+  static constexpr int GPB = PACK ? (64 / G) * (TB / 64) : BLOCK / G;  // listed faces per block
 };
 
 // Kind of the face of active cell cc on (axis k, side): 0 an active cell of
@@ -410,7 +417,8 @@ __device__ __forceinline__ void amr_face_flux(const AmrUpdArgs& a, const MeshPar
                                               double* __restrict__ fbuf, int64_t i,
                                               const int (&cc)[3], int k, int side, int type,
                                               int64_t nb, int32_t pn, const int (&off)[3],
-                                              int g, double* __restrict__ trc) {
+                                              int g, double* __restrict__ trc,
+                                              double* __restrict__ gsum) {
   constexpr int n = M + 1;
   constexpr int NV = NVars<SYS, DIM>::v;
   constexpr int NS = Pow<n, DIM>::v;
@@ -518,11 +526,30 @@ __device__ __forceinline__ void amr_face_flux(const AmrUpdArgs& a, const MeshPar
       for (int v = 0; v < NV; ++v) F[v] = wtp * Fpt[v];
     }
   }
-  // group sum by a fixed butterfly
+  if constexpr ((G & (G - 1)) == 0) {
+    // group sum by a fixed butterfly
 #pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1)
+    for (int o = G / 2; o > 0; o >>= 1)
 #pragma unroll
-    for (int v = 0; v < NV; ++v) F[v] += __shfl_xor(F[v], o, 64);
+      for (int v = 0; v < NV; ++v) F[v] += __shfl_xor(F[v], o, 64);
+  } else {
+    // a group of G lanes that is not a power of two: its first lane sums
+    // the lanes' values in order, through the wavefront's LDS (gsum, NV
+    // doubles per lane)
+    const int ln = threadIdx.x & 63;
+    wave_lds_order();
+#pragma unroll
+    for (int v = 0; v < NV; ++v) gsum[ln * NV + v] = F[v];
+    wave_lds_order();
+    if (g == 0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double acc = 0.0;
+        for (int j = 0; j < G; ++j) acc += gsum[(ln + j) * NV + v];
+        F[v] = acc;
+      }
+    }
+  }
   if (g == 0) {
     if (type == 3) {
       const double inv = 1.0 / (DIM == 2 ? (double)(a.r * a.r) : (double)(a.r * a.r * a.r));
@@ -547,7 +574,7 @@ __device__ __forceinline__ void amr_cf_entry(const AmrUpdArgs& a, const MeshPara
                                              const DevConsts& c, const AmrConsts& ac,
                                              const int32_t* __restrict__ list, int64_t e,
                                              double* __restrict__ fbuf, int g,
-                                             double* __restrict__ trc) {
+                                             double* __restrict__ trc, double* __restrict__ gsum) {
   const int4 rec = reinterpret_cast<const int4*>(list)[e];
   const int32_t t = rec.x;
   const int64_t i = t / (2 * DIM);
@@ -558,7 +585,7 @@ __device__ __forceinline__ void amr_cf_entry(const AmrUpdArgs& a, const MeshPara
     const int off[3] = {(rec.y >> 8) & 0xFF, (rec.y >> 16) & 0xFF, (rec.y >> 24) & 0xFF};
     if (type == 3) dense_coords<DIM>(a.act[i], mp.n, cc);  // the face's fine children
     amr_face_flux<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, fbuf, i, cc, k, side, type, rec.z,
-                                           rec.w, off, g, trc);
+                                           rec.w, off, g, trc, gsum);
   } else {
     // 3D: deriving the kind again from the lists measured faster with the
     // fp64 predictor (93.5 against 118.5 us per launch on the 3D blast;
@@ -570,7 +597,7 @@ __device__ __forceinline__ void amr_cf_entry(const AmrUpdArgs& a, const MeshPara
     const int type = amr_face_kind<DIM>(a, mp, cc, k, side, &nb, &pn, off);
     if (type < 2) return;
     amr_face_flux<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, fbuf, i, cc, k, side, type, nb, pn,
-                                           off, g, trc);
+                                           off, g, trc, gsum);
   }
 }
 
@@ -633,12 +660,18 @@ k_amr_flux(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, double* __res
   constexpr int G = Sh::G;
   constexpr int NV = NVars<SYS, DIM>::v;
   const int tid = threadIdx.x;
+  const int ln = tid & 63;
+  // PACK: the wavefront's group sums through its LDS
+  __shared__ double s_gsum[Sh::PACK ? Sh::BLOCK : 1][Sh::PACK ? NV : 1];
+  double* gsum = Sh::PACK ? &s_gsum[tid - ln][0] : nullptr;
   if (blockIdx.x < ncb) {  // coarse-fine faces (uniform in the block)
-    __shared__ double s_trc[Sh::BLOCK / G][NV * Sh::NPT];
-    const int64_t e = (int64_t)blockIdx.x * (Sh::BLOCK / G) + tid / G;
-    if (e < ncf)  // uniform in the group
-      amr_cf_entry<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, cfl, e, fbuf, tid % G,
-                                            s_trc[tid / G]);
+    __shared__ double s_trc[Sh::GPB][NV * Sh::NPT];
+    const int grp = Sh::PACK ? (tid >> 6) * (64 / G) + ln / G : tid / G;
+    const bool grp_ok = !Sh::PACK || ln / G < 64 / G;
+    const int64_t e = (int64_t)blockIdx.x * Sh::GPB + grp;
+    if (grp_ok && e < ncf)  // uniform in the group
+      amr_cf_entry<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, cfl, e, fbuf,
+                                            Sh::PACK ? ln % G : tid % G, s_trc[grp], gsum);
     return;
   }
   if constexpr (DIM == 2) {
@@ -650,16 +683,19 @@ k_amr_flux(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, double* __res
       return;
     }
   }
-  const int cs = tid / Sh::LPC;
-  const int k = (tid % Sh::LPC) / G;
-  const int g = tid % G;
+  // (cell in the block, axis, lane in the face group)
+  const int lt = Sh::PACK ? ln : tid;
+  const bool lane_ok = !Sh::PACK || lt / Sh::LPC < Sh::CPW;
+  const int cs = Sh::PACK ? (tid >> 6) * Sh::CPW + (lane_ok ? lt / Sh::LPC : 0) : tid / Sh::LPC;
+  const int k = (lt % Sh::LPC) / G;
+  const int g = lt % G;
   // groups in the reverse of the predictor's order (2D: predictor forward;
   // 3D: predictor reversed): the q_h written last are read first, while
   // still cached
   const int64_t bm = (int64_t)blockIdx.x - ncb - nab, nbm = (int64_t)gridDim.x - ncb - nab;
   const int64_t blk = DIM == 2 ? nbm - 1 - bm : bm;
   const int64_t i = blk * Sh::CPB + cs;
-  const bool valid = i < a.nact;
+  const bool valid = lane_ok && i < a.nact;
   unsigned int flags = 0;
   const int cc[3] = {0, 0, 0};  // not read for same-level and boundary faces
   const int off[3] = {0, 0, 0};
@@ -671,7 +707,7 @@ k_amr_flux(AmrUpdArgs a, MeshParams mp, DevConsts c, AmrConsts ac, double* __res
     if (code == kFaceCoarseFine || code == kFaceBad || (side == 0 && code >= 0)) continue;
     const int type = code >= 0 ? 0 : 1;
     amr_face_flux<DIM, M, SYS, R, G, FLUX>(a, mp, c, ac, fbuf, i, cc, k, side, type, 0,
-                                           code >= 0 ? code : -1, off, g, nullptr);
+                                           code >= 0 ? code : -1, off, g, nullptr, gsum);
   }
   block_report(0u, flags, hdr);
 }

@@ -272,7 +272,7 @@ class AmrImpl final : public AmrImplBase {
     WsHeader* uhdr = with_pend ? pend->hdr : lv.hdr;
     // one instantiation per flux (only Euler has the Osher-type flux); the
     // listed coarse-fine faces in the first ncb blocks of the same launch
-    constexpr int GPB = Sh::BLOCK / Sh::G;  // coarse-fine faces per block
+    constexpr int GPB = Sh::GPB;  // coarse-fine faces per block
     const unsigned ncb = (unsigned)((lv.ncf + GPB - 1) / GPB);
     const int32_t* cfl = (const int32_t*)lv.cf;
     const dim3 grid(ncb + nab + nb);
